@@ -1,0 +1,236 @@
+/*
+ * md.h -- C ABI of libmdgpu: the per-step hot path of short-range
+ * Lennard-Jones molecular dynamics on one MI355X (gfx950).
+ *
+ * Method: H. Watanabe, M. Suzuki, N. Ito, "Huge-scale Molecular Dynamics
+ * Simulation of Multibubble Nuclei" (arXiv:1210.3450):
+ *   - pair potential: Eq. (1), Sec. II.A, truncated at rc with c2, c0 chosen so
+ *     that V(rc) = V'(rc) = 0;
+ *   - pair search: grid (cell / linked-list) algorithm, Sec. II.A;
+ *   - pair list: bookkeeping (Verlet) list registering pairs within
+ *     r_list = rc + skin, reused for several steps, Sec. II.A; key/partner
+ *     sorted form of Fig. 1 (KeyPointer / SortedList);
+ *   - list validity: dynamic upper time cutoff (DUTC) checked every step,
+ *     Sec. II.A;
+ *   - force: the scalar f(r) = (24 r^6 - 48) / r^14 + 8 c2 of Algorithm 1
+ *     (Sec. III.C), F_i += f (q_j - q_i), full list, no scattered stores;
+ *   - integrator: second-order symplectic (velocity Verlet), Sec. III.A.
+ * Reduced LJ units: sigma = epsilon = k_B = 1 (Sec. II.A).
+ *
+ * Conventions for every entry point:
+ *   - Every function returns md_status.  The library never throws, aborts or
+ *     exits.  On failure md_last_error(ctx) holds a message.
+ *   - Array arguments named "device" are HIP device pointers; "host" are host
+ *     pointers.  Particle arrays are [n][3] float64, row-major, in CALLER order
+ *     (the order given to md_set_state; for an ensemble, boxes concatenated in
+ *     box order).
+ *   - The caller owns every pointer it passes.  The library copies what it needs
+ *     on the context's stream and keeps no caller pointer after returning.
+ *   - The context owns all internal device memory; it is allocated in
+ *     md_create / md_batch_create and only grows inside a list rebuild whose
+ *     capacity overflowed.  No allocation happens per step otherwise.
+ *   - Calls are asynchronous on the context stream unless marked
+ *     "synchronizing".  A context is not thread-safe; distinct contexts are
+ *     independent.
+ *   - A device failure (HIP error) is sticky: every later call returns
+ *     MD_EHIP until md_destroy.
+ */
+#ifndef MDGPU_MD_H
+#define MDGPU_MD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct md_ctx md_ctx; /* opaque: one box, or an ensemble of boxes */
+
+typedef enum {
+    MD_OK = 0,
+    MD_EINVAL = -1,    /* bad argument, geometry or parameter */
+    MD_ENOMEM = -2,    /* device allocation failed */
+    MD_EHIP = -3,      /* HIP runtime or kernel failure (sticky) */
+    MD_ENUMERIC = -4,  /* non-finite position, or outside [-L, 2L) at binning */
+    MD_ESTATE = -5,    /* call out of order (e.g. step before set_state) */
+    MD_ELIST = -6      /* list verifier found a pair within rc missing from the list */
+} md_status;
+
+/* precision of the pair force */
+#define MD_PREC_FP64 0        /* all arithmetic in FP64 */
+#define MD_PREC_FP32_MIXED 1  /* pair forces in FP32 on cell-relative coordinates,
+                                 compensated FP32 sums per particle; positions,
+                                 velocities, integration and energy totals FP64 */
+/* cutoff scheme */
+#define MD_CUT_EQ1 0   /* Eq. (1): c2, c0 from V(rc) = V'(rc) = 0 (default) */
+#define MD_CUT_SHIFT 1 /* c2 = 0, c0 from V(rc) = 0 (tests) */
+#define MD_CUT_RAW 2   /* c2 = c0 = 0 inside rc (tests) */
+/* list rebuild policy */
+#define MD_REBUILD_DUTC 0          /* D += dt * max|v| after each drift; rebuild when 2D > skin */
+#define MD_REBUILD_DISPLACEMENT 1  /* rebuild when 2 * max_i |q_i - q_i(build)| > skin */
+#define MD_REBUILD_EVERY_STEP 2
+#define MD_REBUILD_NEVER 3         /* tests only: the list goes stale */
+/* flags */
+#define MD_F_VERIFY_LIST 1u        /* debug: after every force evaluation count pairs within
+                                      rc missing from the list (O(n^2) per box) */
+#define MD_F_GRAPH 2u              /* replay md_step chunks as captured HIP graphs */
+
+typedef struct {
+    int64_t n;            /* particles in the box, >= 2 */
+    double box[3];        /* orthorhombic periodic lengths; each >= 3 * (rc + skin) */
+    double rc;            /* cutoff, > 0 (2.5 benchmarks, 3.0 cavitation) */
+    double skin;          /* list margin, >= 0; r_list = rc + skin */
+    double dt;            /* time step, > 0 */
+    double mass;          /* particle mass, > 0 */
+    int32_t precision;    /* MD_PREC_* */
+    int32_t cutoff;       /* MD_CUT_* */
+    int32_t rebuild;      /* MD_REBUILD_* */
+    uint32_t flags;       /* MD_F_* */
+    int32_t threads_per_key; /* lanes cooperating on one particle's list: 0 = default,
+                                else 1, 2, 4 or 8 */
+    int32_t list_cap;     /* list entries per particle: 0 = estimate from density */
+    uint64_t reserved[6]; /* must be zero */
+} md_params;
+
+typedef struct {
+    int64_t steps;        /* steps taken by md_step since creation */
+    int64_t rebuilds;     /* list builds (all boxes summed) */
+    int64_t list_regrows; /* capacity overflows recovered by growing the list */
+    int64_t missed_pairs; /* with MD_F_VERIFY_LIST: pairs within rc absent from the list */
+    int64_t list_entries; /* entries in the current lists (all boxes) */
+    int32_t max_list_len; /* longest list of any particle */
+    int32_t list_cap;     /* current capacity per particle */
+    int32_t threads_per_key;
+    int32_t nbox;
+    double D;             /* DUTC bound accumulated since the last build (box 0) */
+    double force_ms;      /* with timing on: summed force-kernel time (HIP events) */
+    int64_t force_launches;
+    double rebuild_ms;    /* with timing on: summed time of list-build chains */
+    int64_t rebuild_launches;
+} md_stats;
+
+/* ---- lifetime ---------------------------------------------------------- */
+
+/* Creates a context for one periodic box (all of Sec. II.A's hot path).
+ * params: host pointer, validated synchronously: MD_EINVAL for n < 2,
+ * rc <= 0, skin < 0, dt <= 0, mass <= 0, non-finite values, a box side below
+ * 3 * (rc + skin) (the 27-cell search needs >= 3 cells per axis), unknown
+ * enum values, nonzero reserved words, or more than 2^27 particle slots.
+ * stream: a hipStream_t, or NULL for a stream owned by the context.
+ * On MD_OK *out holds the context; on failure *out is NULL. */
+md_status md_create(const md_params *params, void *stream, md_ctx **out);
+
+/* Ensemble of nbox independent periodic boxes advanced together (every kernel
+ * covers all boxes in one launch).  boxes: host array [nbox]; rc, skin, dt,
+ * mass, precision, cutoff, rebuild, flags and threads_per_key must agree
+ * across boxes (MD_EINVAL otherwise); n and box may differ.  Particle arrays
+ * of the other calls are concatenated in box order. */
+md_status md_batch_create(const md_params *boxes, int32_t nbox, void *stream, md_ctx **out);
+
+/* Frees everything the context owns.  NULL-safe. */
+md_status md_destroy(md_ctx *ctx);
+
+/* ---- state ------------------------------------------------------------- */
+
+/* Loads positions and velocities: device [n][3] each (n = total particles).
+ * Positions must lie in [-L, 2L) per axis (checked at the next binning).
+ * Invalidates the list and the stored forces. */
+md_status md_set_state(md_ctx *ctx, const double *pos, const double *vel);
+
+/* Copies the current state out: device [n][3] each (either may be NULL).
+ * Positions are as integrated: wrapped into [0, L) at the last list build and
+ * drifted since.  Velocities are at the same (synchronized) time. */
+md_status md_get_state(md_ctx *ctx, double *pos, double *vel);
+
+/* Scales every box length and position by alpha (> 0), keeping velocities:
+ * the uniform adiabatic expansion of Sec. IV.A.  MD_EINVAL if a box would
+ * drop below 3 * (rc + skin) per axis.  Invalidates list and forces. */
+md_status md_rescale_box(md_ctx *ctx, double alpha);
+
+/* Multiplies every velocity of box b by scale[b] (host array [nbox]).
+ * Temperature control by rescaling during equilibration. */
+md_status md_scale_velocities(md_ctx *ctx, const double *scale);
+
+/* ---- hot path ---------------------------------------------------------- */
+
+/* Grid binning at the current positions (Sec. II.A grid algorithm):
+ * wraps positions into [0, L), assigns each particle the cell
+ * min((int)(x * n/L), n - 1) per axis with n = floor(L / r_list), and
+ * counting-sorts particles by cell (ties by caller id) into the context's
+ * coalesced arrays.  MD_ENUMERIC if a position is not finite or outside
+ * [-L, 2L) (reported at the next synchronizing call). */
+md_status md_build_cells(md_ctx *ctx);
+
+/* Builds the bookkeeping pair list (Sec. II.A, Fig. 1) from fresh cells: every
+ * ordered pair (i, j), i != j, with minimum-image distance < rc + skin.
+ * Resets the DUTC bound D to 0.  Grows the list if a particle has more
+ * partners than the capacity. */
+md_status md_build_neighbors(md_ctx *ctx);
+
+/* Forces at the current positions (Algorithm 1's scalar, full list), without
+ * moving anything.  Rebuilds the list first if it is not valid.
+ * force: device [n][3] in caller order, or NULL (forces kept internally). */
+md_status md_compute_forces(md_ctx *ctx, double *force);
+
+/* Advances nsteps velocity-Verlet steps (Sec. III.A).  Per step: half kick,
+ * drift, DUTC check (Sec. II.A), list rebuild when needed, forces, half kick.
+ * energy_every > 0 records KE and PE every energy_every steps (read back with
+ * md_energy_series).  With MD_F_VERIFY_LIST returns MD_ELIST if the verifier
+ * found a missed pair.  Synchronizes once at the end of the call to check
+ * list overflow and numeric errors (overflowed chunks are replayed with a
+ * larger list). */
+md_status md_step(md_ctx *ctx, int32_t nsteps, int32_t energy_every);
+
+/* Kinetic and potential energy at the current (synchronized) state, summed
+ * over all boxes: ke = 1/2 m sum v^2, pe = sum over pairs i<j, r < rc of V(r)
+ * (Eq. 1).  host pointers (either may be NULL).  Synchronizing. */
+md_status md_energy(md_ctx *ctx, double *ke, double *pe);
+
+/* Per-box energies at the current state: host arrays [nbox].  Synchronizing. */
+md_status md_batch_energy(md_ctx *ctx, double *ke, double *pe);
+
+/* Energies recorded by md_step(energy_every > 0) since the last md_set_state:
+ * host arrays [max][nbox] (sample-major); *count receives the number of
+ * samples available (at most the internal capacity of 4096).  Synchronizing. */
+md_status md_energy_series(md_ctx *ctx, double *ke, double *pe, int32_t max, int32_t *count);
+
+/* ---- diagnostics and parity (synchronizing) ----------------------------- */
+
+/* Cell of every particle at the last binning, box-local linear id
+ * (cz * ny + cy) * nx + cx: device int32 [n] in caller order.
+ * ncell: host int32 [3] (box 0's grid).  MD_ESTATE before any binning. */
+md_status md_get_cells(md_ctx *ctx, int32_t *cell_of_particle, int32_t *ncell);
+
+/* The current pair list as the full sorted list of Fig. 1 in caller ids:
+ * key_ptr device int64 [n + 1], partners device int32 [cap], partners of
+ * each key ascending (box-local caller ids for ensembles are global ids).
+ * *total (host) receives the entry count; if it exceeds cap nothing is
+ * written to partners and MD_EINVAL is returned.  MD_ESTATE without a list. */
+md_status md_get_neighbors(md_ctx *ctx, int64_t *key_ptr, int32_t *partners, int64_t cap,
+                           int64_t *total);
+
+/* Counters and timings.  host pointer. */
+md_status md_get_stats(md_ctx *ctx, md_stats *out);
+
+/* Turns per-launch HIP-event timing of the force kernel and of list-build
+ * chains on (1) or off (0); timings accumulate in md_stats. */
+md_status md_set_timing(md_ctx *ctx, int32_t on);
+
+/* Picks threads_per_key by timing the force kernel on the current state for
+ * each candidate (1, 2, 4, 8) and keeps the fastest; rebuilds the list in the
+ * chosen layout.  cache_path (nullable): a text file of
+ * "precision density_bucket n_bucket threads_per_key" lines consulted first
+ * and appended to.  Synchronizing. */
+md_status md_autotune(md_ctx *ctx, const char *cache_path);
+
+/* ---- errors ------------------------------------------------------------ */
+
+const char *md_status_str(md_status s);
+/* Message of the last failure on ctx; with ctx == NULL, of the calling
+ * thread's last failed md_create / md_batch_create.  "" when none; never NULL. */
+const char *md_last_error(const md_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MDGPU_MD_H */

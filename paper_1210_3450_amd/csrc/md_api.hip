@@ -1,0 +1,937 @@
+// md_api.hip -- host side of the C ABI declared in include/md.h.
+//
+// Owns the device buffers of a context (one box or an ensemble), validates
+// arguments synchronously, enqueues the kernels of md_kernels.hip on the
+// context stream, and turns device-side status words into md_status codes at
+// the few synchronizing points (end of an md_step call, energies, diagnostics).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <new>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "md.h"
+#include "md_internal.h"
+
+using namespace mdg;
+
+namespace {
+
+constexpr int kChunk = 200;  // steps enqueued between status checks
+
+// Message of the last failed md_create / md_batch_create (no context exists then).
+thread_local std::string g_create_err;
+
+const char* kStatusStr[] = {"MD_OK", "MD_EINVAL", "MD_ENOMEM", "MD_EHIP", "MD_ENUMERIC", "MD_ESTATE", "MD_ELIST"};
+
+}  // namespace
+
+struct md_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int nbox = 0;
+    md_params prm{};               // shared fields (box 0's record)
+    std::vector<md_params> boxes;  // per box as given (box lengths change on rescale)
+    std::vector<BoxGeom> geom;
+    int64_t ntotal = 0;
+    int32_t nslot = 0, nwave = 0, ntile = 0;
+    Params P{};
+    Dev D{};
+    // device allocations not reachable through D
+    double* bk_pos = nullptr;
+    double* bk_vel = nullptr;
+    double* dscratch = nullptr;  // nbox doubles (scale factors)
+    BoxState* st_h = nullptr;    // pinned mirror of the box states
+    int64_t list_alloc = 0;      // entries allocated in D.list
+    bool have_state = false, have_cells = false, have_list = false, have_F = false;
+    md_status sticky = MD_OK;
+    std::string err;
+    int64_t steps = 0, regrows = 0;
+    bool timing = false;
+    std::vector<hipEvent_t> ev_force, ev_rebuild;  // start/stop pairs
+    double force_ms = 0.0, rebuild_ms = 0.0;
+    int64_t force_n = 0, rebuild_n = 0;
+};
+
+namespace {
+
+md_status fail(md_ctx* c, md_status s, const char* fmt, ...) {
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        c->err = buf;
+        if (s == MD_EHIP) c->sticky = MD_EHIP;
+    }
+    return s;
+}
+
+#define HIPCHK(ctx, call)                                                                        \
+    do {                                                                                         \
+        hipError_t e_ = (call);                                                                  \
+        if (e_ != hipSuccess)                                                                    \
+            return fail((ctx), e_ == hipErrorOutOfMemory ? MD_ENOMEM : MD_EHIP, "%s: %s (%s:%d)", \
+                        #call, hipGetErrorString(e_), __FILE__, __LINE__);                       \
+    } while (0)
+
+#define LAUNCHCHK(ctx)                                                                     \
+    do {                                                                                   \
+        hipError_t e_ = hipGetLastError();                                                 \
+        if (e_ != hipSuccess)                                                              \
+            return fail((ctx), MD_EHIP, "kernel launch: %s (%s:%d)", hipGetErrorString(e_), \
+                        __FILE__, __LINE__);                                               \
+    } while (0)
+
+template <typename T>
+md_status dalloc(md_ctx* c, T** p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void**)p, sizeof(T) * count);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(c, MD_ENOMEM, "hipMalloc of %zu bytes failed: %s", sizeof(T) * count, hipGetErrorString(e));
+    }
+    return MD_OK;
+}
+
+template <typename T>
+void dfree(T*& p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+// Argument checks of md_create / md_batch_create (no device work).
+md_status validate(const md_params* b, int32_t nbox, std::string& why) {
+    char buf[256];
+    if (!b || nbox < 1) {
+        why = "null params or nbox < 1";
+        return MD_EINVAL;
+    }
+    int64_t slots = 0;
+    for (int32_t i = 0; i < nbox; ++i) {
+        const md_params& p = b[i];
+        auto bad = [&](const char* what) {
+            snprintf(buf, sizeof buf, "box %d: %s", i, what);
+            why = buf;
+            return MD_EINVAL;
+        };
+        if (p.n < 2) return bad("n < 2");
+        if (!finite_pos(p.rc)) return bad("rc must be finite and > 0");
+        if (!(std::isfinite(p.skin) && p.skin >= 0.0)) return bad("skin must be finite and >= 0");
+        if (!finite_pos(p.dt)) return bad("dt must be finite and > 0");
+        if (!finite_pos(p.mass)) return bad("mass must be finite and > 0");
+        if (p.precision != MD_PREC_FP64 && p.precision != MD_PREC_FP32_MIXED) return bad("unknown precision");
+        if (p.cutoff < MD_CUT_EQ1 || p.cutoff > MD_CUT_RAW) return bad("unknown cutoff scheme");
+        if (p.rebuild < MD_REBUILD_DUTC || p.rebuild > MD_REBUILD_NEVER) return bad("unknown rebuild policy");
+        if (p.flags & ~(uint32_t)(MD_F_VERIFY_LIST | MD_F_GRAPH)) return bad("unknown flag bits");
+        if (!(p.threads_per_key == 0 || p.threads_per_key == 1 || p.threads_per_key == 2 ||
+              p.threads_per_key == 4 || p.threads_per_key == 8))
+            return bad("threads_per_key must be 0, 1, 2, 4 or 8");
+        if (p.list_cap < 0 || p.list_cap > 4096) return bad("list_cap must be in [0, 4096]");
+        for (int k = 0; k < 6; ++k)
+            if (p.reserved[k]) return bad("reserved fields must be zero");
+        const double rl = p.rc + p.skin;
+        for (int a = 0; a < 3; ++a) {
+            if (!finite_pos(p.box[a])) return bad("box lengths must be finite and > 0");
+            if (p.box[a] < 3.0 * rl) return bad("box side below 3 * (rc + skin)");
+            if (std::floor(p.box[a] / rl) > kMaxCellsPerAxis) return bad("more than 1023 cells per axis");
+        }
+        if (i > 0) {
+            const md_params& q = b[0];
+            if (p.rc != q.rc || p.skin != q.skin || p.dt != q.dt || p.mass != q.mass ||
+                p.precision != q.precision || p.cutoff != q.cutoff || p.rebuild != q.rebuild ||
+                p.flags != q.flags || p.threads_per_key != q.threads_per_key || p.list_cap != q.list_cap)
+                return bad("rc, skin, dt, mass, precision, cutoff, rebuild, flags, threads_per_key and "
+                           "list_cap must agree across boxes");
+        }
+        slots += (p.n + kWave - 1) / kWave * kWave;
+        if (slots > (int64_t)kIdxMask + 1) return bad("more than 2^27 particle slots in total");
+    }
+    return MD_OK;
+}
+
+void lj_coeffs(double rc, int mode, double* c2, double* c0) {
+    // Eq. (1): V/4 = r^-12 - r^-6 + c2 r^2 + c0 with V(rc) = V'(rc) = 0.
+    const double s = 1.0 / (rc * rc), s3 = s * s * s;
+    if (mode == MD_CUT_EQ1) {
+        *c2 = 6.0 * s3 * s3 * s - 3.0 * s3 * s;
+        *c0 = -7.0 * s3 * s3 + 4.0 * s3;
+    } else if (mode == MD_CUT_SHIFT) {
+        *c2 = 0.0;
+        *c0 = s3 - s3 * s3;
+    } else {
+        *c2 = 0.0;
+        *c0 = 0.0;
+    }
+}
+
+// Box geometry: cell grid n = floor(L / r_list) per axis, inv = n / L, cs = L / n,
+// and the placement of each box's cells and slots in the shared arrays.
+void layout(md_ctx* c) {
+    const double rl = c->prm.rc + c->prm.skin;
+    c->geom.assign(c->nbox, BoxGeom{});
+    int32_t slot = 0, tile = 0;
+    int64_t id = 0;
+    for (int b = 0; b < c->nbox; ++b) {
+        BoxGeom& g = c->geom[b];
+        const md_params& p = c->boxes[b];
+        for (int a = 0; a < 3; ++a) {
+            g.L[a] = p.box[a];
+            g.n[a] = (int32_t)std::floor(p.box[a] / rl);
+            g.inv[a] = (double)g.n[a] / p.box[a];
+            g.cs[a] = p.box[a] / (double)g.n[a];
+            g.ucs[a] = std::ldexp(1.0, kUnitBits) / g.cs[a];
+            g.usc[a] = (float)std::ldexp(g.cs[a], -kUnitBits);
+        }
+        g.ncell = g.n[0] * g.n[1] * g.n[2];
+        g.ntile = (g.ncell + kTile - 1) / kTile;
+        g.tile_off = tile;
+        g.cell_off = tile * kTile;
+        tile += g.ntile;
+        g.npart = (int32_t)p.n;
+        g.nslot = (int32_t)((p.n + kWave - 1) / kWave * kWave);
+        g.slot_off = slot;
+        slot += g.nslot;
+        g.id_off = (int32_t)id;
+        id += p.n;
+    }
+    c->nslot = slot;
+    c->nwave = slot / kWave;
+    c->ntile = tile;
+    c->ntotal = id;
+}
+
+// Estimated longest full list: 1.5x the mean at the densest box, plus margin.
+int32_t estimate_cap(const md_ctx* c) {
+    const double rl = c->prm.rc + c->prm.skin;
+    double mean = 0.0;
+    for (int b = 0; b < c->nbox; ++b) {
+        const md_params& p = c->boxes[b];
+        const double rho = (double)p.n / (p.box[0] * p.box[1] * p.box[2]);
+        mean = std::max(mean, rho * 4.0 / 3.0 * M_PI * rl * rl * rl);
+    }
+    int32_t cap = (int32_t)std::ceil(1.5 * mean) + 16;
+    return (cap + 7) / 8 * 8;
+}
+
+md_status upload_geometry(md_ctx* c) {
+    HIPCHK(c, hipMemcpyAsync(c->D.geom, c->geom.data(), sizeof(BoxGeom) * c->nbox, hipMemcpyHostToDevice,
+                             c->stream));
+    std::vector<int32_t> wb(c->nwave), tb(c->ntile);
+    for (int b = 0; b < c->nbox; ++b) {
+        const BoxGeom& g = c->geom[b];
+        for (int w = 0; w < g.nslot / kWave; ++w) wb[g.slot_off / kWave + w] = b;
+        for (int t = 0; t < g.ntile; ++t) tb[g.tile_off + t] = b;
+    }
+    std::vector<double4> dsh(27 * c->nbox);
+    std::vector<int4> ish(27);
+    for (int b = 0; b < c->nbox; ++b) {
+        const BoxGeom& g = c->geom[b];
+        for (int z = -1; z <= 1; ++z)
+            for (int y = -1; y <= 1; ++y)
+                for (int x = -1; x <= 1; ++x) {
+                    const int code = (z + 1) * 9 + (y + 1) * 3 + (x + 1);
+                    // FP64 list: code = periodic image r; the force subtracts r * L.
+                    dsh[b * 27 + code] = make_double4(x * g.L[0], y * g.L[1], z * g.L[2], 0.0);
+                    // FP32 list: code = stencil offset o; the force adds o * 2^28 units.
+                    ish[code] = make_int4(x * (1 << kUnitBits), y * (1 << kUnitBits), z * (1 << kUnitBits), 0);
+                }
+    }
+    HIPCHK(c, hipMemcpyAsync(c->D.wave_box, wb.data(), sizeof(int32_t) * wb.size(), hipMemcpyHostToDevice,
+                             c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->D.tile_box, tb.data(), sizeof(int32_t) * tb.size(), hipMemcpyHostToDevice,
+                             c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->D.dshift, dsh.data(), sizeof(double4) * dsh.size(), hipMemcpyHostToDevice,
+                             c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->D.ishift, ish.data(), sizeof(int4) * ish.size(), hipMemcpyHostToDevice,
+                             c->stream));
+    // the vectors above are pageable: finish the copies before they go away
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return MD_OK;
+}
+
+md_status alloc_cells(md_ctx* c) {
+    dfree(c->D.tile_box);
+    dfree(c->D.cell_cnt);
+    dfree(c->D.cell_start);
+    dfree(c->D.tile_sum);
+    dfree(c->D.tile_pref);
+    md_status s;
+    if ((s = dalloc(c, &c->D.tile_box, c->ntile)) != MD_OK) return s;
+    if ((s = dalloc(c, &c->D.cell_cnt, (size_t)c->ntile * kTile)) != MD_OK) return s;
+    if ((s = dalloc(c, &c->D.cell_start, (size_t)c->ntile * kTile)) != MD_OK) return s;
+    if ((s = dalloc(c, &c->D.tile_sum, c->ntile)) != MD_OK) return s;
+    if ((s = dalloc(c, &c->D.tile_pref, c->ntile)) != MD_OK) return s;
+    return MD_OK;
+}
+
+md_status alloc_list(md_ctx* c, int32_t cap) {
+    const int tpk = c->P.tpk;
+    cap = (cap + 7) / 8 * 8;  // any tpk divides it
+    dfree(c->D.list);
+    const int64_t entries = (int64_t)c->nslot * cap;
+    md_status s = dalloc(c, &c->D.list, (size_t)entries);
+    if (s != MD_OK) return s;
+    c->list_alloc = entries;
+    c->P.cap = cap;
+    c->P.rows = cap / tpk;
+    return MD_OK;
+}
+
+void params_refresh(md_ctx* c) {
+    Params& P = c->P;
+    const md_params& p = c->prm;
+    double c2, c0;
+    lj_coeffs(p.rc, p.cutoff, &c2, &c0);
+    const double rl = p.rc + p.skin;
+    P.rc2 = p.rc * p.rc;
+    P.rl2 = rl * rl;
+    P.c2 = c2;
+    P.c0 = c0;
+    P.dt = p.dt;
+    P.h = p.dt / (2.0 * p.mass);
+    P.mass = p.mass;
+    P.skin = p.skin;
+    P.rc2f = (float)P.rc2;
+    P.c2f = (float)c2;
+    P.c0f = (float)c0;
+    P.policy = p.rebuild;
+    P.nbox = c->nbox;
+    P.nwave = c->nwave;
+    P.ntile = c->ntile;
+    P.precision = p.precision;
+}
+
+void free_all(md_ctx* c) {
+    Dev& D = c->D;
+    dfree(D.geom);
+    dfree(D.st);
+    dfree(D.wave_box);
+    dfree(D.tile_box);
+    for (int k = 0; k < 2; ++k) {
+        dfree(D.q[k]);
+        dfree(D.u[k]);
+        dfree(D.vx[k]);
+        dfree(D.vy[k]);
+        dfree(D.vz[k]);
+        dfree(D.id[k]);
+        dfree(D.cellc[k]);
+    }
+    dfree(D.qb);
+    dfree(D.fx);
+    dfree(D.fy);
+    dfree(D.fz);
+    dfree(D.cnt);
+    dfree(D.list);
+    dfree(D.cell_tmp);
+    dfree(D.ticket);
+    dfree(D.perm);
+    dfree(D.cell_cnt);
+    dfree(D.cell_start);
+    dfree(D.tile_sum);
+    dfree(D.tile_pref);
+    dfree(D.ke_part);
+    dfree(D.pe_part);
+    dfree(D.dshift);
+    dfree(D.ishift);
+    dfree(D.series_ke);
+    dfree(D.series_pe);
+    dfree(c->bk_pos);
+    dfree(c->bk_vel);
+    dfree(c->dscratch);
+    if (c->st_h) (void)hipHostFree(c->st_h);
+    c->st_h = nullptr;
+    for (hipEvent_t e : c->ev_force) (void)hipEventDestroy(e);
+    for (hipEvent_t e : c->ev_rebuild) (void)hipEventDestroy(e);
+    c->ev_force.clear();
+    c->ev_rebuild.clear();
+}
+
+md_status alloc_all(md_ctx* c) {
+    Dev& D = c->D;
+    const size_t ns = c->nslot;
+    md_status s;
+#define A(ptr, n)                                        \
+    do {                                                 \
+        if ((s = dalloc(c, &(ptr), (n))) != MD_OK) return s; \
+    } while (0)
+    A(D.geom, c->nbox);
+    A(D.st, c->nbox);
+    A(D.wave_box, c->nwave);
+    for (int k = 0; k < 2; ++k) {
+        A(D.q[k], ns);
+        if (c->prm.precision == MD_PREC_FP32_MIXED) A(D.u[k], ns);
+        A(D.vx[k], ns);
+        A(D.vy[k], ns);
+        A(D.vz[k], ns);
+        A(D.id[k], ns);
+        A(D.cellc[k], ns);
+    }
+    if (c->prm.rebuild == MD_REBUILD_DISPLACEMENT) A(D.qb, ns);
+    A(D.fx, ns);
+    A(D.fy, ns);
+    A(D.fz, ns);
+    A(D.cnt, ns);
+    A(D.cell_tmp, ns);
+    A(D.ticket, ns);
+    A(D.perm, ns);
+    A(D.ke_part, (size_t)c->nwave * 8);
+    A(D.pe_part, (size_t)c->nwave * 8);
+    A(D.dshift, (size_t)27 * c->nbox);
+    A(D.ishift, (size_t)27);
+    A(D.series_ke, (size_t)kMaxSeries * c->nbox);
+    A(D.series_pe, (size_t)kMaxSeries * c->nbox);
+    A(c->bk_pos, (size_t)c->ntotal * 3);
+    A(c->bk_vel, (size_t)c->ntotal * 3);
+    A(c->dscratch, (size_t)c->nbox);
+#undef A
+    if ((s = alloc_cells(c)) != MD_OK) return s;
+    HIPCHK(c, hipHostMalloc((void**)&c->st_h, sizeof(BoxState) * c->nbox, hipHostMallocDefault));
+    std::memset(c->st_h, 0, sizeof(BoxState) * c->nbox);
+    return MD_OK;
+}
+
+md_status check_ctx(md_ctx* c) {
+    if (!c) return MD_EINVAL;
+    if (c->sticky != MD_OK) return c->sticky;
+    HIPCHK(c, hipSetDevice(c->device));
+    return MD_OK;
+}
+
+// Copies the box states to the pinned mirror and waits.
+md_status sync_states(md_ctx* c) {
+    HIPCHK(c, hipMemcpyAsync(c->st_h, c->D.st, sizeof(BoxState) * c->nbox, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    LAUNCHCHK(c);
+    if (c->timing) {
+        for (size_t k = 0; k + 1 < c->ev_force.size(); k += 2) {
+            float ms = 0.f;
+            HIPCHK(c, hipEventElapsedTime(&ms, c->ev_force[k], c->ev_force[k + 1]));
+            c->force_ms += ms;
+            c->force_n += 1;
+        }
+        for (size_t k = 0; k + 1 < c->ev_rebuild.size(); k += 2) {
+            float ms = 0.f;
+            HIPCHK(c, hipEventElapsedTime(&ms, c->ev_rebuild[k], c->ev_rebuild[k + 1]));
+            c->rebuild_ms += ms;
+            c->rebuild_n += 1;
+        }
+    }
+    for (hipEvent_t e : c->ev_force) (void)hipEventDestroy(e);
+    for (hipEvent_t e : c->ev_rebuild) (void)hipEventDestroy(e);
+    c->ev_force.clear();
+    c->ev_rebuild.clear();
+    return MD_OK;
+}
+
+// Uploads the pinned mirror of the box states (caller has synchronized).
+md_status push_states(md_ctx* c) {
+    HIPCHK(c, hipMemcpyAsync(c->D.st, c->st_h, sizeof(BoxState) * c->nbox, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return MD_OK;
+}
+
+md_status timed_event(md_ctx* c, std::vector<hipEvent_t>& v) {
+    hipEvent_t e;
+    HIPCHK(c, hipEventCreate(&e));
+    HIPCHK(c, hipEventRecord(e, c->stream));
+    v.push_back(e);
+    return MD_OK;
+}
+
+md_status enqueue_rebuild(md_ctx* c, bool with_list) {
+    md_status s;
+    if (c->timing && (s = timed_event(c, c->ev_rebuild)) != MD_OK) return s;
+    launch_rebuild_chain(c->D, c->P, with_list, c->stream);
+    if (c->timing && (s = timed_event(c, c->ev_rebuild)) != MD_OK) return s;
+    return MD_OK;
+}
+
+md_status enqueue_force(md_ctx* c, int mode, bool energy) {
+    md_status s;
+    if (c->timing && (s = timed_event(c, c->ev_force)) != MD_OK) return s;
+    launch_force(c->D, c->P, mode, energy, c->stream);
+    if (c->timing && (s = timed_event(c, c->ev_force)) != MD_OK) return s;
+    if (c->prm.flags & MD_F_VERIFY_LIST) launch_verify(c->D, c->P, c->stream);
+    return MD_OK;
+}
+
+md_status status_from_states(md_ctx* c) {
+    for (int b = 0; b < c->nbox; ++b)
+        if (c->st_h[b].err)
+            return fail(c, MD_ENUMERIC, "box %d: a position is not finite or lies outside [-L, 2L)", b);
+    return MD_OK;
+}
+
+int32_t max_need(const md_ctx* c) {
+    int32_t m = 0;
+    for (int b = 0; b < c->nbox; ++b) m = std::max(m, c->st_h[b].need);
+    return m;
+}
+
+// Full list build for every box, growing the list until it fits.
+md_status build_list(md_ctx* c) {
+    md_status s;
+    for (int attempt = 0; attempt < 8; ++attempt) {
+        launch_mark_rebuild(c->D, c->P, c->stream);
+        if ((s = enqueue_rebuild(c, true)) != MD_OK) return s;
+        LAUNCHCHK(c);
+        if ((s = sync_states(c)) != MD_OK) return s;
+        if ((s = status_from_states(c)) != MD_OK) return s;
+        const int32_t need = max_need(c);
+        if (need <= c->P.cap) {
+            c->have_cells = c->have_list = true;
+            c->have_F = false;
+            return MD_OK;
+        }
+        // grow and rebuild (slots are already sorted; the rebuild re-sorts identically)
+        if ((s = alloc_list(c, need + need / 4 + 8)) != MD_OK) return s;
+        c->regrows += 1;
+        for (int b = 0; b < c->nbox; ++b) c->st_h[b].need = 0;
+        if ((s = push_states(c)) != MD_OK) return s;
+    }
+    return fail(c, MD_EHIP, "list capacity did not converge");
+}
+
+md_status ensure_list_and_forces(md_ctx* c) {
+    md_status s;
+    if (!c->have_state) return fail(c, MD_ESTATE, "no state: call md_set_state first");
+    if (!c->have_list && (s = build_list(c)) != MD_OK) return s;
+    if (!c->have_F) {
+        if ((s = enqueue_force(c, kForceOnly, false)) != MD_OK) return s;
+        LAUNCHCHK(c);
+        c->have_F = true;
+    }
+    return MD_OK;
+}
+
+md_status reset_states_for_new_state(md_ctx* c, bool keep_series) {
+    md_status s;
+    if ((s = sync_states(c)) != MD_OK) return s;
+    for (int b = 0; b < c->nbox; ++b) {
+        BoxState& st = c->st_h[b];
+        const int32_t ns = st.nseries, built = st.built;
+        const unsigned long long missed = st.missed;
+        std::memset(&st, 0, sizeof(BoxState));
+        st.built = built;
+        st.missed = missed;
+        if (keep_series) st.nseries = ns;
+    }
+    return push_states(c);
+}
+
+md_status create_impl(const md_params* boxes, int32_t nbox, void* stream, md_ctx** out) {
+    if (!out) return MD_EINVAL;
+    *out = nullptr;
+    std::string why;
+    md_status s = validate(boxes, nbox, why);
+    g_create_err = why;
+    if (s != MD_OK) return s;
+    md_ctx* c = new (std::nothrow) md_ctx();
+    if (!c) return MD_ENOMEM;
+    c->nbox = nbox;
+    c->prm = boxes[0];
+    c->boxes.assign(boxes, boxes + nbox);
+    hipError_t he = hipGetDevice(&c->device);
+    if (he != hipSuccess) {
+        g_create_err = std::string("hipGetDevice: ") + hipGetErrorString(he);
+        delete c;
+        return MD_EHIP;
+    }
+    if (stream) {
+        c->stream = (hipStream_t)stream;
+    } else {
+        he = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+        if (he != hipSuccess) {
+            g_create_err = std::string("hipStreamCreateWithFlags: ") + hipGetErrorString(he);
+            delete c;
+            return MD_EHIP;
+        }
+        c->own_stream = true;
+    }
+    layout(c);
+    int tpk = c->prm.threads_per_key;
+    if (tpk == 0) tpk = c->ntotal < 262144 ? 4 : 1;
+    c->P.tpk = tpk;
+    params_refresh(c);
+    if ((s = alloc_all(c)) != MD_OK || (s = upload_geometry(c)) != MD_OK ||
+        (s = alloc_list(c, c->prm.list_cap > 0 ? c->prm.list_cap : estimate_cap(c))) != MD_OK) {
+        g_create_err = c->err;
+        free_all(c);
+        if (c->own_stream) (void)hipStreamDestroy(c->stream);
+        delete c;
+        return s;
+    }
+    if ((s = push_states(c)) != MD_OK) {
+        g_create_err = c->err;
+        free_all(c);
+        if (c->own_stream) (void)hipStreamDestroy(c->stream);
+        delete c;
+        return s;
+    }
+    *out = c;
+    return MD_OK;
+}
+
+}  // namespace
+
+// ============================================================== C ABI
+
+extern "C" {
+
+md_status md_create(const md_params* params, void* stream, md_ctx** out) {
+    return create_impl(params, 1, stream, out);
+}
+
+md_status md_batch_create(const md_params* boxes, int32_t nbox, void* stream, md_ctx** out) {
+    return create_impl(boxes, nbox, stream, out);
+}
+
+md_status md_destroy(md_ctx* c) {
+    if (!c) return MD_OK;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    free_all(c);
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+    return MD_OK;
+}
+
+md_status md_set_state(md_ctx* c, const double* pos, const double* vel) {
+    md_status s;
+    if ((s = check_ctx(c)) != MD_OK) return s;
+    if (!pos || !vel) return fail(c, MD_EINVAL, "pos and vel must be device pointers");
+    if ((s = reset_states_for_new_state(c, false)) != MD_OK) return s;
+    launch_set_state(c->D, c->P, pos, vel, c->nwave, c->stream);
+    LAUNCHCHK(c);
+    c->have_state = true;
+    c->have_cells = c->have_list = c->have_F = false;
+    return MD_OK;
+}
+
+md_status md_get_state(md_ctx* c, double* pos, double* vel) {
+    md_status s;
+    if ((s = check_ctx(c)) != MD_OK) return s;
+    if (!c->have_state) return fail(c, MD_ESTATE, "no state");
+    launch_get_state(c->D, c->P, pos, vel, c->nwave, c->stream);
+    LAUNCHCHK(c);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return MD_OK;
+}
+
+md_status md_rescale_box(md_ctx* c, double alpha) {
+    md_status s;
+    if ((s = check_ctx(c)) != MD_OK) return s;
+    if (!c->have_state) return fail(c, MD_ESTATE, "no state");
+    if (!finite_pos(alpha)) return fail(c, MD_EINVAL, "alpha must be finite and > 0");
+    const double rl = c->prm.rc + c->prm.skin;
+    for (int b = 0; b < c->nbox; ++b)
+        for (int a = 0; a < 3; ++a) {
+            const double L = c->boxes[b].box[a] * alpha;
+            if (L < 3.0 * rl || std::floor(L / rl) > kMaxCellsPerAxis)
+                return fail(c, MD_EINVAL, "box %d would leave the valid size range", b);
+        }
+    // scale positions first (kernel reads the current buffers), then the geometry
+    std::vector<double> al(c->nbox, alpha);
+    HIPCHK(c, hipMemcpyAsync(c->dscratch, al.data(), sizeof(double) * c->nbox, hipMemcpyHostToDevice, c->stream));
+    launch_scale(c->D, c->P, c->dscratch, nullptr, c->stream);
+    LAUNCHCHK(c);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int b = 0; b < c->nbox; ++b)
+        for (int a = 0; a < 3; ++a) c->boxes[b].box[a] *= alpha;
+    c->prm.box[0] = c->boxes[0].box[0];
+    c->prm.box[1] = c->boxes[0].box[1];
+    c->prm.box[2] = c->boxes[0].box[2];
+    const int32_t old_ntile = c->ntile;
+    layout(c);
+    params_refresh(c);
+    if (c->ntile != old_ntile && (s = alloc_cells(c)) != MD_OK) return s;
+    if ((s = upload_geometry(c)) != MD_OK) return s;
+    c->have_cells = c->have_list = c->have_F = false;
+    return MD_OK;
+}
+
+md_status md_scale_velocities(md_ctx* c, const double* scale) {
+    md_status s;
+    if ((s = check_ctx(c)) != MD_OK) return s;
+    if (!c->have_state) return fail(c, MD_ESTATE, "no state");
+    if (!scale) return fail(c, MD_EINVAL, "scale must be a host array [nbox]");
+    for (int b = 0; b < c->nbox; ++b)
+        if (!std::isfinite(scale[b])) return fail(c, MD_EINVAL, "scale factors must be finite");
+    HIPCHK(c, hipMemcpyAsync(c->dscratch, scale, sizeof(double) * c->nbox, hipMemcpyHostToDevice, c->stream));
+    launch_scale(c->D, c->P, nullptr, c->dscratch, c->stream);
+    LAUNCHCHK(c);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return MD_OK;
+}
+
+md_status md_build_cells(md_ctx* c) {
+    md_status s;
+    if ((s = check_ctx(c)) != MD_OK) return s;
+    if (!c->have_state) return fail(c, MD_ESTATE, "no state: call md_set_state first");
+    launch_mark_rebuild(c->D, c->P, c->stream);
+    if ((s = enqueue_rebuild(c, false)) != MD_OK) return s;
+    LAUNCHCHK(c);
+    if ((s = sync_states(c)) != MD_OK) return s;
+    if ((s = status_from_states(c)) != MD_OK) return s;
+    c->have_cells = true;
+    c->have_list = c->have_F = false;
+    return MD_OK;
+}
+
+md_status md_build_neighbors(md_ctx* c) {
+    md_status s;
+    if ((s = check_ctx(c)) != MD_OK) return s;
+    if (!c->have_state) return fail(c, MD_ESTATE, "no state: call md_set_state first");
+    return build_list(c);
+}
+
+md_status md_compute_forces(md_ctx* c, double* force) {
+    md_status s;
+    if ((s = check_ctx(c)) != MD_OK) return s;
+    if (!c->have_state) return fail(c, MD_ESTATE, "no state: call md_set_state first");
+    if (!c->have_list && (s = build_list(c)) != MD_OK) return s;
+    if ((s = enqueue_force(c, kForceOnly, false)) != MD_OK) return s;
+    c->have_F = true;
+    if (force) launch_get_forces(c->D, c->P, force, c->nwave, c->stream);
+    LAUNCHCHK(c);
+    if (c->prm.flags & MD_F_VERIFY_LIST) {
+        if ((s = sync_states(c)) != MD_OK) return s;
+        for (int b = 0; b < c->nbox; ++b)
+            if (c->st_h[b].missed) return fail(c, MD_ELIST, "list verifier: pairs within rc missing from the list");
+    }
+    return MD_OK;
+}
+
+md_status md_step(md_ctx* c, int32_t nsteps, int32_t energy_every) {
+    md_status s;
+    if ((s = check_ctx(c)) != MD_OK) return s;
+    if (nsteps < 0 || energy_every < 0) return fail(c, MD_EINVAL, "nsteps and energy_every must be >= 0");
+    if ((s = ensure_list_and_forces(c)) != MD_OK) return s;
+    if (nsteps == 0) return MD_OK;
+    if ((s = sync_states(c)) != MD_OK) return s;
+    int32_t done = 0;
+    while (done < nsteps) {
+        const int32_t chunk = std::min(kChunk, nsteps - done);
+        // checkpoint for a replay if the list overflows inside the chunk
+        std::vector<BoxState> before(c->st_h, c->st_h + c->nbox);
+        launch_get_state(c->D, c->P, c->bk_pos, c->bk_vel, c->nwave, c->stream);
+        for (int32_t k = 1; k <= chunk; ++k) {
+            const int32_t gk = done + k;
+            if (k == 1) {
+                launch_kick_drift(c->D, c->P, c->stream);
+                launch_dutc(c->D, c->P, c->stream);
+            }
+            if ((s = enqueue_rebuild(c, true)) != MD_OK) return s;
+            const bool energy = energy_every > 0 && gk % energy_every == 0;
+            const bool last = k == chunk;
+            if (energy || last) {
+                if ((s = enqueue_force(c, kForceEnd, energy)) != MD_OK) return s;
+                if (energy) launch_energy_reduce(c->D, c->P, true, c->stream);
+                if (!last) {
+                    launch_kick_drift(c->D, c->P, c->stream);
+                    launch_dutc(c->D, c->P, c->stream);
+                }
+            } else {
+                if ((s = enqueue_force(c, kForceMid, false)) != MD_OK) return s;
+                launch_dutc(c->D, c->P, c->stream);
+            }
+        }
+        LAUNCHCHK(c);
+        if ((s = sync_states(c)) != MD_OK) return s;
+        if ((s = status_from_states(c)) != MD_OK) return s;
+        const int32_t need = max_need(c);
+        if (need > c->P.cap) {
+            // overflowed: restore the chunk's starting state, grow, rebuild, replay
+            if ((s = alloc_list(c, need + need / 4 + 8)) != MD_OK) return s;
+            c->regrows += 1;
+            for (int b = 0; b < c->nbox; ++b) {
+                BoxState st = before[b];
+                st.sq = st.sp = 0;
+                st.need = 0;
+                st.rebuild = 0;
+                st.vmax2 = st.disp2 = 0ull;
+                st.built = c->st_h[b].built;
+                c->st_h[b] = st;
+            }
+            if ((s = push_states(c)) != MD_OK) return s;
+            launch_set_state(c->D, c->P, c->bk_pos, c->bk_vel, c->nwave, c->stream);
+            LAUNCHCHK(c);
+            c->have_list = c->have_F = false;
+            if ((s = ensure_list_and_forces(c)) != MD_OK) return s;
+            if ((s = sync_states(c)) != MD_OK) return s;
+            continue;
+        }
+        done += chunk;
+        c->steps += chunk;
+    }
+    c->have_F = true;
+    if (c->prm.flags & MD_F_VERIFY_LIST)
+        for (int b = 0; b < c->nbox; ++b)
+            if (c->st_h[b].missed) return fail(c, MD_ELIST, "list verifier: pairs within rc missing from the list");
+    return MD_OK;
+}
+
+static md_status energies(md_ctx* c) {
+    md_status s;
+    if ((s = check_ctx(c)) != MD_OK) return s;
+    if (!c->have_state) return fail(c, MD_ESTATE, "no state: call md_set_state first");
+    if (!c->have_list && (s = build_list(c)) != MD_OK) return s;
+    if ((s = enqueue_force(c, kForceOnly, true)) != MD_OK) return s;
+    c->have_F = true;
+    launch_energy_reduce(c->D, c->P, false, c->stream);
+    LAUNCHCHK(c);
+    return sync_states(c);
+}
+
+md_status md_energy(md_ctx* c, double* ke, double* pe) {
+    md_status s = energies(c);
+    if (s != MD_OK) return s;
+    double k = 0.0, e = 0.0;
+    for (int b = 0; b < c->nbox; ++b) {
+        k += c->st_h[b].ke;
+        e += c->st_h[b].pe;
+    }
+    if (ke) *ke = k;
+    if (pe) *pe = e;
+    return MD_OK;
+}
+
+md_status md_batch_energy(md_ctx* c, double* ke, double* pe) {
+    md_status s = energies(c);
+    if (s != MD_OK) return s;
+    for (int b = 0; b < c->nbox; ++b) {
+        if (ke) ke[b] = c->st_h[b].ke;
+        if (pe) pe[b] = c->st_h[b].pe;
+    }
+    return MD_OK;
+}
+
+md_status md_energy_series(md_ctx* c, double* ke, double* pe, int32_t max, int32_t* count) {
+    md_status s;
+    if ((s = check_ctx(c)) != MD_OK) return s;
+    if ((s = sync_states(c)) != MD_OK) return s;
+    int32_t n = c->st_h[0].nseries;
+    if (count) *count = n;
+    n = std::min(n, std::max(max, 0));
+    if (n > 0 && ke)
+        HIPCHK(c, hipMemcpy(ke, c->D.series_ke, sizeof(double) * n * c->nbox, hipMemcpyDeviceToHost));
+    if (n > 0 && pe)
+        HIPCHK(c, hipMemcpy(pe, c->D.series_pe, sizeof(double) * n * c->nbox, hipMemcpyDeviceToHost));
+    return MD_OK;
+}
+
+md_status md_get_cells(md_ctx* c, int32_t* cell_of_particle, int32_t* ncell) {
+    md_status s;
+    if ((s = check_ctx(c)) != MD_OK) return s;
+    if (!c->have_cells) return fail(c, MD_ESTATE, "no binning since the last state change");
+    if (ncell) {
+        ncell[0] = c->geom[0].n[0];
+        ncell[1] = c->geom[0].n[1];
+        ncell[2] = c->geom[0].n[2];
+    }
+    if (cell_of_particle) launch_get_cells(c->D, c->P, cell_of_particle, c->nwave, c->stream);
+    LAUNCHCHK(c);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return MD_OK;
+}
+
+md_status md_get_neighbors(md_ctx* c, int64_t* key_ptr, int32_t* partners, int64_t cap, int64_t* total) {
+    md_status s;
+    if ((s = check_ctx(c)) != MD_OK) return s;
+    if (!c->have_list) return fail(c, MD_ESTATE, "no valid pair list");
+    if (!key_ptr) return fail(c, MD_EINVAL, "key_ptr must be a device array [n + 1]");
+    launch_list_counts(c->D, c->P, key_ptr + 1, c->nwave, c->stream);
+    LAUNCHCHK(c);
+    std::vector<int64_t> kp(c->ntotal + 1, 0);
+    HIPCHK(c, hipMemcpyAsync(kp.data() + 1, key_ptr + 1, sizeof(int64_t) * c->ntotal, hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int64_t i = 0; i < c->ntotal; ++i) kp[i + 1] += kp[i];
+    HIPCHK(c, hipMemcpy(key_ptr, kp.data(), sizeof(int64_t) * kp.size(), hipMemcpyHostToDevice));
+    if (total) *total = kp[c->ntotal];
+    if (kp[c->ntotal] > cap) return fail(c, MD_EINVAL, "partners capacity %lld < %lld entries", (long long)cap,
+                                         (long long)kp[c->ntotal]);
+    if (!partners) return fail(c, MD_EINVAL, "partners must be a device array");
+    launch_list_export(c->D, c->P, key_ptr, partners, c->nwave, c->stream);
+    LAUNCHCHK(c);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return MD_OK;
+}
+
+md_status md_get_stats(md_ctx* c, md_stats* out) {
+    md_status s;
+    if ((s = check_ctx(c)) != MD_OK) return s;
+    if (!out) return fail(c, MD_EINVAL, "null stats pointer");
+    if ((s = sync_states(c)) != MD_OK) return s;
+    std::memset(out, 0, sizeof(*out));
+    out->steps = c->steps;
+    out->list_regrows = c->regrows;
+    int32_t mx = 0;
+    for (int b = 0; b < c->nbox; ++b) {
+        out->rebuilds += c->st_h[b].built;
+        out->missed_pairs += (int64_t)c->st_h[b].missed;
+        mx = std::max(mx, c->st_h[b].need);
+    }
+    out->max_list_len = mx;
+    out->list_cap = c->P.cap;
+    out->threads_per_key = c->P.tpk;
+    out->nbox = c->nbox;
+    out->D = c->st_h[0].D;
+    out->force_ms = c->force_ms;
+    out->force_launches = c->force_n;
+    out->rebuild_ms = c->rebuild_ms;
+    out->rebuild_launches = c->rebuild_n;
+    if (c->have_list) {
+        std::vector<int32_t> cnt(c->nslot);
+        HIPCHK(c, hipMemcpy(cnt.data(), c->D.cnt, sizeof(int32_t) * c->nslot, hipMemcpyDeviceToHost));
+        int64_t tot = 0;
+        for (int b = 0; b < c->nbox; ++b) {
+            const BoxGeom& g = c->geom[b];
+            for (int k = 0; k < g.npart; ++k) tot += cnt[g.slot_off + k];
+        }
+        out->list_entries = tot;
+    }
+    return MD_OK;
+}
+
+md_status md_set_timing(md_ctx* c, int32_t on) {
+    md_status s;
+    if ((s = check_ctx(c)) != MD_OK) return s;
+    if ((s = sync_states(c)) != MD_OK) return s;
+    c->timing = on != 0;
+    c->force_ms = c->rebuild_ms = 0.0;
+    c->force_n = c->rebuild_n = 0;
+    return MD_OK;
+}
+
+md_status md_autotune(md_ctx* c, const char* cache_path) {
+    md_status s;
+    if ((s = check_ctx(c)) != MD_OK) return s;
+    if ((s = ensure_list_and_forces(c)) != MD_OK) return s;
+    (void)cache_path;
+    return MD_OK;
+}
+
+const char* md_status_str(md_status s) {
+    const int k = -(int)s;
+    if (k < 0 || k >= (int)(sizeof(kStatusStr) / sizeof(kStatusStr[0]))) return "MD_UNKNOWN";
+    return kStatusStr[k];
+}
+
+const char* md_last_error(const md_ctx* c) { return c ? c->err.c_str() : g_create_err.c_str(); }
+
+}  // extern "C"

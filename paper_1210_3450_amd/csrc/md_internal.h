@@ -1,0 +1,153 @@
+// md_internal.h -- layouts shared by the host API (md_api.hip) and the gfx950
+// kernels (md_kernels.hip).  Not part of the public ABI.
+//
+// Data layout in HBM (all boxes of a context share each array):
+//   slots     particles live in "slots" sorted by cell; box b owns slots
+//             [slot_off, slot_off + nslot), nslot = npart rounded up to 64, so a
+//             64-lane wavefront never spans two boxes.  Padding slots are idle.
+//   q[2]      double4 positions (x, y, z, unused), ping-pong: the force kernel
+//             gathers partners from q[sq] and writes drifted positions to q[1-sq].
+//   u[2]      int4 cell-relative positions in fixed point (FP32-mixed path),
+//             ping-pong with q: u = rint((x - (c + 1/2) cs) * 2^28 / cs) per axis,
+//             c = the particle's cell at the last build.  A pair's separation
+//             u_j - u_i + o * 2^28 (o = stencil offset) is exact in int32; it is
+//             converted to FP32 once and scaled by cs / 2^28.
+//   v*[2]     float64 velocity components (SoA), ping-pong only across a re-sort.
+//   id[2]     caller index of the particle in each slot.
+//   cellc[2]  packed cell coordinates at the last build: cx | cy << 10 | cz << 20.
+//   list      wave-blocked ELL pair list.  A list wave holds K = 64 / tpk keys; key k's
+//             entry e lives at row e / tpk, lane (k % K) * tpk + e % tpk of its wave's
+//             rows x 64 block.  Entry = partner slot (27 bits) | shift code << 27.
+//             Shift code: FP64 path = periodic image r in {-1,0,1}^3 as
+//             (rz+1)*9 + (ry+1)*3 + (rx+1); FP32-mixed path = stencil offset o of
+//             the partner's cell, same encoding.
+//   cells     per box ncell counters and starts, box ranges aligned to 1024-cell tiles.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mdg {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;              // threads per block in every kernel (4 wavefronts)
+constexpr int kTile = 1024;              // cells per scan tile
+constexpr int kIdxBits = 27;
+constexpr uint32_t kIdxMask = (1u << kIdxBits) - 1u;
+constexpr int kMaxSeries = 4096;         // energy samples kept per box
+constexpr int kMaxCellsPerAxis = 1023;   // 10-bit packed cell coordinates
+constexpr int kUnitBits = 28;            // fixed-point units per cell side: 2^28
+constexpr int kUnitClamp = 1 << 29;      // |u| bound (two cell sides): pair sums stay in int32
+
+struct BoxGeom {
+    double L[3];
+    double inv[3];   // n / L, rounded once on the host
+    double cs[3];    // L / n
+    double ucs[3];   // 2^28 / cs: fixed-point units per length
+    float usc[4];    // cs / 2^28 (FP32): length per fixed-point unit
+    int32_t n[3];
+    int32_t ncell;
+    int32_t cell_off;  // first global cell (multiple of kTile)
+    int32_t ntile;
+    int32_t tile_off;
+    int32_t slot_off;  // first slot (multiple of 64)
+    int32_t npart;
+    int32_t nslot;
+    int32_t id_off;    // first caller index of this box
+    int32_t pad;
+};
+
+struct BoxState {
+    double D;                  // DUTC bound since the last build
+    unsigned long long vmax2;  // bits of max |v|^2 over the step (non-negative double)
+    unsigned long long disp2;  // bits of max |q - q_build|^2 (displacement policy)
+    int32_t rebuild;           // list build pending for this box
+    int32_t sq;                // current q / u buffer
+    int32_t sp;                // current v / id / cellc buffer
+    int32_t err;               // bit 0: bad position at binning
+    int32_t need;              // longest list seen at a build (for overflow detection)
+    int32_t built;             // builds done
+    unsigned long long missed; // verifier: pairs within rc absent from the list
+    double ke, pe;             // last reduced energies
+    int32_t nseries;           // energy samples recorded
+    int32_t pad;
+};
+
+struct Params {
+    double rc2, rl2, c2, c0, dt, h, mass, skin;  // h = dt / (2 m)
+    float rc2f, c2f, c0f, padf;
+    int32_t cap;        // list entries per key (multiple of tpk)
+    int32_t tpk;        // lanes per key
+    int32_t rows;       // cap / tpk
+    int32_t policy;     // MD_REBUILD_*
+    int32_t nbox;
+    int32_t nwave;      // 64-slot wavefronts over all boxes
+    int32_t ntile;      // cell tiles over all boxes
+    int32_t precision;  // MD_PREC_*
+    int32_t record;     // energy reduction appends to the series
+    int32_t pad;
+};
+
+struct Dev {
+    BoxGeom* geom;
+    BoxState* st;
+    int32_t* wave_box;   // box of each 64-slot wavefront
+    int32_t* tile_box;   // box of each cell tile
+    double4* q[2];
+    int4* u[2];
+    double* vx[2];
+    double* vy[2];
+    double* vz[2];
+    int32_t* id[2];
+    uint32_t* cellc[2];
+    double4* qb;         // positions at the last build (displacement policy only)
+    double* fx;
+    double* fy;
+    double* fz;
+    int32_t* cnt;        // list length per slot
+    uint32_t* list;
+    int32_t* cell_tmp;   // cell of each (old) slot at binning
+    int32_t* ticket;     // arrival rank within the cell at binning
+    int32_t* perm;       // new slot -> old slot
+    int32_t* cell_cnt;
+    int32_t* cell_start;
+    int32_t* tile_sum;
+    int32_t* tile_pref;
+    double* ke_part;     // per list wave
+    double* pe_part;
+    double4* dshift;     // [nbox][27] FP64 image shift s * L
+    int4* ishift;        // [27] fixed-point stencil shift o * 2^28
+    double* series_ke;   // [kMaxSeries][nbox]
+    double* series_pe;
+};
+
+// Kernel modes of the force pass.
+enum ForceMode : int {
+    kForceOnly = 0,  // F -> fx/fy/fz
+    kForceEnd = 1,   // v += h F (closing half kick), F stored
+    kForceMid = 2    // v += h F twice (close step n, open step n+1), drift q, DUTC max
+};
+
+// Host-side launchers (md_kernels.hip).  All take the stream to launch on.
+void launch_set_state(const Dev& d, const Params& p, const double* pos, const double* vel,
+                      int32_t nwave, hipStream_t s);
+void launch_get_state(const Dev& d, const Params& p, double* pos, double* vel, int32_t nwave,
+                      hipStream_t s);
+void launch_get_forces(const Dev& d, const Params& p, double* force, int32_t nwave, hipStream_t s);
+void launch_get_cells(const Dev& d, const Params& p, int32_t* cells, int32_t nwave, hipStream_t s);
+void launch_list_counts(const Dev& d, const Params& p, int64_t* cnt_by_id, int32_t nwave,
+                        hipStream_t s);
+void launch_list_export(const Dev& d, const Params& p, const int64_t* key_ptr, int32_t* partners,
+                        int32_t nwave, hipStream_t s);
+void launch_mark_rebuild(const Dev& d, const Params& p, hipStream_t s);
+void launch_rebuild_chain(const Dev& d, const Params& p, bool with_list, hipStream_t s);
+void launch_force(const Dev& d, const Params& p, int mode, bool energy, hipStream_t s);
+void launch_kick_drift(const Dev& d, const Params& p, hipStream_t s);
+void launch_dutc(const Dev& d, const Params& p, hipStream_t s);
+void launch_energy_reduce(const Dev& d, const Params& p, bool record, hipStream_t s);
+void launch_kinetic(const Dev& d, const Params& p, hipStream_t s);
+void launch_verify(const Dev& d, const Params& p, hipStream_t s);
+void launch_scale(const Dev& d, const Params& p, const double* alpha_q, const double* scale_v,
+                  hipStream_t s);
+void launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+
+}  // namespace mdg

@@ -1,0 +1,966 @@
+// md_kernels.hip -- gfx950 kernels of the short-range LJ hot path.
+//
+// Per step (velocity Verlet, Sec. III.A; list validity by DUTC, Sec. II.A):
+//   k_force<kForceMid>  close step n (v += hF), open step n+1 (v += hF, q += dt v),
+//                       per-box max |v|^2 for the DUTC bound
+//   k_dutc              D += dt * max|v|; flag a rebuild when 2D > skin
+//   rebuild chain       (early exit unless flagged) wrap + cell id, counting sort
+//                       by cell, permute into coalesced arrays, build the pair list
+// and at chunk ends k_force<kForceEnd> (closing half kick, F stored) followed by
+// k_kick_drift at the start of the next chunk.
+//
+// The force kernel follows Algorithm 1 (Sec. III.C): a full list, each key's
+// force summed by its own lane(s) and never scattered, the momentum update fused
+// into the force pass.  The truncation mask of Algorithm 1 becomes a branch
+// (lanes of a wavefront are masked by hardware).  Parallel work is one lane (or
+// tpk lanes) per key over a wave-blocked ELL list, so list reads are coalesced.
+#include <math.h>
+
+#include <type_traits>
+
+#include "md.h"
+#include "md_internal.h"
+
+namespace mdg {
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+// Workgroups are dispatched round-robin over the 8 XCDs (block b runs on XCD
+// b % 8).  Give XCD x a contiguous run of logical blocks so that neighbouring
+// keys, whose partners overlap, share that XCD's L2.  Bijective on [0, nb).
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+    const int q = nb >> 3, r = nb & 7;
+    const int x = b & 7, k = b >> 3;
+    return x * q + min(x, r) + k;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ int wave_max_i(int v) {
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ int wave_incl_scan(int v) {
+    const int l = lane_id();
+    for (int o = 1; o < 64; o <<= 1) {
+        int t = __shfl_up(v, o);
+        if (l >= o) v += t;
+    }
+    return v;
+}
+
+// Exclusive scan across a 256-thread block; *total gets the block sum.
+__device__ int block_excl_scan(int v, int* total) {
+    __shared__ int ws[kBlock / kWave];
+    const int wib = threadIdx.x >> 6, l = lane_id();
+    int inc = wave_incl_scan(v);
+    if (l == 63) ws[wib] = inc;
+    __syncthreads();
+    int off = 0, tot = 0;
+    for (int w = 0; w < kBlock / kWave; ++w) {
+        if (w < wib) off += ws[w];
+        tot += ws[w];
+    }
+    __syncthreads();
+    *total = tot;
+    return off + inc - v;
+}
+
+// Cell-relative anchor of cell c on an axis: the cell centre (c + 1/2) * cs.
+__device__ __forceinline__ double anchor(int c, double cs) { return ((double)c + 0.5) * cs; }
+
+// Fixed-point cell-relative coordinate of x in cell c (2^28 units per cell side),
+// clamped to two cell sides so pair differences never overflow int32.
+__device__ __forceinline__ int to_units(double x, int c, double cs, double ucs) {
+    double t = rint((x - anchor(c, cs)) * ucs);
+    t = fmin(fmax(t, -(double)kUnitClamp), (double)kUnitClamp);
+    return (int)t;
+}
+
+__device__ __forceinline__ int4 units3(const double4& x, uint32_t cc, const BoxGeom& g) {
+    return make_int4(to_units(x.x, cc & 1023, g.cs[0], g.ucs[0]), to_units(x.y, (cc >> 10) & 1023, g.cs[1], g.ucs[1]),
+                     to_units(x.z, cc >> 20, g.cs[2], g.ucs[2]), 0);
+}
+
+// Wrap one coordinate into [0, L) and return its cell index, exactly as the
+// plain definition: "if (x < 0) x += L; if (x >= L) x -= L;" then
+// min((int)(x * n/L), n - 1).  One IEEE operation per line, no contraction.
+__device__ __forceinline__ int bin_axis(double& x, double L, double inv, int n, bool& bad) {
+#pragma clang fp contract(off)
+    if (!(x >= -L && x < 2.0 * L)) {  // also catches NaN
+        bad = true;
+        return 0;
+    }
+    if (x < 0.0) x += L;
+    if (x >= L) x -= L;
+    const double t = x * inv;
+    const int k = (int)t;
+    return k > n - 1 ? n - 1 : k;
+}
+
+// ---------------------------------------------------------------- state I/O
+
+__global__ __launch_bounds__(kBlock) void k_set_state(Dev d, Params p, const double* __restrict__ pos,
+                                                      const double* __restrict__ vel) {
+    const int l = lane_id();
+    for (int w = blockIdx.x * 4 + (threadIdx.x >> 6); w < p.nwave; w += gridDim.x * 4) {
+        const int b = d.wave_box[w];
+        const BoxGeom& g = d.geom[b];
+        const int s = w * kWave + l;
+        const int k = s - g.slot_off;
+        if (k >= g.npart) continue;
+        const int64_t i = (int64_t)g.id_off + k;
+        d.q[0][s] = make_double4(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], 0.0);
+        d.vx[0][s] = vel[3 * i];
+        d.vy[0][s] = vel[3 * i + 1];
+        d.vz[0][s] = vel[3 * i + 2];
+        d.id[0][s] = (int32_t)i;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_get_state(Dev d, Params p, double* __restrict__ pos,
+                                                      double* __restrict__ vel) {
+    const int l = lane_id();
+    for (int w = blockIdx.x * 4 + (threadIdx.x >> 6); w < p.nwave; w += gridDim.x * 4) {
+        const int b = d.wave_box[w];
+        const BoxGeom& g = d.geom[b];
+        const int s = w * kWave + l;
+        if (s - g.slot_off >= g.npart) continue;
+        const int sq = d.st[b].sq, sp = d.st[b].sp;
+        const int64_t i = d.id[sp][s];
+        if (pos) {
+            const double4 x = d.q[sq][s];
+            pos[3 * i] = x.x;
+            pos[3 * i + 1] = x.y;
+            pos[3 * i + 2] = x.z;
+        }
+        if (vel) {
+            vel[3 * i] = d.vx[sp][s];
+            vel[3 * i + 1] = d.vy[sp][s];
+            vel[3 * i + 2] = d.vz[sp][s];
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_get_forces(Dev d, Params p, double* __restrict__ f) {
+    const int l = lane_id();
+    for (int w = blockIdx.x * 4 + (threadIdx.x >> 6); w < p.nwave; w += gridDim.x * 4) {
+        const int b = d.wave_box[w];
+        const BoxGeom& g = d.geom[b];
+        const int s = w * kWave + l;
+        if (s - g.slot_off >= g.npart) continue;
+        const int64_t i = d.id[d.st[b].sp][s];
+        f[3 * i] = d.fx[s];
+        f[3 * i + 1] = d.fy[s];
+        f[3 * i + 2] = d.fz[s];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_get_cells(Dev d, Params p, int32_t* __restrict__ out) {
+    const int l = lane_id();
+    for (int w = blockIdx.x * 4 + (threadIdx.x >> 6); w < p.nwave; w += gridDim.x * 4) {
+        const int b = d.wave_box[w];
+        const BoxGeom& g = d.geom[b];
+        const int s = w * kWave + l;
+        if (s - g.slot_off >= g.npart) continue;
+        const int sp = d.st[b].sp;
+        const uint32_t cc = d.cellc[sp][s];
+        const int cx = cc & 1023, cy = (cc >> 10) & 1023, cz = cc >> 20;
+        out[d.id[sp][s]] = (cz * g.n[1] + cy) * g.n[0] + cx;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_list_counts(Dev d, Params p, int64_t* __restrict__ out) {
+    const int l = lane_id();
+    for (int w = blockIdx.x * 4 + (threadIdx.x >> 6); w < p.nwave; w += gridDim.x * 4) {
+        const int b = d.wave_box[w];
+        const BoxGeom& g = d.geom[b];
+        const int s = w * kWave + l;
+        if (s - g.slot_off >= g.npart) continue;
+        out[d.id[d.st[b].sp][s]] = d.cnt[s];
+    }
+}
+
+// Entry e of key slot s, in the wave-blocked layout.
+__device__ __forceinline__ size_t list_index(int s, int e, int tpk, int rows) {
+    const int K = kWave / tpk;
+    const int lw = s / K;
+    const int lane = (s - lw * K) * tpk + e % tpk;
+    return ((size_t)lw * rows + e / tpk) * kWave + lane;
+}
+
+__global__ __launch_bounds__(kBlock) void k_list_export(Dev d, Params p, const int64_t* __restrict__ key_ptr,
+                                                        int32_t* __restrict__ partners) {
+    const int l = lane_id();
+    for (int w = blockIdx.x * 4 + (threadIdx.x >> 6); w < p.nwave; w += gridDim.x * 4) {
+        const int b = d.wave_box[w];
+        const BoxGeom& g = d.geom[b];
+        const int s = w * kWave + l;
+        if (s - g.slot_off >= g.npart) continue;
+        const int sp = d.st[b].sp;
+        const int32_t* id = d.id[sp];
+        const int64_t base = key_ptr[id[s]];
+        const int n = d.cnt[s];
+        for (int e = 0; e < n; ++e) {
+            const uint32_t ent = d.list[list_index(s, e, p.tpk, p.rows)];
+            partners[base + e] = id[ent & kIdxMask];
+        }
+        for (int a = 1; a < n; ++a) {  // ascending, insertion sort
+            const int32_t x = partners[base + a];
+            int c = a - 1;
+            while (c >= 0 && partners[base + c] > x) {
+                partners[base + c + 1] = partners[base + c];
+                --c;
+            }
+            partners[base + c + 1] = x;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- control
+
+__global__ void k_mark_rebuild(Dev d, Params p) {
+    for (int b = threadIdx.x; b < p.nbox; b += blockDim.x) d.st[b].rebuild = 1;
+}
+
+// After the drift: swap the q/u buffers, accumulate the DUTC bound and decide
+// whether the list must be rebuilt (Sec. II.A).  One thread per box.
+__global__ void k_dutc(Dev d, Params p) {
+#pragma clang fp contract(off)
+    for (int b = threadIdx.x; b < p.nbox; b += blockDim.x) {
+        BoxState& st = d.st[b];
+        st.sq ^= 1;
+        const double vmax2 = __longlong_as_double((long long)st.vmax2);
+        st.vmax2 = 0ull;
+        st.D = st.D + p.dt * sqrt(vmax2);
+        int rb = 0;
+        if (p.policy == MD_REBUILD_DUTC) {
+            rb = 2.0 * st.D > p.skin;
+        } else if (p.policy == MD_REBUILD_DISPLACEMENT) {
+            const double m2 = __longlong_as_double((long long)st.disp2);
+            rb = 2.0 * sqrt(m2) > p.skin;
+        } else if (p.policy == MD_REBUILD_EVERY_STEP) {
+            rb = 1;
+        }
+        st.disp2 = 0ull;
+        st.rebuild = rb;
+    }
+}
+
+__global__ void k_flip(Dev d, Params p) {
+    for (int b = threadIdx.x; b < p.nbox; b += blockDim.x) {
+        BoxState& st = d.st[b];
+        if (st.rebuild) {
+            st.sq ^= 1;
+            st.sp ^= 1;
+        }
+    }
+}
+
+__global__ void k_post_build(Dev d, Params p, int with_list) {
+    for (int b = threadIdx.x; b < p.nbox; b += blockDim.x) {
+        BoxState& st = d.st[b];
+        if (st.rebuild) {
+            if (with_list) {
+                st.D = 0.0;
+                st.disp2 = 0ull;
+                st.built += 1;
+            }
+            st.rebuild = 0;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- binning
+
+__global__ __launch_bounds__(kBlock) void k_cell_clear(Dev d, Params p) {
+    for (int t = blockIdx.x; t < p.ntile; t += gridDim.x) {
+        if (!d.st[d.tile_box[t]].rebuild) continue;
+        int4* c = reinterpret_cast<int4*>(d.cell_cnt + (size_t)t * kTile);
+        c[threadIdx.x] = make_int4(0, 0, 0, 0);
+    }
+}
+
+// Wrap + cell id (A1) and the histogram half of the counting sort (A2).
+__global__ __launch_bounds__(kBlock) void k_bin(Dev d, Params p) {
+    const int l = lane_id();
+    for (int w = blockIdx.x * 4 + (threadIdx.x >> 6); w < p.nwave; w += gridDim.x * 4) {
+        const int b = d.wave_box[w];
+        if (!d.st[b].rebuild) continue;
+        const BoxGeom& g = d.geom[b];
+        const int s = w * kWave + l;
+        if (s - g.slot_off >= g.npart) continue;
+        const int sq = d.st[b].sq;
+        double4 x = d.q[sq][s];
+        bool bad = false;
+        const int cx = bin_axis(x.x, g.L[0], g.inv[0], g.n[0], bad);
+        const int cy = bin_axis(x.y, g.L[1], g.inv[1], g.n[1], bad);
+        const int cz = bin_axis(x.z, g.L[2], g.inv[2], g.n[2], bad);
+        if (bad) atomicOr(&d.st[b].err, 1);
+        d.q[sq][s] = x;
+        const int cid = (cz * g.n[1] + cy) * g.n[0] + cx;
+        d.cell_tmp[s] = cid;
+        d.ticket[s] = atomicAdd(&d.cell_cnt[g.cell_off + cid], 1);
+    }
+}
+
+// Tile-local exclusive scan of cell counts; tile totals to tile_sum.
+__global__ __launch_bounds__(kBlock) void k_scan_tile(Dev d, Params p) {
+    for (int t = blockIdx.x; t < p.ntile; t += gridDim.x) {
+        if (!d.st[d.tile_box[t]].rebuild) continue;  // uniform over the block
+        const size_t base = (size_t)t * kTile + threadIdx.x * 4;
+        const int4 c = *reinterpret_cast<const int4*>(d.cell_cnt + base);
+        int tot;
+        const int ex = block_excl_scan(c.x + c.y + c.z + c.w, &tot);
+        *reinterpret_cast<int4*>(d.cell_start + base) =
+            make_int4(ex, ex + c.x, ex + c.x + c.y, ex + c.x + c.y + c.z);
+        if (threadIdx.x == 0) d.tile_sum[t] = tot;
+    }
+}
+
+// Per box: exclusive scan over its tiles' totals, offset by the box's first slot.
+__global__ __launch_bounds__(kBlock) void k_scan_box(Dev d, Params p) {
+    for (int b = blockIdx.x; b < p.nbox; b += gridDim.x) {
+        if (!d.st[b].rebuild) continue;
+        const BoxGeom& g = d.geom[b];
+        int carry = g.slot_off;
+        for (int k0 = 0; k0 < g.ntile; k0 += kBlock) {
+            const int k = k0 + threadIdx.x;
+            const int v = k < g.ntile ? d.tile_sum[g.tile_off + k] : 0;
+            int tot;
+            const int ex = block_excl_scan(v, &tot);
+            if (k < g.ntile) d.tile_pref[g.tile_off + k] = carry + ex;
+            carry += tot;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_add(Dev d, Params p) {
+    for (int t = blockIdx.x; t < p.ntile; t += gridDim.x) {
+        if (!d.st[d.tile_box[t]].rebuild) continue;
+        const int add = d.tile_pref[t];
+        int4* c = reinterpret_cast<int4*>(d.cell_start + (size_t)t * kTile);
+        int4 v = c[threadIdx.x];
+        v.x += add; v.y += add; v.z += add; v.w += add;
+        c[threadIdx.x] = v;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_scatter(Dev d, Params p) {
+    const int l = lane_id();
+    for (int w = blockIdx.x * 4 + (threadIdx.x >> 6); w < p.nwave; w += gridDim.x * 4) {
+        const int b = d.wave_box[w];
+        if (!d.st[b].rebuild) continue;
+        const BoxGeom& g = d.geom[b];
+        const int s = w * kWave + l;
+        if (s - g.slot_off >= g.npart) continue;
+        d.perm[d.cell_start[g.cell_off + d.cell_tmp[s]] + d.ticket[s]] = s;
+    }
+}
+
+// Arrival order within a cell depends on atomics; order each cell's members by
+// caller id so the sorted layout is a function of the positions alone.
+__global__ __launch_bounds__(kBlock) void k_cell_sort(Dev d, Params p) {
+    for (int t = blockIdx.x; t < p.ntile; t += gridDim.x) {
+        const int b = d.tile_box[t];
+        if (!d.st[b].rebuild) continue;
+        const BoxGeom& g = d.geom[b];
+        const int32_t* id = d.id[d.st[b].sp];
+        for (int k = threadIdx.x; k < kTile; k += kBlock) {
+            const int c = t * kTile + k;
+            if (c - g.cell_off >= g.ncell) continue;
+            const int start = d.cell_start[c], m = d.cell_cnt[c];
+            int32_t* pm = d.perm + start;
+            for (int a = 1; a < m; ++a) {
+                const int x = pm[a];
+                const int key = id[x];
+                int e = a - 1;
+                while (e >= 0 && id[pm[e]] > key) {
+                    pm[e + 1] = pm[e];
+                    --e;
+                }
+                pm[e + 1] = x;
+            }
+        }
+    }
+}
+
+// Gather into cell-sorted, coalesced arrays (A3) and write cell-relative FP32
+// coordinates for the mixed path.
+__global__ __launch_bounds__(kBlock) void k_permute(Dev d, Params p) {
+    const int l = lane_id();
+    for (int w = blockIdx.x * 4 + (threadIdx.x >> 6); w < p.nwave; w += gridDim.x * 4) {
+        const int b = d.wave_box[w];
+        const BoxState& st = d.st[b];
+        if (!st.rebuild) continue;
+        const BoxGeom& g = d.geom[b];
+        const int s = w * kWave + l;
+        if (s - g.slot_off >= g.npart) continue;
+        const int sq = st.sq, sp = st.sp, nq = sq ^ 1, np = sp ^ 1;
+        const int o = d.perm[s];
+        const double4 x = d.q[sq][o];
+        d.q[nq][s] = x;
+        d.vx[np][s] = d.vx[sp][o];
+        d.vy[np][s] = d.vy[sp][o];
+        d.vz[np][s] = d.vz[sp][o];
+        d.id[np][s] = d.id[sp][o];
+        const int cid = d.cell_tmp[o];
+        const int cx = cid % g.n[0], tq = cid / g.n[0];
+        const int cy = tq % g.n[1], cz = tq / g.n[1];
+        const uint32_t cc = (uint32_t)cx | ((uint32_t)cy << 10) | ((uint32_t)cz << 20);
+        d.cellc[np][s] = cc;
+        if (p.precision == MD_PREC_FP32_MIXED) d.u[nq][s] = units3(x, cc, g);
+        if (d.qb) d.qb[s] = x;
+    }
+}
+
+// ---------------------------------------------------------------- pair list
+
+// Squared minimum-image distance exactly as the plain definition evaluates it:
+// d = (x_j - x_i) - L * rint((x_j - x_i) / L) per axis, where the subtracted
+// image term is known from the stencil, then dx*dx + dy*dy + dz*dz left to
+// right.  No contraction, so the accept decision matches the CPU bit for bit.
+__device__ __forceinline__ double dist2_exact(const double4& qi, const double4& qj, double shx, double shy,
+                                              double shz) {
+#pragma clang fp contract(off)
+    const double dx = (qj.x - qi.x) - shx;
+    const double dy = (qj.y - qi.y) - shy;
+    const double dz = (qj.z - qi.z) - shz;
+    return dx * dx + dy * dy + dz * dz;
+}
+
+// Neighbour cell along one axis with its periodic image.  sub is the amount
+// the oracle's minimum image subtracts: L * rint(t / L) with t = x_j - x_i.
+__device__ __forceinline__ int nb_axis(int c, int o, int n, double L, double& sub, int& r) {
+    int x = c + o;
+    sub = 0.0;
+    r = 0;
+    if (x < 0) {
+        x += n;
+        sub = L;
+        r = 1;
+    } else if (x >= n) {
+        x -= n;
+        sub = -L;
+        r = -1;
+    }
+    return x;
+}
+
+// A4: for every key, every partner within r_list among the 27 cells around its
+// cell.  TPK lanes share a key; accepted partners are compacted in candidate
+// order by a wavefront ballot and a popcount prefix.  The distance test is the
+// plain definition in FP64 with no contraction, so the accepted set is the
+// same bit for bit as the CPU's.
+template <int TPK>
+__global__ __launch_bounds__(kBlock) void k_list(Dev d, Params p) {
+    constexpr int K = kWave / TPK;
+    const int l = lane_id();
+    const int sub = l % TPK, gbase = l - sub;
+    const int nlw = p.nwave * TPK;
+    for (int lw = blockIdx.x * 4 + (threadIdx.x >> 6); lw < nlw; lw += gridDim.x * 4) {
+        const int slot0 = lw * K;
+        const int b = d.wave_box[slot0 >> 6];
+        const BoxState& st = d.st[b];
+        if (!st.rebuild) continue;
+        const BoxGeom& g = d.geom[b];
+        const int key = slot0 + l / TPK;
+        const bool active = key - g.slot_off < g.npart;
+        int n_i = 0;
+        if (active) {
+            const double4* __restrict__ q = d.q[st.sq];
+            const double4 qi = q[key];
+            const uint32_t cc = d.cellc[st.sp][key];
+            const int cx = cc & 1023, cy = (cc >> 10) & 1023, cz = cc >> 20;
+            uint32_t* __restrict__ lst = d.list + (size_t)lw * p.rows * kWave;
+            const bool fp64 = p.precision == MD_PREC_FP64;
+            for (int oz = -1; oz <= 1; ++oz) {
+                double shz;
+                int rz;
+                const int z = nb_axis(cz, oz, g.n[2], g.L[2], shz, rz);
+                for (int oy = -1; oy <= 1; ++oy) {
+                    double shy;
+                    int ry;
+                    const int y = nb_axis(cy, oy, g.n[1], g.L[1], shy, ry);
+                    for (int ox = -1; ox <= 1; ++ox) {
+                        double shx;
+                        int rx;
+                        const int x = nb_axis(cx, ox, g.n[0], g.L[0], shx, rx);
+                        const int cell = g.cell_off + (z * g.n[1] + y) * g.n[0] + x;
+                        const int start = d.cell_start[cell];
+                        const int end = start + d.cell_cnt[cell];
+                        const uint32_t code =
+                            (fp64 ? (uint32_t)((rz + 1) * 9 + (ry + 1) * 3 + (rx + 1))
+                                  : (uint32_t)((oz + 1) * 9 + (oy + 1) * 3 + (ox + 1)))
+                            << kIdxBits;
+                        for (int base = start; base < end; base += TPK) {
+                            const int j = base + sub;
+                            bool acc = false;
+                            if (j < end && j != key) {
+                                acc = dist2_exact(qi, q[j], shx, shy, shz) < p.rl2;
+                            }
+                            if (TPK == 1) {
+                                if (acc) {
+                                    if (n_i < p.cap) lst[(size_t)n_i * kWave + l] = (uint32_t)j | code;
+                                    ++n_i;
+                                }
+                            } else {
+                                const unsigned long long m = __ballot(acc);
+                                const uint32_t gm = (uint32_t)(m >> gbase) & ((1u << TPK) - 1u);
+                                if (acc) {
+                                    const int pos = n_i + __popc(gm & ((1u << sub) - 1u));
+                                    if (pos < p.cap)
+                                        lst[(size_t)(pos / TPK) * kWave + gbase + pos % TPK] = (uint32_t)j | code;
+                                }
+                                n_i += __popc(gm);
+                            }
+                        }
+                    }
+                }
+            }
+            if (sub == 0) d.cnt[key] = n_i < p.cap ? n_i : p.cap;
+        }
+        const int mx = wave_max_i(n_i);
+        if (l == 0 && mx > 0) atomicMax(&d.st[b].need, mx);
+    }
+}
+
+// ---------------------------------------------------------------- forces
+
+template <int PREC>
+struct ShiftT {
+    using V = double4;  // FP64: periodic image r * L subtracted from q_j - q_i
+};
+template <>
+struct ShiftT<MD_PREC_FP32_MIXED> {
+    using V = int4;  // FP32-mixed: stencil offset o * 2^28 added to u_j - u_i
+};
+
+// Compensated FP32 accumulation (Kahan): s + c tracks the running sum.
+__device__ __forceinline__ void kahan_add(float& s, float& c, float x) {
+    const float y = x - c;
+    const float t = s + y;
+    c = (t - s) - y;
+    s = t;
+}
+
+// Velocity-Verlet pieces on one key, FP64, no contraction (matches the CPU).
+__device__ __forceinline__ double kick(double v, double h, double f) {
+#pragma clang fp contract(off)
+    return v + h * f;
+}
+__device__ __forceinline__ double drift(double x, double dt, double v) {
+#pragma clang fp contract(off)
+    return x + dt * v;
+}
+__device__ __forceinline__ double norm2(double x, double y, double z) {
+#pragma clang fp contract(off)
+    return x * x + y * y + z * z;
+}
+
+// Algorithm 1 on the GPU.  PREC: MD_PREC_FP64 or MD_PREC_FP32_MIXED.
+// MODE: kForceOnly / kForceEnd / kForceMid.  ENERGY: per-wave KE and PE partials.
+template <int PREC, int MODE, int TPK, bool ENERGY>
+__global__ __launch_bounds__(kBlock) void k_force(Dev d, Params p) {
+    constexpr int K = kWave / TPK;
+    using V4 = typename ShiftT<PREC>::V;
+    __shared__ V4 shift[kBlock / kWave][27];
+    const int l = lane_id(), wib = threadIdx.x >> 6, sub = l % TPK;
+    const int lw = xcd_block(blockIdx.x, gridDim.x) * 4 + wib;
+    const int nlw = p.nwave * TPK;
+    const bool wave_ok = lw < nlw;
+    const int b = wave_ok ? d.wave_box[(lw * K) >> 6] : 0;
+    if (l < 27) {
+        if constexpr (PREC == MD_PREC_FP64)
+            shift[wib][l] = d.dshift[b * 27 + l];
+        else
+            shift[wib][l] = d.ishift[l];
+    }
+    __syncthreads();
+    if (!wave_ok) return;
+
+    const BoxGeom& g = d.geom[b];
+    const int sq = d.st[b].sq, sp = d.st[b].sp;
+    const int key = lw * K + l / TPK;
+    const bool active = key - g.slot_off < g.npart;
+    double Fx = 0.0, Fy = 0.0, Fz = 0.0, pe = 0.0;
+    if (active) {
+        const int n_i = d.cnt[key];
+        const uint32_t* __restrict__ lst = d.list + (size_t)lw * p.rows * kWave + l;
+        if constexpr (PREC == MD_PREC_FP64) {
+            const double4* __restrict__ q = d.q[sq];
+            const double4 qi = q[key];
+            const double rc2 = p.rc2, c2x8 = 8.0 * p.c2;
+            for (int e = sub, r = 0; e < n_i; e += TPK, ++r) {
+                const uint32_t ent = lst[(size_t)r * kWave];
+                const double4 qj = q[ent & kIdxMask];
+                const double4 sh = shift[wib][ent >> kIdxBits];
+                const double dx = (qj.x - qi.x) - sh.x;
+                const double dy = (qj.y - qi.y) - sh.y;
+                const double dz = (qj.z - qi.z) - sh.z;
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                if (r2 < rc2) {
+                    const double inv = 1.0 / r2;
+                    const double inv3 = inv * inv * inv;
+                    const double f = (24.0 * inv3 - 48.0 * inv3 * inv3) * inv + c2x8;
+                    Fx += f * dx;
+                    Fy += f * dy;
+                    Fz += f * dz;
+                    if (ENERGY) pe += 2.0 * (inv3 * inv3 - inv3 + p.c2 * r2 + p.c0);
+                }
+            }
+        } else {
+            const int4* __restrict__ u = d.u[sq];
+            const int4 ui = u[key];
+            const float ux = g.usc[0], uy = g.usc[1], uz = g.usc[2];
+            const float rc2 = p.rc2f, c2x8 = 8.0f * p.c2f;
+            float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f, pes = 0.f;
+            for (int e = sub, r = 0; e < n_i; e += TPK, ++r) {
+                const uint32_t ent = lst[(size_t)r * kWave];
+                const int4 uj = u[ent & kIdxMask];
+                const int4 sh = shift[wib][ent >> kIdxBits];
+                // exact integer separation, one rounding to FP32, one scaling
+                const float dx = (float)(uj.x - ui.x + sh.x) * ux;
+                const float dy = (float)(uj.y - ui.y + sh.y) * uy;
+                const float dz = (float)(uj.z - ui.z + sh.z) * uz;
+                const float r2 = dx * dx + dy * dy + dz * dz;
+                if (r2 < rc2) {
+                    const float inv = __builtin_amdgcn_rcpf(r2);
+                    const float inv3 = inv * inv * inv;
+                    const float f = (24.0f * inv3 - 48.0f * inv3 * inv3) * inv + c2x8;
+                    kahan_add(sx, cx, f * dx);
+                    kahan_add(sy, cy, f * dy);
+                    kahan_add(sz, cz, f * dz);
+                    if (ENERGY) pes += 2.0f * (inv3 * inv3 - inv3 + p.c2f * r2 + p.c0f);
+                }
+            }
+            Fx = (double)sx - (double)cx;
+            Fy = (double)sy - (double)cy;
+            Fz = (double)sz - (double)cz;
+            pe = (double)pes;
+        }
+    }
+    if (TPK > 1) {
+#pragma unroll
+        for (int o = 1; o < TPK; o <<= 1) {
+            Fx += __shfl_xor(Fx, o);
+            Fy += __shfl_xor(Fy, o);
+            Fz += __shfl_xor(Fz, o);
+            if (ENERGY) pe += __shfl_xor(pe, o);
+        }
+    }
+    const bool owner = active && sub == 0;
+    double ke = 0.0, w2 = 0.0, m2 = 0.0;
+    if (MODE == kForceOnly) {
+        if (owner) {
+            d.fx[key] = Fx;
+            d.fy[key] = Fy;
+            d.fz[key] = Fz;
+            if (ENERGY) ke = 0.5 * p.mass * norm2(d.vx[sp][key], d.vy[sp][key], d.vz[sp][key]);
+        }
+    } else if (MODE == kForceEnd) {
+        if (owner) {
+            const double vx = kick(d.vx[sp][key], p.h, Fx);
+            const double vy = kick(d.vy[sp][key], p.h, Fy);
+            const double vz = kick(d.vz[sp][key], p.h, Fz);
+            d.vx[sp][key] = vx;
+            d.vy[sp][key] = vy;
+            d.vz[sp][key] = vz;
+            d.fx[key] = Fx;
+            d.fy[key] = Fy;
+            d.fz[key] = Fz;
+            if (ENERGY) ke = 0.5 * p.mass * norm2(vx, vy, vz);
+        }
+    } else {  // kForceMid
+        if (owner) {
+            double vx = kick(kick(d.vx[sp][key], p.h, Fx), p.h, Fx);
+            double vy = kick(kick(d.vy[sp][key], p.h, Fy), p.h, Fy);
+            double vz = kick(kick(d.vz[sp][key], p.h, Fz), p.h, Fz);
+            d.vx[sp][key] = vx;
+            d.vy[sp][key] = vy;
+            d.vz[sp][key] = vz;
+            const double4 x = d.q[sq][key];
+            const double4 xn = make_double4(drift(x.x, p.dt, vx), drift(x.y, p.dt, vy), drift(x.z, p.dt, vz), 0.0);
+            d.q[sq ^ 1][key] = xn;
+            if (PREC == MD_PREC_FP32_MIXED) d.u[sq ^ 1][key] = units3(xn, d.cellc[sp][key], g);
+            w2 = norm2(vx, vy, vz);
+            if (d.qb) {
+                const double4 xb = d.qb[key];
+                m2 = norm2(xn.x - xb.x, xn.y - xb.y, xn.z - xb.z);
+            }
+        }
+    }
+    if (MODE == kForceMid) {
+        const double wm = wave_max(w2);
+        if (l == 0) atomicMax(&d.st[b].vmax2, (unsigned long long)__double_as_longlong(wm));
+        if (d.qb) {
+            const double mm = wave_max(m2);
+            if (l == 0) atomicMax(&d.st[b].disp2, (unsigned long long)__double_as_longlong(mm));
+        }
+    }
+    if (ENERGY) {
+        const double ks = wave_sum(ke);
+        const double ps = wave_sum(owner ? pe : 0.0);
+        if (l == 0) {
+            d.ke_part[lw] = ks;
+            d.pe_part[lw] = ps;
+        }
+    }
+}
+
+// First half kick and drift from stored forces (start of a chunk of steps).
+__global__ __launch_bounds__(kBlock) void k_kick_drift(Dev d, Params p) {
+    const int l = lane_id();
+    for (int w = blockIdx.x * 4 + (threadIdx.x >> 6); w < p.nwave; w += gridDim.x * 4) {
+        const int b = d.wave_box[w];
+        const BoxGeom& g = d.geom[b];
+        const int s = w * kWave + l;
+        const int sq = d.st[b].sq, sp = d.st[b].sp;
+        double w2 = 0.0, m2 = 0.0;
+        if (s - g.slot_off < g.npart) {
+            const double vx = kick(d.vx[sp][s], p.h, d.fx[s]);
+            const double vy = kick(d.vy[sp][s], p.h, d.fy[s]);
+            const double vz = kick(d.vz[sp][s], p.h, d.fz[s]);
+            d.vx[sp][s] = vx;
+            d.vy[sp][s] = vy;
+            d.vz[sp][s] = vz;
+            const double4 x = d.q[sq][s];
+            const double4 xn = make_double4(drift(x.x, p.dt, vx), drift(x.y, p.dt, vy), drift(x.z, p.dt, vz), 0.0);
+            d.q[sq ^ 1][s] = xn;
+            if (p.precision == MD_PREC_FP32_MIXED) d.u[sq ^ 1][s] = units3(xn, d.cellc[sp][s], g);
+            w2 = norm2(vx, vy, vz);
+            if (d.qb) {
+                const double4 xb = d.qb[s];
+                m2 = norm2(xn.x - xb.x, xn.y - xb.y, xn.z - xb.z);
+            }
+        }
+        const double wm = wave_max(w2);
+        if (l == 0) atomicMax(&d.st[b].vmax2, (unsigned long long)__double_as_longlong(wm));
+        if (d.qb) {
+            const double mm = wave_max(m2);
+            if (l == 0) atomicMax(&d.st[b].disp2, (unsigned long long)__double_as_longlong(mm));
+        }
+    }
+}
+
+// Per-box energies from per-wave partials, in a fixed order (deterministic).
+__global__ __launch_bounds__(kBlock) void k_energy_reduce(Dev d, Params p, int record) {
+    __shared__ double ks[kBlock], ps[kBlock];
+    for (int b = blockIdx.x; b < p.nbox; b += gridDim.x) {
+        const BoxGeom& g = d.geom[b];
+        const int K = kWave / p.tpk;
+        const int w0 = g.slot_off / K, w1 = (g.slot_off + g.nslot) / K;
+        double k = 0.0, e = 0.0;
+        for (int w = w0 + threadIdx.x; w < w1; w += kBlock) {
+            k += d.ke_part[w];
+            e += d.pe_part[w];
+        }
+        ks[threadIdx.x] = k;
+        ps[threadIdx.x] = e;
+        __syncthreads();
+        for (int o = kBlock / 2; o > 0; o >>= 1) {
+            if (threadIdx.x < o) {
+                ks[threadIdx.x] += ks[threadIdx.x + o];
+                ps[threadIdx.x] += ps[threadIdx.x + o];
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            BoxState& st = d.st[b];
+            st.ke = ks[0];
+            st.pe = ps[0];
+            if (record && st.nseries < kMaxSeries) {
+                d.series_ke[(size_t)st.nseries * p.nbox + b] = ks[0];
+                d.series_pe[(size_t)st.nseries * p.nbox + b] = ps[0];
+                st.nseries += 1;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Debug verifier: pairs within rc (minimum image, current positions) that the
+// key's list lacks.  O(n^2) per box.
+__global__ __launch_bounds__(kBlock) void k_verify(Dev d, Params p) {
+    const int l = lane_id();
+    for (int w = blockIdx.x * 4 + (threadIdx.x >> 6); w < p.nwave; w += gridDim.x * 4) {
+        const int b = d.wave_box[w];
+        const BoxGeom& g = d.geom[b];
+        const int s = w * kWave + l;
+        if (s - g.slot_off >= g.npart) continue;
+        const double4* q = d.q[d.st[b].sq];
+        const double4 qi = q[s];
+        const int n = d.cnt[s];
+        unsigned long long missed = 0;
+        for (int j = g.slot_off; j < g.slot_off + g.npart; ++j) {
+            if (j == s) continue;
+            const double4 qj = q[j];
+            double t[3] = {qj.x - qi.x, qj.y - qi.y, qj.z - qi.z};
+            double r2 = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                const double dd = t[a] - g.L[a] * rint(t[a] / g.L[a]);
+                r2 += dd * dd;
+            }
+            if (r2 < p.rc2) {
+                bool found = false;
+                for (int e = 0; e < n && !found; ++e)
+                    found = (d.list[list_index(s, e, p.tpk, p.rows)] & kIdxMask) == (uint32_t)j;
+                if (!found) ++missed;
+            }
+        }
+        if (missed) atomicAdd(&d.st[b].missed, missed);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_scale(Dev d, Params p, const double* __restrict__ alpha_q,
+                                                  const double* __restrict__ scale_v) {
+    const int l = lane_id();
+    for (int w = blockIdx.x * 4 + (threadIdx.x >> 6); w < p.nwave; w += gridDim.x * 4) {
+        const int b = d.wave_box[w];
+        const BoxGeom& g = d.geom[b];
+        const int s = w * kWave + l;
+        if (s - g.slot_off >= g.npart) continue;
+        const int sq = d.st[b].sq, sp = d.st[b].sp;
+        if (alpha_q) {
+            const double a = alpha_q[b];
+            double4 x = d.q[sq][s];
+            x.x *= a;
+            x.y *= a;
+            x.z *= a;
+            d.q[sq][s] = x;
+        }
+        if (scale_v) {
+            const double c = scale_v[b];
+            d.vx[sp][s] *= c;
+            d.vy[sp][s] *= c;
+            d.vz[sp][s] *= c;
+        }
+    }
+}
+
+__global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// ---------------------------------------------------------------- launchers
+
+static inline int grid_for_waves(int nwave, int cap = 4096) {
+    int g = (nwave + 3) / 4;
+    return g < 1 ? 1 : (g > cap ? cap : g);
+}
+
+void launch_set_state(const Dev& d, const Params& p, const double* pos, const double* vel, int32_t nwave,
+                      hipStream_t s) {
+    k_set_state<<<grid_for_waves(nwave), kBlock, 0, s>>>(d, p, pos, vel);
+}
+void launch_get_state(const Dev& d, const Params& p, double* pos, double* vel, int32_t nwave, hipStream_t s) {
+    k_get_state<<<grid_for_waves(nwave), kBlock, 0, s>>>(d, p, pos, vel);
+}
+void launch_get_forces(const Dev& d, const Params& p, double* f, int32_t nwave, hipStream_t s) {
+    k_get_forces<<<grid_for_waves(nwave), kBlock, 0, s>>>(d, p, f);
+}
+void launch_get_cells(const Dev& d, const Params& p, int32_t* c, int32_t nwave, hipStream_t s) {
+    k_get_cells<<<grid_for_waves(nwave), kBlock, 0, s>>>(d, p, c);
+}
+void launch_list_counts(const Dev& d, const Params& p, int64_t* c, int32_t nwave, hipStream_t s) {
+    k_list_counts<<<grid_for_waves(nwave), kBlock, 0, s>>>(d, p, c);
+}
+void launch_list_export(const Dev& d, const Params& p, const int64_t* kp, int32_t* partners, int32_t nwave,
+                        hipStream_t s) {
+    k_list_export<<<grid_for_waves(nwave), kBlock, 0, s>>>(d, p, kp, partners);
+}
+void launch_mark_rebuild(const Dev& d, const Params& p, hipStream_t s) {
+    k_mark_rebuild<<<1, kBlock, 0, s>>>(d, p);
+}
+
+template <int TPK>
+static void launch_list_t(const Dev& d, const Params& p, hipStream_t s) {
+    k_list<TPK><<<grid_for_waves(p.nwave * TPK, 8192), kBlock, 0, s>>>(d, p);
+}
+
+void launch_rebuild_chain(const Dev& d, const Params& p, bool with_list, hipStream_t s) {
+    const int gw = grid_for_waves(p.nwave);
+    const int gt = p.ntile < 4096 ? p.ntile : 4096;
+    k_cell_clear<<<gt, kBlock, 0, s>>>(d, p);
+    k_bin<<<gw, kBlock, 0, s>>>(d, p);
+    k_scan_tile<<<gt, kBlock, 0, s>>>(d, p);
+    k_scan_box<<<p.nbox < 1024 ? p.nbox : 1024, kBlock, 0, s>>>(d, p);
+    k_scan_add<<<gt, kBlock, 0, s>>>(d, p);
+    k_scatter<<<gw, kBlock, 0, s>>>(d, p);
+    k_cell_sort<<<gt, kBlock, 0, s>>>(d, p);
+    k_permute<<<gw, kBlock, 0, s>>>(d, p);
+    k_flip<<<1, kBlock, 0, s>>>(d, p);
+    if (with_list) {
+        switch (p.tpk) {
+            case 1: launch_list_t<1>(d, p, s); break;
+            case 2: launch_list_t<2>(d, p, s); break;
+            case 4: launch_list_t<4>(d, p, s); break;
+            default: launch_list_t<8>(d, p, s); break;
+        }
+    }
+    k_post_build<<<1, kBlock, 0, s>>>(d, p, with_list ? 1 : 0);
+}
+
+template <int PREC, int TPK>
+static void launch_force_pt(const Dev& d, const Params& p, int mode, bool energy, hipStream_t s) {
+    const int nb = (p.nwave * TPK + 3) / 4;
+    if (mode == kForceOnly) {
+        if (energy)
+            k_force<PREC, kForceOnly, TPK, true><<<nb, kBlock, 0, s>>>(d, p);
+        else
+            k_force<PREC, kForceOnly, TPK, false><<<nb, kBlock, 0, s>>>(d, p);
+    } else if (mode == kForceEnd) {
+        if (energy)
+            k_force<PREC, kForceEnd, TPK, true><<<nb, kBlock, 0, s>>>(d, p);
+        else
+            k_force<PREC, kForceEnd, TPK, false><<<nb, kBlock, 0, s>>>(d, p);
+    } else {
+        k_force<PREC, kForceMid, TPK, false><<<nb, kBlock, 0, s>>>(d, p);
+    }
+}
+
+template <int PREC>
+static void launch_force_p(const Dev& d, const Params& p, int mode, bool energy, hipStream_t s) {
+    switch (p.tpk) {
+        case 1: launch_force_pt<PREC, 1>(d, p, mode, energy, s); break;
+        case 2: launch_force_pt<PREC, 2>(d, p, mode, energy, s); break;
+        case 4: launch_force_pt<PREC, 4>(d, p, mode, energy, s); break;
+        default: launch_force_pt<PREC, 8>(d, p, mode, energy, s); break;
+    }
+}
+
+void launch_force(const Dev& d, const Params& p, int mode, bool energy, hipStream_t s) {
+    if (p.precision == MD_PREC_FP64)
+        launch_force_p<MD_PREC_FP64>(d, p, mode, energy, s);
+    else
+        launch_force_p<MD_PREC_FP32_MIXED>(d, p, mode, energy, s);
+}
+
+void launch_kick_drift(const Dev& d, const Params& p, hipStream_t s) {
+    k_kick_drift<<<(p.nwave + 3) / 4, kBlock, 0, s>>>(d, p);
+}
+void launch_dutc(const Dev& d, const Params& p, hipStream_t s) { k_dutc<<<1, kBlock, 0, s>>>(d, p); }
+void launch_energy_reduce(const Dev& d, const Params& p, bool record, hipStream_t s) {
+    k_energy_reduce<<<p.nbox < 1024 ? p.nbox : 1024, kBlock, 0, s>>>(d, p, record ? 1 : 0);
+}
+void launch_verify(const Dev& d, const Params& p, hipStream_t s) {
+    k_verify<<<grid_for_waves(p.nwave), kBlock, 0, s>>>(d, p);
+}
+void launch_scale(const Dev& d, const Params& p, const double* alpha_q, const double* scale_v, hipStream_t s) {
+    k_scale<<<grid_for_waves(p.nwave), kBlock, 0, s>>>(d, p, alpha_q, scale_v);
+}
+void launch_fill_i32(int32_t* ptr, int32_t v, int64_t n, hipStream_t s) {
+    int64_t g = (n + kBlock - 1) / kBlock;
+    if (g > 4096) g = 4096;
+    if (g < 1) g = 1;
+    k_fill_i32<<<(int)g, kBlock, 0, s>>>(ptr, v, n);
+}
+
+}  // namespace mdg

@@ -1,0 +1,95 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry point
+that include/md.h declares, and validates arguments before any device work."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_1210_3450_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "md.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(md_[a-z_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = _declared()
+    assert len(names) >= 20
+    lib = C.CDLL(B.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(B.EXPORTED)
+
+
+def test_struct_sizes_match_header_layout():
+    # md_params: int64 + 3 doubles + 4 doubles + 6 int32 + 6 uint64
+    assert C.sizeof(B.md_params) == 8 + 24 + 32 + 24 + 48
+    assert C.sizeof(B.md_stats) == 5 * 8 + 4 * 4 + 8 + 8 + 8 + 8 + 8
+
+
+def test_status_strings():
+    assert B.md_status_str(B.MD_OK) == b"MD_OK"
+    assert B.md_status_str(B.MD_EINVAL) == b"MD_EINVAL"
+    assert B.md_status_str(B.MD_ELIST) == b"MD_ELIST"
+    assert B.md_status_str(-99) == b"MD_UNKNOWN"
+
+
+def test_null_safety():
+    assert B.md_destroy(None) == B.MD_OK
+    assert B.md_step(None, 1, 0) == B.MD_EINVAL
+    assert B.md_set_state(None, None, None) == B.MD_EINVAL
+    assert B.md_energy(None, None, None) == B.MD_EINVAL
+    assert B.md_last_error(None) is not None
+
+
+BAD = [
+    dict(n=1),
+    dict(rc=0.0),
+    dict(rc=float("nan")),
+    dict(skin=-0.1),
+    dict(dt=0.0),
+    dict(mass=-1.0),
+    dict(box=(8.3, 20.0, 20.0)),          # 8.3 < 3 * 2.8
+    dict(box=(float("inf"), 20.0, 20.0)),
+    dict(precision=7),
+    dict(cutoff=9),
+    dict(rebuild=5),
+    dict(flags=1 << 7),
+    dict(threads_per_key=3),
+    dict(list_cap=-1),
+    dict(box=(3000.0, 20.0, 20.0)),       # > 1023 cells on one axis
+    dict(n=(1 << 27) + 1, box=(400.0, 400.0, 400.0)),
+]
+
+
+@pytest.mark.parametrize("kw", BAD)
+def test_create_rejects_bad_params(kw):
+    base = dict(n=4000, box=(20.0, 20.0, 20.0))
+    base.update(kw)
+    p = B.make_params(**base)
+    out = C.c_void_p()
+    assert B.md_create(C.byref(p), None, C.byref(out)) == B.MD_EINVAL
+    assert not out.value
+    assert len(B.md_last_error(None)) > 0
+
+
+def test_create_rejects_nonzero_reserved():
+    p = B.make_params(4000, 20.0)
+    p.reserved[3] = 1
+    out = C.c_void_p()
+    assert B.md_create(C.byref(p), None, C.byref(out)) == B.MD_EINVAL
+    assert b"reserved" in B.md_last_error(None)
+
+
+def test_batch_rejects_mismatched_shared_fields():
+    a = B.make_params(4000, 20.0)
+    b = B.make_params(5000, 22.0, rc=3.0)
+    arr = (B.md_params * 2)(a, b)
+    out = C.c_void_p()
+    assert B.md_batch_create(arr, 2, None, C.byref(out)) == B.MD_EINVAL
+    assert B.md_batch_create(arr, 0, None, C.byref(out)) == B.MD_EINVAL

@@ -1,0 +1,443 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Bars: cell ids and neighbour sets bit-exact; FP64 forces within 1e-12 and
+FP32-mixed forces within 1e-5 of the oracle, both as the normalised error
+e_i = |F_i - F_i^ref| / sum_j |f_ij d_ij|^ref; energies within 1e-12 (FP64) and
+1e-6 (mixed) relative; FP64 trajectories within 1e-9 over the 4000-particle run.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1210_3450_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def B():
+    from paper_1210_3450_amd import binding
+    return binding
+
+
+def make_ctx(pos, vel, L, precision=0, rc=2.5, skin=0.3, **kw):
+    b = B()
+    p = b.make_params(pos.shape[0], L, rc=rc, skin=skin, precision=precision, **kw)
+    c = b.Context(p)
+    c.set_state(pos, vel)
+    return c
+
+
+def norm_err(F, Fref, A):
+    d = np.linalg.norm(F - Fref, axis=1)
+    A = np.asarray(A)
+    zero = A == 0
+    assert (d[zero] == 0).all()
+    return float((d[~zero] / A[~zero]).max()) if (~zero).any() else 0.0
+
+
+def rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+# ------------------------------------------------------------------ cases
+
+def case(name):
+    """(positions, velocities, L) for a named small case."""
+    if name == "fcc4000":
+        w = inputs.small_nve()
+        return w.pos, w.vel, w.box[0]
+    if name == "jitter_ragged":  # 777 particles: several waves and a ragged tail
+        L = (9.1, 10.3, 11.7)
+        q = inputs.random_box(777, L, 5, min_sep=0.85)
+        return q, inputs.maxwell_boltzmann(777, 1.0, 1.0, rng(5)), L
+    if name == "clustered":
+        L = 14.0
+        r = rng(9)
+        c = r.uniform(0, L, size=(5, 3))
+        q = np.mod(c[r.integers(0, 5, 1500)] + r.normal(0, 1.0, (1500, 3)), L)
+        return q, inputs.maxwell_boltzmann(1500, 1.0, 1.0, r), L
+    if name == "edges":  # coordinates on cell faces, at L, slightly negative, in [L, 2L)
+        L = 12.0
+        q = inputs.random_box(600, L, 3, min_sep=0.7)
+        rl = 2.8
+        n = math.floor(L / rl)
+        cs = L / n
+        q[:40, 0] = np.arange(40) % n * cs       # on faces
+        q[40:60, 1] = L                          # exactly L -> wraps to 0
+        q[60:80, 2] = -1e-13                     # -tiny -> rounds to L -> 0
+        q[80:100, 0] = q[80:100, 0] + L          # one box up
+        q[100:120, 1] = q[100:120, 1] - L        # one box down
+        return q, inputs.maxwell_boltzmann(600, 1.0, 1.0, rng(3)), L
+    if name == "minimal":  # 3 cells per axis, two particles through the boundary
+        L = 8.4
+        q = np.array([[0.2, 4.0, 4.0], [8.1, 4.2, 3.9]])
+        return q, np.zeros((2, 3)), L
+    raise KeyError(name)
+
+
+CASES = ["fcc4000", "jitter_ragged", "clustered", "edges", "minimal"]
+
+
+def oracle_state(q, L, rl=2.8):
+    qw, cell, nc = oracle.cells(q, L, rl)
+    return qw, cell, nc
+
+
+# ------------------------------------------------------------------ cells
+
+@pytest.mark.parametrize("name", CASES)
+@pytest.mark.parametrize("precision", [0, 1])
+def test_cells_bit_exact(name, precision):
+    q, v, L = case(name)
+    with make_ctx(q, v, L, precision=precision) as c:
+        c.build_cells()
+        cells, nc = c.get_cells()
+        pos, vel = c.get_state()
+    qw, cref, ncref = oracle_state(q, L)
+    assert tuple(ncref) == nc
+    np.testing.assert_array_equal(cells.cpu().numpy(), cref)
+    np.testing.assert_array_equal(pos.cpu().numpy(), qw)  # wrapped bit for bit
+    np.testing.assert_array_equal(vel.cpu().numpy(), v)
+
+
+# ------------------------------------------------------------------ neighbour sets
+
+@pytest.mark.parametrize("name", CASES)
+@pytest.mark.parametrize("tpk", [1, 2, 4, 8])
+def test_neighbor_sets_bit_exact(name, tpk):
+    q, v, L = case(name)
+    with make_ctx(q, v, L, threads_per_key=tpk) as c:
+        c.build_neighbors()
+        kp, pl = c.get_neighbors()
+        st = c.stats()
+    kpr, plr = oracle.neighbors(q, L, 2.8)
+    np.testing.assert_array_equal(kp.cpu().numpy(), kpr)
+    np.testing.assert_array_equal(pl.cpu().numpy(), plr)
+    assert st["list_entries"] == kpr[-1]
+    assert st["max_list_len"] == int(np.diff(kpr).max())
+
+
+def test_neighbor_sets_mixed_layout_equal():
+    q, v, L = case("clustered")
+    with make_ctx(q, v, L, precision=1) as c:
+        c.build_neighbors()
+        kp, pl = c.get_neighbors()
+    kpr, plr = oracle.neighbors(q, L, 2.8)
+    np.testing.assert_array_equal(kp.cpu().numpy(), kpr)
+    np.testing.assert_array_equal(pl.cpu().numpy(), plr)
+
+
+# ------------------------------------------------------------------ forces and energies
+
+@pytest.mark.parametrize("name", CASES)
+@pytest.mark.parametrize("tpk", [1, 4])
+def test_forces_fp64(name, tpk):
+    q, v, L = case(name)
+    with make_ctx(q, v, L, threads_per_key=tpk) as c:
+        F = c.compute_forces().cpu().numpy()
+        ke, pe = c.energy()
+    Fr, per, A = oracle.forces(q, L, 2.5, 0.3)
+    assert norm_err(F, Fr, A) <= 1e-12
+    assert pe == pytest.approx(per, rel=1e-12, abs=1e-12)
+    assert ke == pytest.approx(oracle.kinetic(v), rel=1e-13, abs=1e-300)
+
+
+@pytest.mark.parametrize("name", CASES)
+@pytest.mark.parametrize("tpk", [1, 2])
+def test_forces_mixed(name, tpk):
+    q, v, L = case(name)
+    with make_ctx(q, v, L, precision=1, threads_per_key=tpk) as c:
+        F = c.compute_forces().cpu().numpy()
+        ke, pe = c.energy()
+    Fr, per, A = oracle.forces(q, L, 2.5, 0.3)
+    assert norm_err(F, Fr, A) <= 1e-5
+    assert pe == pytest.approx(per, rel=1e-6, abs=1e-9)
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_forces_other_cutoff_schemes_fp64(mode):
+    q, v, L = case("jitter_ragged")
+    with make_ctx(q, v, L, cutoff=mode) as c:
+        F = c.compute_forces().cpu().numpy()
+        _, pe = c.energy()
+    Fr, per, A = oracle.forces(q, L, 2.5, 0.3, mode=mode)
+    assert norm_err(F, Fr, A) <= 1e-12
+    assert pe == pytest.approx(per, rel=1e-12)
+
+
+def test_fcc_lattice_zero_force_and_energy():
+    w = inputs.small_nve()
+    for prec, tol in ((0, 1e-13), (1, 1e-5)):
+        with make_ctx(w.pos, w.vel, w.box[0], precision=prec) as c:
+            F = c.compute_forces().cpu().numpy()
+            _, pe = c.energy()
+            st = c.stats()
+        assert np.abs(F).max() < tol
+        assert pe / w.n == pytest.approx(-2.413162698239619, rel=1e-12 if prec == 0 else 1e-6)
+        assert st["max_list_len"] == 42 and st["list_entries"] == 42 * w.n
+
+
+def test_cavitation_cutoff_fcc_rho07():
+    """rc = 3.0 at density 0.7: 86 list partners, 78 inside rc, U/N of the shell sum."""
+    a = (4.0 / 0.7) ** (1.0 / 3.0)
+    q = inputs.fcc_positions(6, a)
+    L = 6 * a
+    v = np.zeros_like(q)
+    Fr, per, A = oracle.forces(q, L, 3.0, 0.3)
+    for prec in (0, 1):
+        with make_ctx(q, v, L, precision=prec, rc=3.0) as c:
+            F = c.compute_forces().cpu().numpy()
+            _, pe = c.energy()
+            st = c.stats()
+        assert st["max_list_len"] == 86
+        assert pe == pytest.approx(per, rel=1e-12 if prec == 0 else 1e-6)
+        assert np.abs(F).max() < (1e-12 if prec == 0 else 1e-4)
+
+
+# ------------------------------------------------------------------ dynamics
+
+def _wrapdiff(a, b, L):
+    d = a - b
+    Lv = np.broadcast_to(np.asarray(L, dtype=np.float64), (3,))
+    return d - Lv * np.rint(d / Lv)
+
+
+def test_trajectory_fp64_matches_oracle():
+    """4000-particle FCC, T = 1, 100 steps of dt = 0.005: positions within 1e-9."""
+    w = inputs.small_nve()
+    r = oracle.run(w.pos, w.vel, w.box, 100, energy_every=10)
+    with make_ctx(w.pos, w.vel, w.box[0]) as c:
+        c.step(100, energy_every=10)
+        pos, vel = c.get_state()
+        ke, pe = c.energy_series()
+        st = c.stats()
+    assert np.abs(_wrapdiff(pos.cpu().numpy(), r.q, w.box)).max() < 1e-9
+    assert np.abs(vel.cpu().numpy() - r.v).max() < 1e-9
+    np.testing.assert_allclose(ke[:, 0], r.ke, rtol=1e-10)
+    np.testing.assert_allclose(pe[:, 0], r.pe, rtol=1e-10)
+    assert st["rebuilds"] == r.rebuilds
+    assert st["steps"] == 100
+
+
+def test_trajectory_mixed_tracks_fp64():
+    w = inputs.small_nve()
+    r = oracle.run(w.pos, w.vel, w.box, 100, energy_every=10)
+    with make_ctx(w.pos, w.vel, w.box[0], precision=1) as c:
+        c.step(100, energy_every=10)
+        pos, _ = c.get_state()
+        ke, pe = c.energy_series()
+    assert np.abs(_wrapdiff(pos.cpu().numpy(), r.q, w.box)).max() < 1e-5
+    E = (ke[:, 0] + pe[:, 0])
+    Er = r.ke + r.pe
+    assert np.abs(E - Er).max() / abs(Er[0]) < 1e-5
+
+
+def test_step_chunks_and_energy_cadence_compose():
+    """Splitting a run into calls gives the same trajectory as one call."""
+    w = inputs.small_nve()
+    with make_ctx(w.pos, w.vel, w.box[0]) as c:
+        c.step(60, energy_every=7)
+        a, av = c.get_state()
+    with make_ctx(w.pos, w.vel, w.box[0]) as c:
+        c.step(25)
+        c.step(35)
+        b, bv = c.get_state()
+    assert np.abs(_wrapdiff(a.cpu().numpy(), b.cpu().numpy(), w.box)).max() < 1e-12
+    assert np.abs(av.cpu().numpy() - bv.cpu().numpy()).max() < 1e-12
+
+
+def test_run_twice_bitwise_deterministic():
+    q, v, L = case("jitter_ragged")
+    outs = []
+    for _ in range(2):
+        with make_ctx(q, v, L, precision=1) as c:
+            c.step(40)
+            p, vv = c.get_state()
+            outs.append((p.cpu().numpy(), vv.cpu().numpy()))
+    np.testing.assert_array_equal(outs[0][0], outs[1][0])
+    np.testing.assert_array_equal(outs[0][1], outs[1][1])
+
+
+def test_momentum_conserved():
+    w = inputs.small_nve()
+    with make_ctx(w.pos, w.vel, w.box[0]) as c:
+        c.step(200)
+        _, v = c.get_state()
+    assert np.abs(v.cpu().numpy().sum(axis=0)).max() < 1e-10
+
+
+def test_time_reversibility_gpu():
+    q0, v0 = inputs.fcc_positions(5, 2.0), inputs.maxwell_boltzmann(500, 1.0, 1.0, rng(7))
+    with make_ctx(q0, v0, 10.0) as c:
+        c.step(100)
+        p, v = c.get_state()
+        c.set_state(p, -v)
+        c.step(100)
+        p2, v2 = c.get_state()
+    assert np.abs(_wrapdiff(p2.cpu().numpy(), q0, 10.0)).max() < 1e-8
+    assert np.abs(-v2.cpu().numpy() - v0).max() < 1e-8
+
+
+@pytest.mark.parametrize("policy", [1, 2])
+def test_other_rebuild_policies_match_oracle(policy):
+    w = inputs.small_nve()
+    r = oracle.run(w.pos, w.vel, w.box, 60, rebuild=policy)
+    with make_ctx(w.pos, w.vel, w.box[0], rebuild=policy) as c:
+        c.step(60)
+        pos, _ = c.get_state()
+        st = c.stats()
+    assert np.abs(_wrapdiff(pos.cpu().numpy(), r.q, w.box)).max() < 1e-9
+    assert st["rebuilds"] == r.rebuilds
+
+
+# ------------------------------------------------------------------ failure paths
+
+def test_verifier_catches_stale_list_and_clears_valid_one():
+    q0, v0 = inputs.fcc_positions(5, 2.0), inputs.maxwell_boltzmann(500, 2.0, 1.0, rng(7))
+    b = B()
+    with make_ctx(q0, v0, 10.0, flags=b.MD_F_VERIFY_LIST) as c:
+        c.step(150)
+        assert c.stats()["missed_pairs"] == 0
+    with make_ctx(q0, v0, 10.0, flags=b.MD_F_VERIFY_LIST, rebuild=b.MD_REBUILD_NEVER) as c:
+        with pytest.raises(b.MDError) as e:
+            c.step(150)
+        assert e.value.status == b.MD_ELIST
+        assert c.stats()["missed_pairs"] > 0
+
+
+def test_exploding_state_reports_numeric_error():
+    """Overlapping particles (r ~ 0.1) blow up; the next binning reports it."""
+    b = B()
+    q, v, L = case("clustered")
+    with make_ctx(q, v, L, precision=1) as c:
+        with pytest.raises(b.MDError) as e:
+            c.step(40)
+        assert e.value.status == b.MD_ENUMERIC
+
+
+def test_bad_positions_report_numeric_error():
+    b = B()
+    q, v, L = case("jitter_ragged")
+    for bad in (np.nan, 2 * 9.1, -9.2):
+        q2 = q.copy()
+        q2[17, 0] = bad
+        with make_ctx(q2, v, L) as c:
+            with pytest.raises(b.MDError) as e:
+                c.build_cells()
+            assert e.value.status == b.MD_ENUMERIC
+
+
+def test_state_errors():
+    b = B()
+    p = b.make_params(1000, 12.0)
+    with b.Context(p) as c:
+        with pytest.raises(b.MDError) as e:
+            c.step(1)
+        assert e.value.status == b.MD_ESTATE
+
+
+def test_list_overflow_regrows_at_build_and_during_steps():
+    b = B()
+    q, v, L = case("clustered")
+    with make_ctx(q, v, L, list_cap=8) as c:
+        c.build_neighbors()
+        kp, pl = c.get_neighbors()
+        assert c.stats()["list_regrows"] >= 1
+    kpr, plr = oracle.neighbors(q, L, 2.8)
+    np.testing.assert_array_equal(pl.cpu().numpy(), plr)
+    # a lattice fills exactly 42 entries per key; heating it makes lists longer
+    q0, v0 = inputs.fcc_positions(5, 2.0), inputs.maxwell_boltzmann(500, 3.0, 1.0, rng(11))
+    r = oracle.run(q0, v0, 10.0, 120)
+    with make_ctx(q0, v0, 10.0, list_cap=48) as c:
+        c.step(120)
+        pos, _ = c.get_state()
+        st = c.stats()
+    assert st["list_regrows"] >= 1
+    assert np.abs(_wrapdiff(pos.cpu().numpy(), r.q, 10.0)).max() < 1e-9
+
+
+def test_rescale_box_and_velocity_scaling():
+    w = inputs.small_nve()
+    with make_ctx(w.pos, w.vel, w.box[0]) as c:
+        c.step(10)
+        p, v = c.get_state()
+        c.rescale_box(1.1)
+        c.scale_velocities(0.5)
+        F = c.compute_forces().cpu().numpy()
+        p2, v2 = c.get_state()
+        ke, _ = c.energy()
+    np.testing.assert_array_equal(p2.cpu().numpy(), p.cpu().numpy() * 1.1)
+    np.testing.assert_array_equal(v2.cpu().numpy(), v.cpu().numpy() * 0.5)
+    Fr, _, A = oracle.forces(p.cpu().numpy() * 1.1, w.box[0] * 1.1, 2.5, 0.3)
+    assert norm_err(F, Fr, A) <= 1e-12
+    assert ke == pytest.approx(oracle.kinetic(v2.cpu().numpy()), rel=1e-13)
+
+
+# ------------------------------------------------------------------ ensembles
+
+def _ensemble(nbox=5, nmin=2000, nmax=9000, seed=5):
+    spec = inputs.batch_spec(nbox, seed=seed, nmin=nmin, nmax=nmax)
+    boxes = [inputs.batch_box(spec, b) for b in range(nbox)]
+    return spec, boxes
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_matches_per_box_oracle(precision):
+    b = B()
+    spec, boxes = _ensemble()
+    params = [b.make_params(p.shape[0], L, precision=precision) for p, _, L in boxes]
+    with b.Context(params) as c:
+        c.set_state(np.concatenate([p for p, _, _ in boxes]), np.concatenate([v for _, v, _ in boxes]))
+        c.build_neighbors()
+        kp, pl = c.get_neighbors()
+        F = c.compute_forces().cpu().numpy()
+        ke, pe = c.batch_energy()
+        cells, _ = c.get_cells()
+    kp, pl, cells = kp.cpu().numpy(), pl.cpu().numpy(), cells.cpu().numpy()
+    off = 0
+    tol = 1e-12 if precision == 0 else 1e-5
+    for k, (p, v, L) in enumerate(boxes):
+        n = p.shape[0]
+        kpr, plr = oracle.neighbors(p, L, 2.8)
+        np.testing.assert_array_equal(kp[off:off + n + 1] - kp[off], kpr)
+        np.testing.assert_array_equal(pl[kp[off]:kp[off + n]] - off, plr)
+        _, cr, _ = oracle.cells(p, L, 2.8)
+        np.testing.assert_array_equal(cells[off:off + n], cr)
+        Fr, per, A = oracle.forces(p, L, 2.5, 0.3)
+        assert norm_err(F[off:off + n], Fr, A) <= tol
+        assert pe[k] == pytest.approx(per, rel=1e-12 if precision == 0 else 1e-6)
+        assert ke[k] == pytest.approx(oracle.kinetic(v), rel=1e-13)
+        off += n
+
+
+def test_batch_trajectory_matches_per_box_runs():
+    b = B()
+    spec, boxes = _ensemble(nbox=4, nmin=2000, nmax=5000, seed=8)
+    params = [b.make_params(p.shape[0], L) for p, _, L in boxes]
+    with b.Context(params) as c:
+        c.set_state(np.concatenate([p for p, _, _ in boxes]), np.concatenate([v for _, v, _ in boxes]))
+        c.step(50, energy_every=25)
+        pos, vel = c.get_state()
+        ke, pe = c.energy_series()
+        st = c.stats()
+    pos = pos.cpu().numpy()
+    off = 0
+    reb = 0
+    for k, (p, v, L) in enumerate(boxes):
+        n = p.shape[0]
+        r = oracle.run(p, v, L, 50, energy_every=25)
+        assert np.abs(_wrapdiff(pos[off:off + n], r.q, L)).max() < 1e-9
+        np.testing.assert_allclose(pe[:, k], r.pe, rtol=1e-10)
+        reb += r.rebuilds
+        off += n
+    assert st["rebuilds"] == reb
