@@ -223,8 +223,7 @@ int32_t estimate_cap(const md_ctx* c) {
         const double rho = (double)p.n / (p.box[0] * p.box[1] * p.box[2]);
         mean = std::max(mean, rho * 4.0 / 3.0 * M_PI * rl * rl * rl);
     }
-    int32_t cap = (int32_t)std::ceil(1.5 * mean) + 16;
-    return (cap + 7) / 8 * 8;
+    return (int32_t)std::ceil(1.5 * mean) + 16;
 }
 
 md_status upload_geometry(md_ctx* c) {
@@ -275,12 +274,13 @@ md_status alloc_cells(md_ctx* c) {
     if ((s = dalloc(c, &c->D.cell_start, (size_t)c->ntile * kTile)) != MD_OK) return s;
     if ((s = dalloc(c, &c->D.tile_sum, c->ntile)) != MD_OK) return s;
     if ((s = dalloc(c, &c->D.tile_pref, c->ntile)) != MD_OK) return s;
+    if ((s = dalloc(c, &c->D.tile_need, c->ntile)) != MD_OK) return s;
     return MD_OK;
 }
 
 md_status alloc_list(md_ctx* c, int32_t cap) {
     const int tpk = c->P.tpk;
-    cap = (cap + 7) / 8 * 8;  // any tpk divides it
+    cap = (cap + 4 * tpk - 1) / (4 * tpk) * (4 * tpk);  // rows = cap / tpk is a multiple of 4
     dfree(c->D.list);
     const int64_t entries = (int64_t)c->nslot * cap;
     md_status s = dalloc(c, &c->D.list, (size_t)entries);
@@ -319,6 +319,7 @@ void free_all(md_ctx* c) {
     Dev& D = c->D;
     dfree(D.geom);
     dfree(D.st);
+    dfree(D.any);
     dfree(D.wave_box);
     dfree(D.tile_box);
     for (int k = 0; k < 2; ++k) {
@@ -343,6 +344,9 @@ void free_all(md_ctx* c) {
     dfree(D.cell_start);
     dfree(D.tile_sum);
     dfree(D.tile_pref);
+    dfree(D.tile_need);
+    dfree(D.vmax_s);
+    dfree(D.disp_s);
     dfree(D.ke_part);
     dfree(D.pe_part);
     dfree(D.dshift);
@@ -370,6 +374,7 @@ md_status alloc_all(md_ctx* c) {
     } while (0)
     A(D.geom, c->nbox);
     A(D.st, c->nbox);
+    A(D.any, 1);
     A(D.wave_box, c->nwave);
     for (int k = 0; k < 2; ++k) {
         A(D.q[k], ns);
@@ -388,6 +393,8 @@ md_status alloc_all(md_ctx* c) {
     A(D.cell_tmp, ns);
     A(D.ticket, ns);
     A(D.perm, ns);
+    A(D.vmax_s, (size_t)c->nbox * kStripes * kStripeStride);
+    A(D.disp_s, (size_t)c->nbox * kStripes * kStripeStride);
     A(D.ke_part, (size_t)c->nwave * 8);
     A(D.pe_part, (size_t)c->nwave * 8);
     A(D.dshift, (size_t)27 * c->nbox);
@@ -399,6 +406,9 @@ md_status alloc_all(md_ctx* c) {
     A(c->dscratch, (size_t)c->nbox);
 #undef A
     if ((s = alloc_cells(c)) != MD_OK) return s;
+    HIPCHK(c, hipMemsetAsync(D.any, 0, sizeof(int32_t), c->stream));
+    HIPCHK(c, hipMemsetAsync(D.vmax_s, 0, sizeof(unsigned long long) * c->nbox * kStripes * kStripeStride, c->stream));
+    HIPCHK(c, hipMemsetAsync(D.disp_s, 0, sizeof(unsigned long long) * c->nbox * kStripes * kStripeStride, c->stream));
     HIPCHK(c, hipHostMalloc((void**)&c->st_h, sizeof(BoxState) * c->nbox, hipHostMallocDefault));
     std::memset(c->st_h, 0, sizeof(BoxState) * c->nbox);
     return MD_OK;
@@ -763,7 +773,6 @@ md_status md_step(md_ctx* c, int32_t nsteps, int32_t energy_every) {
                 st.sq = st.sp = 0;
                 st.need = 0;
                 st.rebuild = 0;
-                st.vmax2 = st.disp2 = 0ull;
                 st.built = c->st_h[b].built;
                 c->st_h[b] = st;
             }

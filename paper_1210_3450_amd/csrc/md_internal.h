@@ -15,9 +15,12 @@
 //   v*[2]     float64 velocity components (SoA), ping-pong only across a re-sort.
 //   id[2]     caller index of the particle in each slot.
 //   cellc[2]  packed cell coordinates at the last build: cx | cy << 10 | cz << 20.
-//   list      wave-blocked ELL pair list.  A list wave holds K = 64 / tpk keys; key k's
-//             entry e lives at row e / tpk, lane (k % K) * tpk + e % tpk of its wave's
-//             rows x 64 block.  Entry = partner slot (27 bits) | shift code << 27.
+//   list      wave-blocked ELL pair list.  A list wave holds K = 64 / tpk keys and
+//             rows * 64 words (rows = cap / tpk, a multiple of 4).  Key k's entry e
+//             belongs to lane ln = (k % K) * tpk + e % tpk as that lane's entry
+//             m = e / tpk; each lane's entries sit in 4-word chunks, chunk c of all
+//             64 lanes side by side, so one 16-byte load per lane reads 4 entries.
+//             Entry = partner slot (27 bits) | shift code << 27.
 //             Shift code: FP64 path = periodic image r in {-1,0,1}^3 as
 //             (rz+1)*9 + (ry+1)*3 + (rx+1); FP32-mixed path = stencil offset o of
 //             the partner's cell, same encoding.
@@ -37,6 +40,8 @@ constexpr int kMaxSeries = 4096;         // energy samples kept per box
 constexpr int kMaxCellsPerAxis = 1023;   // 10-bit packed cell coordinates
 constexpr int kUnitBits = 28;            // fixed-point units per cell side: 2^28
 constexpr int kUnitClamp = 1 << 29;      // |u| bound (two cell sides): pair sums stay in int32
+constexpr int kStripes = 1024;           // slots per box for per-step maxima
+constexpr int kStripeStride = 16;        // 128 bytes between slots
 
 struct BoxGeom {
     double L[3];
@@ -58,13 +63,11 @@ struct BoxGeom {
 
 struct BoxState {
     double D;                  // DUTC bound since the last build
-    unsigned long long vmax2;  // bits of max |v|^2 over the step (non-negative double)
-    unsigned long long disp2;  // bits of max |q - q_build|^2 (displacement policy)
     int32_t rebuild;           // list build pending for this box
     int32_t sq;                // current q / u buffer
     int32_t sp;                // current v / id / cellc buffer
     int32_t err;               // bit 0: bad position at binning
-    int32_t need;              // longest list seen at a build (for overflow detection)
+    int32_t need;              // longest list seen at any build (for overflow detection)
     int32_t built;             // builds done
     unsigned long long missed; // verifier: pairs within rc absent from the list
     double ke, pe;             // last reduced energies
@@ -90,6 +93,7 @@ struct Params {
 struct Dev {
     BoxGeom* geom;
     BoxState* st;
+    int32_t* any;        // nonzero while some box has a list build pending this step
     int32_t* wave_box;   // box of each 64-slot wavefront
     int32_t* tile_box;   // box of each cell tile
     double4* q[2];
@@ -112,6 +116,9 @@ struct Dev {
     int32_t* cell_start;
     int32_t* tile_sum;
     int32_t* tile_pref;
+    int32_t* tile_need;  // longest list per cell tile at the last build
+    unsigned long long* vmax_s;  // [nbox][kStripes] striped max |v|^2 (bits), stride kStripeStride
+    unsigned long long* disp_s;  // [nbox][kStripes] striped max |q - q_build|^2 (bits)
     double* ke_part;     // per list wave
     double* pe_part;
     double4* dshift;     // [nbox][27] FP64 image shift s * L
@@ -144,7 +151,6 @@ void launch_force(const Dev& d, const Params& p, int mode, bool energy, hipStrea
 void launch_kick_drift(const Dev& d, const Params& p, hipStream_t s);
 void launch_dutc(const Dev& d, const Params& p, hipStream_t s);
 void launch_energy_reduce(const Dev& d, const Params& p, bool record, hipStream_t s);
-void launch_kinetic(const Dev& d, const Params& p, hipStream_t s);
 void launch_verify(const Dev& d, const Params& p, hipStream_t s);
 void launch_scale(const Dev& d, const Params& p, const double* alpha_q, const double* scale_v,
                   hipStream_t s);

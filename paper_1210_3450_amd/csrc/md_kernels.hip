@@ -187,12 +187,24 @@ __global__ __launch_bounds__(kBlock) void k_list_counts(Dev d, Params p, int64_t
     }
 }
 
-// Entry e of key slot s, in the wave-blocked layout.
-__device__ __forceinline__ size_t list_index(int s, int e, int tpk, int rows) {
+// Offset of entry e from entry 0 of the same key in the chunked list.
+template <int TPK>
+__device__ __forceinline__ uint32_t list_off(int e) {
+    const int m = e / TPK;
+    return ((uint32_t)(m & ~3) << 6) + (uint32_t)((e % TPK) << 2) + (uint32_t)(m & 3);
+}
+
+// Address of entry e of key slot s in the chunked wave-blocked list: a list wave
+// of K = 64 / tpk keys owns rows * 64 words; lane ln = (s % K) * tpk + e % tpk
+// keeps its per-lane entries m = e / tpk in 4-word chunks, chunk c of every lane
+// stored side by side (one 16-byte load per lane reads 4 entries).
+__device__ __forceinline__ size_t list_addr(int s, int e, int tpk, int rows) {
     const int K = kWave / tpk;
     const int lw = s / K;
-    const int lane = (s - lw * K) * tpk + e % tpk;
-    return ((size_t)lw * rows + e / tpk) * kWave + lane;
+    const int kl = s - lw * K;
+    const int m = e / tpk;
+    const int ln = kl * tpk + (e - m * tpk);
+    return ((size_t)lw * rows + (m & ~3)) * kWave + ln * 4 + (m & 3);
 }
 
 __global__ __launch_bounds__(kBlock) void k_list_export(Dev d, Params p, const int64_t* __restrict__ key_ptr,
@@ -208,7 +220,7 @@ __global__ __launch_bounds__(kBlock) void k_list_export(Dev d, Params p, const i
         const int64_t base = key_ptr[id[s]];
         const int n = d.cnt[s];
         for (int e = 0; e < n; ++e) {
-            const uint32_t ent = d.list[list_index(s, e, p.tpk, p.rows)];
+            const uint32_t ent = d.list[list_addr(s, e, p.tpk, p.rows)];
             partners[base + e] = id[ent & kIdxMask];
         }
         for (int a = 1; a < n; ++a) {  // ascending, insertion sort
@@ -227,33 +239,57 @@ __global__ __launch_bounds__(kBlock) void k_list_export(Dev d, Params p, const i
 
 __global__ void k_mark_rebuild(Dev d, Params p) {
     for (int b = threadIdx.x; b < p.nbox; b += blockDim.x) d.st[b].rebuild = 1;
+    if (threadIdx.x == 0) *d.any = 1;
+}
+
+// Max over a box's striped partial maxima (bit patterns of non-negative doubles),
+// clearing the stripes for the next step.  One block per box.
+__device__ double stripe_max(unsigned long long* stripes) {
+    __shared__ double red[kBlock];
+    double m = 0.0;
+    for (int k = threadIdx.x; k < kStripes; k += kBlock) {
+        unsigned long long* a = stripes + (size_t)k * kStripeStride;
+        m = fmax(m, __longlong_as_double((long long)*a));
+        *a = 0ull;
+    }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int o = kBlock / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
 }
 
 // After the drift: swap the q/u buffers, accumulate the DUTC bound and decide
-// whether the list must be rebuilt (Sec. II.A).  One thread per box.
-__global__ void k_dutc(Dev d, Params p) {
+// whether the list must be rebuilt (Sec. II.A).  One block per box.
+__global__ __launch_bounds__(kBlock) void k_dutc(Dev d, Params p) {
 #pragma clang fp contract(off)
-    for (int b = threadIdx.x; b < p.nbox; b += blockDim.x) {
-        BoxState& st = d.st[b];
-        st.sq ^= 1;
-        const double vmax2 = __longlong_as_double((long long)st.vmax2);
-        st.vmax2 = 0ull;
-        st.D = st.D + p.dt * sqrt(vmax2);
-        int rb = 0;
-        if (p.policy == MD_REBUILD_DUTC) {
-            rb = 2.0 * st.D > p.skin;
-        } else if (p.policy == MD_REBUILD_DISPLACEMENT) {
-            const double m2 = __longlong_as_double((long long)st.disp2);
-            rb = 2.0 * sqrt(m2) > p.skin;
-        } else if (p.policy == MD_REBUILD_EVERY_STEP) {
-            rb = 1;
+    for (int b = blockIdx.x; b < p.nbox; b += gridDim.x) {
+        const double vmax2 = stripe_max(d.vmax_s + (size_t)b * kStripes * kStripeStride);
+        double m2 = 0.0;
+        if (d.qb) m2 = stripe_max(d.disp_s + (size_t)b * kStripes * kStripeStride);
+        if (threadIdx.x == 0) {
+            BoxState& st = d.st[b];
+            st.sq ^= 1;
+            st.D = st.D + p.dt * sqrt(vmax2);
+            int rb = 0;
+            if (p.policy == MD_REBUILD_DUTC)
+                rb = 2.0 * st.D > p.skin;
+            else if (p.policy == MD_REBUILD_DISPLACEMENT)
+                rb = 2.0 * sqrt(m2) > p.skin;
+            else if (p.policy == MD_REBUILD_EVERY_STEP)
+                rb = 1;
+            st.rebuild = rb;
+            if (rb) atomicOr(d.any, 1);
         }
-        st.disp2 = 0ull;
-        st.rebuild = rb;
     }
 }
 
 __global__ void k_flip(Dev d, Params p) {
+    if (!*d.any) return;
     for (int b = threadIdx.x; b < p.nbox; b += blockDim.x) {
         BoxState& st = d.st[b];
         if (st.rebuild) {
@@ -263,55 +299,93 @@ __global__ void k_flip(Dev d, Params p) {
     }
 }
 
-__global__ void k_post_build(Dev d, Params p, int with_list) {
-    for (int b = threadIdx.x; b < p.nbox; b += blockDim.x) {
+// After a build: longest list over each box's cell tiles, DUTC bound reset, and
+// the "some box rebuilds" gate cleared.  A single block walks every box, so the
+// gate is cleared only after all of them are done.
+__global__ __launch_bounds__(kBlock) void k_post_build(Dev d, Params p, int with_list) {
+    __shared__ int red[kBlock];
+    if (!*d.any) return;
+    for (int b = 0; b < p.nbox; ++b) {
         BoxState& st = d.st[b];
-        if (st.rebuild) {
+        if (!st.rebuild) continue;  // uniform over the block
+        const BoxGeom& g = d.geom[b];
+        int m = 0;
+        if (with_list)
+            for (int t = threadIdx.x; t < g.ntile; t += kBlock) m = max(m, d.tile_need[g.tile_off + t]);
+        red[threadIdx.x] = m;
+        __syncthreads();
+        for (int o = kBlock / 2; o > 0; o >>= 1) {
+            if (threadIdx.x < o) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + o]);
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
             if (with_list) {
                 st.D = 0.0;
-                st.disp2 = 0ull;
                 st.built += 1;
+                st.need = max(st.need, red[0]);
             }
             st.rebuild = 0;
         }
+        __syncthreads();
     }
+    if (threadIdx.x == 0) *d.any = 0;
 }
 
 // ---------------------------------------------------------------- binning
 
 __global__ __launch_bounds__(kBlock) void k_cell_clear(Dev d, Params p) {
+    if (!*d.any) return;  // no box rebuilds this step
     for (int t = blockIdx.x; t < p.ntile; t += gridDim.x) {
         if (!d.st[d.tile_box[t]].rebuild) continue;
         int4* c = reinterpret_cast<int4*>(d.cell_cnt + (size_t)t * kTile);
         c[threadIdx.x] = make_int4(0, 0, 0, 0);
+        if (threadIdx.x == 0) d.tile_need[t] = 0;
     }
 }
 
 // Wrap + cell id (A1) and the histogram half of the counting sort (A2).
+// Slots arrive sorted by cell from the previous build, so a wavefront issues one
+// atomic per run of equal cells and hands out tickets within the run.
 __global__ __launch_bounds__(kBlock) void k_bin(Dev d, Params p) {
+    if (!*d.any) return;  // no box rebuilds this step
     const int l = lane_id();
     for (int w = blockIdx.x * 4 + (threadIdx.x >> 6); w < p.nwave; w += gridDim.x * 4) {
         const int b = d.wave_box[w];
-        if (!d.st[b].rebuild) continue;
+        if (!d.st[b].rebuild) continue;  // uniform over the wavefront
         const BoxGeom& g = d.geom[b];
         const int s = w * kWave + l;
-        if (s - g.slot_off >= g.npart) continue;
-        const int sq = d.st[b].sq;
-        double4 x = d.q[sq][s];
-        bool bad = false;
-        const int cx = bin_axis(x.x, g.L[0], g.inv[0], g.n[0], bad);
-        const int cy = bin_axis(x.y, g.L[1], g.inv[1], g.n[1], bad);
-        const int cz = bin_axis(x.z, g.L[2], g.inv[2], g.n[2], bad);
-        if (bad) atomicOr(&d.st[b].err, 1);
-        d.q[sq][s] = x;
-        const int cid = (cz * g.n[1] + cy) * g.n[0] + cx;
-        d.cell_tmp[s] = cid;
-        d.ticket[s] = atomicAdd(&d.cell_cnt[g.cell_off + cid], 1);
+        const bool valid = s - g.slot_off < g.npart;  // the valid lanes are a prefix
+        int cid = -1;
+        if (valid) {
+            const int sq = d.st[b].sq;
+            double4 x = d.q[sq][s];
+            bool bad = false;
+            const int cx = bin_axis(x.x, g.L[0], g.inv[0], g.n[0], bad);
+            const int cy = bin_axis(x.y, g.L[1], g.inv[1], g.n[1], bad);
+            const int cz = bin_axis(x.z, g.L[2], g.inv[2], g.n[2], bad);
+            if (bad) atomicOr(&d.st[b].err, 1);
+            d.q[sq][s] = x;
+            cid = (cz * g.n[1] + cy) * g.n[0] + cx;
+            d.cell_tmp[s] = cid;
+        }
+        const unsigned long long vm = __ballot(valid);
+        const int prev = __shfl_up(cid, 1);
+        const bool head = valid && (l == 0 || prev != cid);
+        const unsigned long long hm = __ballot(head);
+        const unsigned long long upto = l == 63 ? ~0ull : ((2ull << l) - 1ull);
+        const int my_head = 63 - __clzll((long long)(hm & upto));
+        const unsigned long long above = hm & ~upto;
+        const int run_end = above ? __ffsll((long long)above) - 1 : __popcll(vm);
+        int base = 0;
+        if (head) base = atomicAdd(&d.cell_cnt[g.cell_off + cid], run_end - l);
+        base = __shfl(base, my_head & 63);
+        if (valid) d.ticket[s] = base + (l - my_head);
     }
 }
 
 // Tile-local exclusive scan of cell counts; tile totals to tile_sum.
 __global__ __launch_bounds__(kBlock) void k_scan_tile(Dev d, Params p) {
+    if (!*d.any) return;  // no box rebuilds this step
     for (int t = blockIdx.x; t < p.ntile; t += gridDim.x) {
         if (!d.st[d.tile_box[t]].rebuild) continue;  // uniform over the block
         const size_t base = (size_t)t * kTile + threadIdx.x * 4;
@@ -326,6 +400,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_tile(Dev d, Params p) {
 
 // Per box: exclusive scan over its tiles' totals, offset by the box's first slot.
 __global__ __launch_bounds__(kBlock) void k_scan_box(Dev d, Params p) {
+    if (!*d.any) return;  // no box rebuilds this step
     for (int b = blockIdx.x; b < p.nbox; b += gridDim.x) {
         if (!d.st[b].rebuild) continue;
         const BoxGeom& g = d.geom[b];
@@ -342,6 +417,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_box(Dev d, Params p) {
 }
 
 __global__ __launch_bounds__(kBlock) void k_scan_add(Dev d, Params p) {
+    if (!*d.any) return;  // no box rebuilds this step
     for (int t = blockIdx.x; t < p.ntile; t += gridDim.x) {
         if (!d.st[d.tile_box[t]].rebuild) continue;
         const int add = d.tile_pref[t];
@@ -353,6 +429,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_add(Dev d, Params p) {
 }
 
 __global__ __launch_bounds__(kBlock) void k_scatter(Dev d, Params p) {
+    if (!*d.any) return;  // no box rebuilds this step
     const int l = lane_id();
     for (int w = blockIdx.x * 4 + (threadIdx.x >> 6); w < p.nwave; w += gridDim.x * 4) {
         const int b = d.wave_box[w];
@@ -367,6 +444,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(Dev d, Params p) {
 // Arrival order within a cell depends on atomics; order each cell's members by
 // caller id so the sorted layout is a function of the positions alone.
 __global__ __launch_bounds__(kBlock) void k_cell_sort(Dev d, Params p) {
+    if (!*d.any) return;  // no box rebuilds this step
     for (int t = blockIdx.x; t < p.ntile; t += gridDim.x) {
         const int b = d.tile_box[t];
         if (!d.st[b].rebuild) continue;
@@ -394,6 +472,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_sort(Dev d, Params p) {
 // Gather into cell-sorted, coalesced arrays (A3) and write cell-relative FP32
 // coordinates for the mixed path.
 __global__ __launch_bounds__(kBlock) void k_permute(Dev d, Params p) {
+    if (!*d.any) return;  // no box rebuilds this step
     const int l = lane_id();
     for (int w = blockIdx.x * 4 + (threadIdx.x >> 6); w < p.nwave; w += gridDim.x * 4) {
         const int b = d.wave_box[w];
@@ -434,6 +513,21 @@ __device__ __forceinline__ double dist2_exact(const double4& qi, const double4& 
     const double dz = (qj.z - qi.z) - shz;
     return dx * dx + dy * dy + dz * dz;
 }
+// The same value when every image term is zero (t - 0 is t exactly).
+__device__ __forceinline__ double dist2_exact0(const double4& qi, const double4& qj) {
+#pragma clang fp contract(off)
+    const double dx = qj.x - qi.x;
+    const double dy = qj.y - qi.y;
+    const double dz = qj.z - qi.z;
+    return dx * dx + dy * dy + dz * dz;
+}
+
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+    const long long u = __double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(u & 0xffffffffll), lane);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(u >> 32), lane);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
 
 // Neighbour cell along one axis with its periodic image.  sub is the amount
 // the oracle's minimum image subtracts: L * rint(t / L) with t = x_j - x_i.
@@ -453,81 +547,114 @@ __device__ __forceinline__ int nb_axis(int c, int o, int n, double L, double& su
     return x;
 }
 
-// A4: for every key, every partner within r_list among the 27 cells around its
-// cell.  TPK lanes share a key; accepted partners are compacted in candidate
-// order by a wavefront ballot and a popcount prefix.  The distance test is the
-// plain definition in FP64 with no contraction, so the accepted set is the
-// same bit for bit as the CPU's.
+// A4, one wavefront per home cell.  All keys of a cell share one candidate set:
+// the particles of its 27 stencil cells, concatenated in stencil order.  Lane l
+// holds candidate l of each 64-wide chunk (loads are contiguous runs), and the
+// wavefront walks the cell's keys: an exact FP64 test per (key, candidate), a
+// ballot, a popcount prefix, and the accepted partners appended in candidate
+// order.  The distance test is the plain definition with no contraction, so the
+// accepted set is the CPU's bit for bit.
+
+// Positions seen through the constant address space: in the list build they are
+// read-only, and uniform indices then become scalar loads into SGPRs.
+typedef const __attribute__((address_space(4))) double const_double;
+
 template <int TPK>
 __global__ __launch_bounds__(kBlock) void k_list(Dev d, Params p) {
-    constexpr int K = kWave / TPK;
+    if (!*d.any) return;  // no box rebuilds this step
     const int l = lane_id();
-    const int sub = l % TPK, gbase = l - sub;
-    const int nlw = p.nwave * TPK;
-    for (int lw = blockIdx.x * 4 + (threadIdx.x >> 6); lw < nlw; lw += gridDim.x * 4) {
-        const int slot0 = lw * K;
-        const int b = d.wave_box[slot0 >> 6];
+    const int ncells = p.ntile * kTile;
+    const bool fp64 = p.precision == MD_PREC_FP64;
+    const double nan = __longlong_as_double(0x7ff8000000000000ll);
+    const double rl2 = p.rl2;
+    const int cap = p.cap, rows = p.rows;
+    for (int c = blockIdx.x * 4 + (threadIdx.x >> 6); c < ncells; c += gridDim.x * 4) {
+        const int t = c / kTile;
+        const int b = d.tile_box[t];
         const BoxState& st = d.st[b];
         if (!st.rebuild) continue;
         const BoxGeom& g = d.geom[b];
-        const int key = slot0 + l / TPK;
-        const bool active = key - g.slot_off < g.npart;
-        int n_i = 0;
-        if (active) {
-            const double4* __restrict__ q = d.q[st.sq];
-            const double4 qi = q[key];
-            const uint32_t cc = d.cellc[st.sp][key];
-            const int cx = cc & 1023, cy = (cc >> 10) & 1023, cz = cc >> 20;
-            uint32_t* __restrict__ lst = d.list + (size_t)lw * p.rows * kWave;
-            const bool fp64 = p.precision == MD_PREC_FP64;
-            for (int oz = -1; oz <= 1; ++oz) {
-                double shz;
-                int rz;
-                const int z = nb_axis(cz, oz, g.n[2], g.L[2], shz, rz);
-                for (int oy = -1; oy <= 1; ++oy) {
-                    double shy;
-                    int ry;
-                    const int y = nb_axis(cy, oy, g.n[1], g.L[1], shy, ry);
-                    for (int ox = -1; ox <= 1; ++ox) {
-                        double shx;
-                        int rx;
-                        const int x = nb_axis(cx, ox, g.n[0], g.L[0], shx, rx);
-                        const int cell = g.cell_off + (z * g.n[1] + y) * g.n[0] + x;
-                        const int start = d.cell_start[cell];
-                        const int end = start + d.cell_cnt[cell];
-                        const uint32_t code =
-                            (fp64 ? (uint32_t)((rz + 1) * 9 + (ry + 1) * 3 + (rx + 1))
-                                  : (uint32_t)((oz + 1) * 9 + (oy + 1) * 3 + (ox + 1)))
-                            << kIdxBits;
-                        for (int base = start; base < end; base += TPK) {
-                            const int j = base + sub;
-                            bool acc = false;
-                            if (j < end && j != key) {
-                                acc = dist2_exact(qi, q[j], shx, shy, shz) < p.rl2;
-                            }
-                            if (TPK == 1) {
-                                if (acc) {
-                                    if (n_i < p.cap) lst[(size_t)n_i * kWave + l] = (uint32_t)j | code;
-                                    ++n_i;
-                                }
-                            } else {
-                                const unsigned long long m = __ballot(acc);
-                                const uint32_t gm = (uint32_t)(m >> gbase) & ((1u << TPK) - 1u);
-                                if (acc) {
-                                    const int pos = n_i + __popc(gm & ((1u << sub) - 1u));
-                                    if (pos < p.cap)
-                                        lst[(size_t)(pos / TPK) * kWave + gbase + pos % TPK] = (uint32_t)j | code;
-                                }
-                                n_i += __popc(gm);
-                            }
+        const int local = c - g.cell_off;
+        if (local >= g.ncell) continue;
+        const int m = __builtin_amdgcn_readfirstlane(d.cell_cnt[c]);
+        if (m == 0) continue;
+        const int cs0 = __builtin_amdgcn_readfirstlane(d.cell_start[c]);
+        const double4* __restrict__ q = d.q[__builtin_amdgcn_readfirstlane(st.sq)];
+        const int cx = local % g.n[0], cy = (local / g.n[0]) % g.n[1], cz = local / (g.n[0] * g.n[1]);
+        // stencil cell s = lane s < 27: start, count, image term and shift code
+        int start = 0, cnt = 0;
+        uint32_t code = 0;
+        double shx = 0.0, shy = 0.0, shz = 0.0;
+        if (l < 27) {
+            const int ox = l % 3 - 1, oy = (l / 3) % 3 - 1, oz = l / 9 - 1;
+            int rx, ry, rz;
+            const int x = nb_axis(cx, ox, g.n[0], g.L[0], shx, rx);
+            const int y = nb_axis(cy, oy, g.n[1], g.L[1], shy, ry);
+            const int z = nb_axis(cz, oz, g.n[2], g.L[2], shz, rz);
+            const int nc = g.cell_off + (z * g.n[1] + y) * g.n[0] + x;
+            start = d.cell_start[nc];
+            cnt = d.cell_cnt[nc];
+            code = (fp64 ? (uint32_t)((rz + 1) * 9 + (ry + 1) * 3 + (rx + 1)) : (uint32_t)l) << kIdxBits;
+        }
+        const int incl = wave_incl_scan(cnt);
+        const int pre = incl - cnt;
+        const int total = __builtin_amdgcn_readlane(incl, 26);
+        int need = 0;
+        for (int kb = 0; kb < m; kb += kWave) {
+            const int mb = min(kWave, m - kb);
+            int n_own = 0;  // lane a counts the partners of key kb + a
+            const const_double* qc = (const const_double*)q;  // 4 doubles per particle
+            for (int c0 = 0; c0 < total; c0 += kWave) {
+                const int ci = c0 + l;
+                const bool valid = ci < total;
+                int sc = 0;  // last stencil cell whose range starts at or before ci
+                for (int step = 16; step > 0; step >>= 1) {
+                    const int tt = sc + step;
+                    const int pv = __shfl(pre, tt < 27 ? tt : 26);
+                    if (tt < 27 && pv <= ci) sc = tt;
+                }
+                // shuffles run on every lane: a bpermute from an inactive lane reads 0
+                const int st_sc = __shfl(start, sc), pre_sc = __shfl(pre, sc);
+                const int j = valid ? st_sc + ci - pre_sc : -1;
+                const uint32_t ent = (uint32_t)j | (uint32_t)__shfl((int)code, sc);
+                const double sx = __shfl(shx, sc), sy = __shfl(shy, sc), sz = __shfl(shz, sc);
+                double4 qj = q[valid ? j : cs0];
+                if (!valid) qj.x = nan;  // NaN distance: never accepted
+                const bool wrapped = __ballot(valid && (sx != 0.0 || sy != 0.0 || sz != 0.0)) != 0ull;
+                // The candidate loads must land before the key loop: a wait placed
+                // inside it would also wait on the list stores issued there.
+                __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+                double nx = qc[4 * (cs0 + kb)], ny = qc[4 * (cs0 + kb) + 1], nz = qc[4 * (cs0 + kb) + 2];
+                for (int a = 0; a < mb; ++a) {
+                    const int key = cs0 + kb + a;
+                    double4 qi;  // scalar loads, one key ahead
+                    qi.x = nx;
+                    qi.y = ny;
+                    qi.z = nz;
+                    if (a + 1 < mb) {
+                        nx = qc[4 * (key + 1)];
+                        ny = qc[4 * (key + 1) + 1];
+                        nz = qc[4 * (key + 1) + 2];
+                    }
+                    const double r2 = wrapped ? dist2_exact(qi, qj, sx, sy, sz) : dist2_exact0(qi, qj);
+                    const bool acc = r2 < rl2 && j != key;
+                    const unsigned long long mask = __ballot(acc);
+                    if (mask) {
+                        const int na = __builtin_amdgcn_readlane(n_own, a);
+                        if (acc) {
+                            const int pos = na + (int)__builtin_amdgcn_mbcnt_hi(
+                                                     (unsigned)(mask >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+                            if (pos < cap) d.list[list_addr(key, pos, TPK, rows)] = ent;
                         }
+                        if (l == a) n_own += __popcll(mask);
                     }
                 }
             }
-            if (sub == 0) d.cnt[key] = n_i < p.cap ? n_i : p.cap;
+            if (l < mb) d.cnt[cs0 + kb + l] = n_own < cap ? n_own : cap;
+            need = max(need, wave_max_i(n_own));
         }
-        const int mx = wave_max_i(n_i);
-        if (l == 0 && mx > 0) atomicMax(&d.st[b].need, mx);
+        if (l == 0) atomicMax(&d.tile_need[t], need);
     }
 }
 
@@ -564,11 +691,22 @@ __device__ __forceinline__ double norm2(double x, double y, double z) {
     return x * x + y * y + z * z;
 }
 
+// Striped per-box maximum: each wavefront folds its value into one of kStripes
+// cache-line-separated slots, so no single address sees more than a few hundred
+// atomics per step.  k_dutc reduces and clears the stripes.
+__device__ __forceinline__ void stripe_put(unsigned long long* base, int b, int w, double v) {
+    atomicMax(base + ((size_t)b * kStripes + (w & (kStripes - 1))) * kStripeStride,
+              (unsigned long long)__double_as_longlong(v));
+}
+
 // Algorithm 1 on the GPU.  PREC: MD_PREC_FP64 or MD_PREC_FP32_MIXED.
 // MODE: kForceOnly / kForceEnd / kForceMid.  ENERGY: per-wave KE and PE partials.
+// Each lane reads 4 list entries per 16-byte load and keeps 8 partner gathers in
+// flight (Algorithm 1's unrolling for latency hiding, in GPU form).
 template <int PREC, int MODE, int TPK, bool ENERGY>
 __global__ __launch_bounds__(kBlock) void k_force(Dev d, Params p) {
     constexpr int K = kWave / TPK;
+    constexpr int U = 8;  // entries per iteration
     using V4 = typename ShiftT<PREC>::V;
     __shared__ V4 shift[kBlock / kWave][27];
     const int l = lane_id(), wib = threadIdx.x >> 6, sub = l % TPK;
@@ -592,27 +730,45 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Params p) {
     double Fx = 0.0, Fy = 0.0, Fz = 0.0, pe = 0.0;
     if (active) {
         const int n_i = d.cnt[key];
-        const uint32_t* __restrict__ lst = d.list + (size_t)lw * p.rows * kWave + l;
+        const int nl = n_i > sub ? (n_i - sub + TPK - 1) / TPK : 0;  // this lane's entries
+        const uint4* __restrict__ l4 = reinterpret_cast<const uint4*>(d.list + (size_t)lw * p.rows * kWave) + l;
+        const uint32_t self = (uint32_t)key | (13u << kIdxBits);  // padding: zero shift, masked below
         if constexpr (PREC == MD_PREC_FP64) {
             const double4* __restrict__ q = d.q[sq];
             const double4 qi = q[key];
             const double rc2 = p.rc2, c2x8 = 8.0 * p.c2;
-            for (int e = sub, r = 0; e < n_i; e += TPK, ++r) {
-                const uint32_t ent = lst[(size_t)r * kWave];
-                const double4 qj = q[ent & kIdxMask];
-                const double4 sh = shift[wib][ent >> kIdxBits];
-                const double dx = (qj.x - qi.x) - sh.x;
-                const double dy = (qj.y - qi.y) - sh.y;
-                const double dz = (qj.z - qi.z) - sh.z;
-                const double r2 = dx * dx + dy * dy + dz * dz;
-                if (r2 < rc2) {
-                    const double inv = 1.0 / r2;
-                    const double inv3 = inv * inv * inv;
-                    const double f = (24.0 * inv3 - 48.0 * inv3 * inv3) * inv + c2x8;
-                    Fx += f * dx;
-                    Fy += f * dy;
-                    Fz += f * dz;
-                    if (ENERGY) pe += 2.0 * (inv3 * inv3 - inv3 + p.c2 * r2 + p.c0);
+            for (int m0 = 0; m0 < nl; m0 += U) {
+                uint32_t e[U];
+                const uint4 a0 = l4[(size_t)(m0 >> 2) * kWave];
+                e[0] = a0.x; e[1] = a0.y; e[2] = a0.z; e[3] = a0.w;
+                if (m0 + 4 < nl) {
+                    const uint4 a1 = l4[(size_t)((m0 >> 2) + 1) * kWave];
+                    e[4] = a1.x; e[5] = a1.y; e[6] = a1.z; e[7] = a1.w;
+                } else {
+                    e[4] = e[5] = e[6] = e[7] = self;
+                }
+#pragma unroll
+                for (int k = 0; k < U; ++k)
+                    if (m0 + k >= nl) e[k] = self;
+                double4 qj[U];
+#pragma unroll
+                for (int k = 0; k < U; ++k) qj[k] = q[e[k] & kIdxMask];
+#pragma unroll
+                for (int k = 0; k < U; ++k) {
+                    const double4 sh = shift[wib][e[k] >> kIdxBits];
+                    const double dx = (qj[k].x - qi.x) - sh.x;
+                    const double dy = (qj[k].y - qi.y) - sh.y;
+                    const double dz = (qj[k].z - qi.z) - sh.z;
+                    const double r2 = dx * dx + dy * dy + dz * dz;
+                    if (m0 + k < nl && r2 < rc2) {
+                        const double inv = 1.0 / r2;
+                        const double inv3 = inv * inv * inv;
+                        const double f = (24.0 * inv3 - 48.0 * inv3 * inv3) * inv + c2x8;
+                        Fx += f * dx;
+                        Fy += f * dy;
+                        Fz += f * dz;
+                        if (ENERGY) pe += 2.0 * (inv3 * inv3 - inv3 + p.c2 * r2 + p.c0);
+                    }
                 }
             }
         } else {
@@ -621,24 +777,44 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Params p) {
             const float ux = g.usc[0], uy = g.usc[1], uz = g.usc[2];
             const float rc2 = p.rc2f, c2x8 = 8.0f * p.c2f;
             float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f, pes = 0.f;
-            for (int e = sub, r = 0; e < n_i; e += TPK, ++r) {
-                const uint32_t ent = lst[(size_t)r * kWave];
-                const int4 uj = u[ent & kIdxMask];
-                const int4 sh = shift[wib][ent >> kIdxBits];
-                // exact integer separation, one rounding to FP32, one scaling
-                const float dx = (float)(uj.x - ui.x + sh.x) * ux;
-                const float dy = (float)(uj.y - ui.y + sh.y) * uy;
-                const float dz = (float)(uj.z - ui.z + sh.z) * uz;
-                const float r2 = dx * dx + dy * dy + dz * dz;
-                if (r2 < rc2) {
-                    const float inv = __builtin_amdgcn_rcpf(r2);
-                    const float inv3 = inv * inv * inv;
-                    const float f = (24.0f * inv3 - 48.0f * inv3 * inv3) * inv + c2x8;
-                    kahan_add(sx, cx, f * dx);
-                    kahan_add(sy, cy, f * dy);
-                    kahan_add(sz, cz, f * dz);
-                    if (ENERGY) pes += 2.0f * (inv3 * inv3 - inv3 + p.c2f * r2 + p.c0f);
+            for (int m0 = 0; m0 < nl; m0 += U) {
+                uint32_t e[U];
+                const uint4 a0 = l4[(size_t)(m0 >> 2) * kWave];
+                e[0] = a0.x; e[1] = a0.y; e[2] = a0.z; e[3] = a0.w;
+                if (m0 + 4 < nl) {
+                    const uint4 a1 = l4[(size_t)((m0 >> 2) + 1) * kWave];
+                    e[4] = a1.x; e[5] = a1.y; e[6] = a1.z; e[7] = a1.w;
+                } else {
+                    e[4] = e[5] = e[6] = e[7] = self;
                 }
+#pragma unroll
+                for (int k = 0; k < U; ++k)
+                    if (m0 + k >= nl) e[k] = self;
+                int4 uj[U];
+#pragma unroll
+                for (int k = 0; k < U; ++k) uj[k] = u[e[k] & kIdxMask];
+                float bx = 0.f, by = 0.f, bz = 0.f;  // plain FP32 sum of this batch
+#pragma unroll
+                for (int k = 0; k < U; ++k) {
+                    const int4 sh = shift[wib][e[k] >> kIdxBits];
+                    // exact integer separation, one rounding to FP32, one scaling
+                    const float dx = (float)(uj[k].x - ui.x + sh.x) * ux;
+                    const float dy = (float)(uj[k].y - ui.y + sh.y) * uy;
+                    const float dz = (float)(uj[k].z - ui.z + sh.z) * uz;
+                    const float r2 = dx * dx + dy * dy + dz * dz;
+                    if (m0 + k < nl && r2 < rc2) {
+                        const float inv = __builtin_amdgcn_rcpf(r2);
+                        const float inv3 = inv * inv * inv;
+                        const float f = (24.0f * inv3 - 48.0f * inv3 * inv3) * inv + c2x8;
+                        bx += f * dx;
+                        by += f * dy;
+                        bz += f * dz;
+                        if (ENERGY) pes += 2.0f * (inv3 * inv3 - inv3 + p.c2f * r2 + p.c0f);
+                    }
+                }
+                kahan_add(sx, cx, bx);  // compensated across batches
+                kahan_add(sy, cy, by);
+                kahan_add(sz, cz, bz);
             }
             Fx = (double)sx - (double)cx;
             Fy = (double)sy - (double)cy;
@@ -698,10 +874,10 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Params p) {
     }
     if (MODE == kForceMid) {
         const double wm = wave_max(w2);
-        if (l == 0) atomicMax(&d.st[b].vmax2, (unsigned long long)__double_as_longlong(wm));
+        if (l == 0) stripe_put(d.vmax_s, b, lw, wm);
         if (d.qb) {
             const double mm = wave_max(m2);
-            if (l == 0) atomicMax(&d.st[b].disp2, (unsigned long long)__double_as_longlong(mm));
+            if (l == 0) stripe_put(d.disp_s, b, lw, mm);
         }
     }
     if (ENERGY) {
@@ -741,10 +917,10 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(Dev d, Params p) {
             }
         }
         const double wm = wave_max(w2);
-        if (l == 0) atomicMax(&d.st[b].vmax2, (unsigned long long)__double_as_longlong(wm));
+        if (l == 0) stripe_put(d.vmax_s, b, w, wm);
         if (d.qb) {
             const double mm = wave_max(m2);
-            if (l == 0) atomicMax(&d.st[b].disp2, (unsigned long long)__double_as_longlong(mm));
+            if (l == 0) stripe_put(d.disp_s, b, w, mm);
         }
     }
 }
@@ -810,7 +986,7 @@ __global__ __launch_bounds__(kBlock) void k_verify(Dev d, Params p) {
             if (r2 < p.rc2) {
                 bool found = false;
                 for (int e = 0; e < n && !found; ++e)
-                    found = (d.list[list_index(s, e, p.tpk, p.rows)] & kIdxMask) == (uint32_t)j;
+                    found = (d.list[list_addr(s, e, p.tpk, p.rows)] & kIdxMask) == (uint32_t)j;
                 if (!found) ++missed;
             }
         }
@@ -882,7 +1058,7 @@ void launch_mark_rebuild(const Dev& d, const Params& p, hipStream_t s) {
 
 template <int TPK>
 static void launch_list_t(const Dev& d, const Params& p, hipStream_t s) {
-    k_list<TPK><<<grid_for_waves(p.nwave * TPK, 8192), kBlock, 0, s>>>(d, p);
+    k_list<TPK><<<grid_for_waves(p.ntile * kTile, 8192), kBlock, 0, s>>>(d, p);
 }
 
 void launch_rebuild_chain(const Dev& d, const Params& p, bool with_list, hipStream_t s) {
@@ -946,7 +1122,9 @@ void launch_force(const Dev& d, const Params& p, int mode, bool energy, hipStrea
 void launch_kick_drift(const Dev& d, const Params& p, hipStream_t s) {
     k_kick_drift<<<(p.nwave + 3) / 4, kBlock, 0, s>>>(d, p);
 }
-void launch_dutc(const Dev& d, const Params& p, hipStream_t s) { k_dutc<<<1, kBlock, 0, s>>>(d, p); }
+void launch_dutc(const Dev& d, const Params& p, hipStream_t s) {
+    k_dutc<<<p.nbox < 1024 ? p.nbox : 1024, kBlock, 0, s>>>(d, p);
+}
 void launch_energy_reduce(const Dev& d, const Params& p, bool record, hipStream_t s) {
     k_energy_reduce<<<p.nbox < 1024 ? p.nbox : 1024, kBlock, 0, s>>>(d, p, record ? 1 : 0);
 }
