@@ -24,7 +24,8 @@ using namespace mdg;
 
 namespace {
 
-constexpr int kChunk = 200;  // steps enqueued between status checks
+constexpr int kChunk = 200;      // steps enqueued between status checks
+constexpr int kGraphSteps = 8;   // continuing steps per captured graph
 
 // Message of the last failed md_create / md_batch_create (no context exists then).
 thread_local std::string g_create_err;
@@ -57,6 +58,8 @@ struct md_ctx {
     int64_t steps = 0, regrows = 0;
     bool timing = false;
     std::vector<hipEvent_t> ev_force, ev_rebuild;  // start/stop pairs
+    // captured step graphs (MD_F_GRAPH): kGraphSteps and 1 continuing steps
+    hipGraphExec_t graph_many = nullptr, graph_one = nullptr;
     double force_ms = 0.0, rebuild_ms = 0.0;
     int64_t force_n = 0, rebuild_n = 0;
 };
@@ -112,6 +115,8 @@ void dfree(T*& p) {
 }
 
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+void drop_graphs(md_ctx* c);
 
 // Argument checks of md_create / md_batch_create (no device work).
 md_status validate(const md_params* b, int32_t nbox, std::string& why) {
@@ -263,6 +268,7 @@ md_status upload_geometry(md_ctx* c) {
 }
 
 md_status alloc_cells(md_ctx* c) {
+    drop_graphs(c);
     dfree(c->D.tile_box);
     dfree(c->D.cell_cnt);
     dfree(c->D.cell_start);
@@ -278,7 +284,16 @@ md_status alloc_cells(md_ctx* c) {
     return MD_OK;
 }
 
+// Captured graphs bake in kernel arguments (buffer pointers, sizes): drop them
+// whenever those change.
+void drop_graphs(md_ctx* c) {
+    if (c->graph_many) (void)hipGraphExecDestroy(c->graph_many);
+    if (c->graph_one) (void)hipGraphExecDestroy(c->graph_one);
+    c->graph_many = c->graph_one = nullptr;
+}
+
 md_status alloc_list(md_ctx* c, int32_t cap) {
+    drop_graphs(c);
     const int tpk = c->P.tpk;
     cap = (cap + 4 * tpk - 1) / (4 * tpk) * (4 * tpk);  // rows = cap / tpk is a multiple of 4
     dfree(c->D.list);
@@ -316,6 +331,7 @@ void params_refresh(md_ctx* c) {
 }
 
 void free_all(md_ctx* c) {
+    drop_graphs(c);
     Dev& D = c->D;
     dfree(D.geom);
     dfree(D.st);
@@ -476,6 +492,50 @@ md_status enqueue_force(md_ctx* c, int mode, bool energy) {
     launch_force(c->D, c->P, mode, energy, c->stream);
     if (c->timing && (s = timed_event(c, c->ev_force)) != MD_OK) return s;
     if (c->prm.flags & MD_F_VERIFY_LIST) launch_verify(c->D, c->P, c->stream);
+    return MD_OK;
+}
+
+// One continuing velocity-Verlet step: list rebuild chain (early exit unless
+// flagged), forces with the closing and opening half kicks and the drift, DUTC.
+md_status enqueue_mid_step(md_ctx* c) {
+    md_status s;
+    if ((s = enqueue_rebuild(c, true)) != MD_OK) return s;
+    if ((s = enqueue_force(c, kForceMid, false)) != MD_OK) return s;
+    launch_dutc(c->D, c->P, c->stream);
+    return MD_OK;
+}
+
+md_status capture(md_ctx* c, int nsteps, hipGraphExec_t* out) {
+    md_status s;
+    hipGraph_t g = nullptr;
+    HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < nsteps; ++k)
+        if ((s = enqueue_mid_step(c)) != MD_OK) {
+            (void)hipStreamEndCapture(c->stream, &g);
+            if (g) (void)hipGraphDestroy(g);
+            return s;
+        }
+    HIPCHK(c, hipStreamEndCapture(c->stream, &g));
+    hipError_t e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(c, MD_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    return MD_OK;
+}
+
+// n continuing steps, as captured graphs when MD_F_GRAPH is set (and no
+// per-kernel timing is requested), else kernel by kernel.
+md_status enqueue_mid_steps(md_ctx* c, int n) {
+    md_status s;
+    const bool graphs = (c->prm.flags & MD_F_GRAPH) && !c->timing && c->stream != nullptr;
+    if (!graphs) {
+        for (int k = 0; k < n; ++k)
+            if ((s = enqueue_mid_step(c)) != MD_OK) return s;
+        return MD_OK;
+    }
+    if (!c->graph_many && (s = capture(c, kGraphSteps, &c->graph_many)) != MD_OK) return s;
+    if (!c->graph_one && (s = capture(c, 1, &c->graph_one)) != MD_OK) return s;
+    for (; n >= kGraphSteps; n -= kGraphSteps) HIPCHK(c, hipGraphLaunch(c->graph_many, c->stream));
+    for (; n > 0; --n) HIPCHK(c, hipGraphLaunch(c->graph_one, c->stream));
     return MD_OK;
 }
 
@@ -745,10 +805,10 @@ md_status md_step(md_ctx* c, int32_t nsteps, int32_t energy_every) {
                 launch_kick_drift(c->D, c->P, c->stream);
                 launch_dutc(c->D, c->P, c->stream);
             }
-            if ((s = enqueue_rebuild(c, true)) != MD_OK) return s;
             const bool energy = energy_every > 0 && gk % energy_every == 0;
             const bool last = k == chunk;
             if (energy || last) {
+                if ((s = enqueue_rebuild(c, true)) != MD_OK) return s;
                 if ((s = enqueue_force(c, kForceEnd, energy)) != MD_OK) return s;
                 if (energy) launch_energy_reduce(c->D, c->P, true, c->stream);
                 if (!last) {
@@ -756,8 +816,11 @@ md_status md_step(md_ctx* c, int32_t nsteps, int32_t energy_every) {
                     launch_dutc(c->D, c->P, c->stream);
                 }
             } else {
-                if ((s = enqueue_force(c, kForceMid, false)) != MD_OK) return s;
-                launch_dutc(c->D, c->P, c->stream);
+                // a run of continuing steps up to the next energy sample or chunk end
+                int32_t run = 1;
+                while (k + run < chunk && !(energy_every > 0 && (gk + run) % energy_every == 0)) ++run;
+                if ((s = enqueue_mid_steps(c, run)) != MD_OK) return s;
+                k += run - 1;
             }
         }
         LAUNCHCHK(c);
@@ -931,7 +994,67 @@ md_status md_autotune(md_ctx* c, const char* cache_path) {
     md_status s;
     if ((s = check_ctx(c)) != MD_OK) return s;
     if ((s = ensure_list_and_forces(c)) != MD_OK) return s;
-    (void)cache_path;
+    // cache key: precision, density (1/20 steps), particles per box (log2), ensemble or not
+    double rho = 0.0, nmean = 0.0;
+    for (int b = 0; b < c->nbox; ++b) {
+        const md_params& p = c->boxes[b];
+        rho += (double)p.n / (p.box[0] * p.box[1] * p.box[2]) / c->nbox;
+        nmean += (double)p.n / c->nbox;
+    }
+    char key[96];
+    snprintf(key, sizeof key, "%d %d %d %d", c->prm.precision, (int)std::lround(rho * 20.0),
+             (int)std::lround(std::log2(nmean)), c->nbox > 1 ? 1 : 0);
+    int best = 0;
+    if (cache_path) {
+        std::ifstream in(cache_path);
+        std::string line;
+        while (std::getline(in, line)) {
+            if (line.empty() || line[0] == '#') continue;
+            std::istringstream ls(line);
+            int a, b2, c2, d2, t;
+            if (ls >> a >> b2 >> c2 >> d2 >> t) {
+                char k2[96];
+                snprintf(k2, sizeof k2, "%d %d %d %d", a, b2, c2, d2);
+                if (std::strcmp(k2, key) == 0 && (t == 1 || t == 2 || t == 4 || t == 8)) best = t;
+            }
+        }
+    }
+    const bool from_cache = best != 0;
+    if (!from_cache) {
+        float best_ms = 1e30f;
+        hipEvent_t e0, e1;
+        HIPCHK(c, hipEventCreate(&e0));
+        HIPCHK(c, hipEventCreate(&e1));
+        for (int tpk : {1, 2, 4, 8}) {
+            c->P.tpk = tpk;
+            if ((s = alloc_list(c, c->P.cap)) != MD_OK) return s;
+            c->have_list = false;
+            if ((s = build_list(c)) != MD_OK) return s;
+            launch_force(c->D, c->P, kForceOnly, false, c->stream);  // warm-up
+            HIPCHK(c, hipEventRecord(e0, c->stream));
+            for (int r = 0; r < 5; ++r) launch_force(c->D, c->P, kForceOnly, false, c->stream);
+            HIPCHK(c, hipEventRecord(e1, c->stream));
+            HIPCHK(c, hipEventSynchronize(e1));
+            LAUNCHCHK(c);
+            float ms = 0.f;
+            HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = tpk;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+    }
+    c->P.tpk = best;
+    if ((s = alloc_list(c, c->P.cap)) != MD_OK) return s;
+    c->have_list = false;
+    if ((s = build_list(c)) != MD_OK) return s;
+    if ((s = ensure_list_and_forces(c)) != MD_OK) return s;
+    if (cache_path && !from_cache) {
+        std::ofstream out(cache_path, std::ios::app);
+        if (out) out << key << " " << best << "\n";
+    }
     return MD_OK;
 }
 
