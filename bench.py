@@ -96,6 +96,192 @@ def cpu_baseline(w, sample_steps):
                       (w.n, sample_steps, r.rebuilds, t)}
 
 
+def drift_stats(ke, pe, n, dt, every):
+    """Energy-drift figures of a sampled series: least-squares slope of E/N in
+    epsilon per tau, max |E(t) - E(0)| / |E(0)|, and the RMS fluctuation of E/N."""
+    E = (np.asarray(ke) + np.asarray(pe)) / n
+    t = np.arange(1, E.size + 1) * every * dt
+    slope = float(np.polyfit(t, E, 1)[0]) if E.size > 1 else 0.0
+    return {"samples": int(E.size), "slope_per_tau": slope,
+            "max_rel_dev": float(np.abs(E - E[0]).max() / abs(E[0])),
+            "rms": float(E.std()), "E0_per_particle": float(E[0]), "E_end_per_particle": float(E[-1])}
+
+
+def timed_steps(ctx, torch, stream, steps, energy_every=0):
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    ctx.step(steps, energy_every)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def list_histogram(ctx):
+    kp, _ = ctx.get_neighbors()
+    cnt = (kp[1:] - kp[:-1]).cpu().numpy()
+    pct = np.percentile(cnt, [1, 10, 50, 90, 99]).tolist()
+    hist, edges = np.histogram(cnt, bins=np.arange(0, cnt.max() + 11, 10))
+    return {"mean": float(cnt.mean()), "std": float(cnt.std()), "min": int(cnt.min()), "max": int(cnt.max()),
+            "p1_p10_p50_p90_p99": pct, "bins_of_10": hist.tolist()}
+
+
+def workload_small(B, torch, args):
+    """4000-particle FCC box (10^3 cells, L = 20, T = 1, seed 1): 100 FP64 steps in
+    captured graphs, then the 10^4-step energy drift of the FP64 and FP32-mixed paths."""
+    from paper_1210_3450_amd import inputs
+    w = inputs.small_nve()
+    out = {}
+    for name, prec in (("fp64", B.MD_PREC_FP64), ("fp32_mixed", B.MD_PREC_FP32_MIXED)):
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            ctx = B.Context(B.make_params(w.n, w.box, precision=prec, flags=B.MD_F_GRAPH), stream=stream)
+            ctx.set_state(w.pos, w.vel)
+            ctx.step(args.warmup)
+            ms = timed_steps(ctx, torch, stream, 100)
+            ctx.set_state(w.pos, w.vel)
+            ctx.step(args.drift_steps, 10)
+            ke, pe = ctx.energy_series()
+            st = ctx.stats()
+            ctx.close()
+        out[name] = {"us_per_step_100": ms * 1e3 / 100, "particle_steps_per_s": w.n * 100 / (ms / 1e3),
+                     "drift_%d_steps" % args.drift_steps: drift_stats(ke[:, 0], pe[:, 0], w.n, w.dt, 10),
+                     "rebuilds": st["rebuilds"]}
+    return {"metric": "particle-steps/s, 4000-particle FCC LJ NVE on 1 MI355X", "value":
+            out["fp64"]["particle_steps_per_s"], "unit": "particle-steps/s", "n_gpus": 1, "steps": 100,
+            "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "fcc4000_rho0.5_rc2.5_skin0.3_dt0.005", "graphs": True}, "paths": out}
+
+
+def workload_medium(B, torch, args):
+    """1,048,576 particles (64^3 FCC cells, L = 128, seed 2): 1000 steps, FP64 and
+    FP32-mixed side by side."""
+    from paper_1210_3450_amd import inputs
+    w = inputs.medium_1m()
+    out = {}
+    for name, prec in (("fp64", B.MD_PREC_FP64), ("fp32_mixed", B.MD_PREC_FP32_MIXED)):
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            ctx = B.Context(B.make_params(w.n, w.box, precision=prec, flags=B.MD_F_GRAPH), stream=stream)
+            ctx.set_state(w.pos, w.vel)
+            ctx.autotune(args.tune_cache)
+            ctx.step(args.warmup)
+            ms = timed_steps(ctx, torch, stream, 1000, 100)
+            ke, pe = ctx.energy_series()
+            st = ctx.stats()
+            ctx.close()
+        out[name] = {"ms_per_step": ms / 1000, "particle_steps_per_s": w.n * 1000 / (ms / 1e3),
+                     "threads_per_key": st["threads_per_key"], "rebuilds": st["rebuilds"],
+                     "drift_1000_steps": drift_stats(ke[:, 0], pe[:, 0], w.n, w.dt, 100)}
+    return {"metric": "particle-steps/s, 1M LJ, FP32-mixed vs FP64 on 1 MI355X",
+            "value": out["fp32_mixed"]["particle_steps_per_s"], "unit": "particle-steps/s", "n_gpus": 1,
+            "steps": 1000, "higher_is_better": True, "dtype": "f32 pair forces / f64 state", "data": "synthetic",
+            "config": {"workload": "fcc1M_rho0.5_rc2.5_skin0.3_dt0.005", "graphs": True}, "paths": out}
+
+
+def workload_cavitation(B, torch, args):
+    """Cavitation-style box: 128^3 simple-cubic sites at density 0.7 (2,097,152
+    particles, rc = 3.0, seed 4); equilibrated at T = 0.9 by velocity rescaling every
+    10 steps; all lengths expanded by 1.1 (density 0.526); 5000 NVE steps."""
+    from paper_1210_3450_amd import inputs
+    w = inputs.cavitation_liquid(n_side=args.cav_side)
+    res = {}
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        ctx = B.Context(B.make_params(w.n, w.box, rc=w.rc, skin=w.skin, dt=w.dt,
+                                      precision=B.MD_PREC_FP32_MIXED, flags=B.MD_F_GRAPH), stream=stream)
+        ctx.set_state(w.pos, w.vel)
+        t0 = time.time()
+        for _ in range(args.cav_equil // 10):
+            ctx.step(10)
+            ke, _ = ctx.energy()
+            T = 2.0 * ke / (3 * w.n - 3)
+            ctx.scale_velocities(math.sqrt(w.T / T))
+        ke, pe = ctx.energy()
+        res["equilibration"] = {"steps": args.cav_equil, "T_end": 2.0 * ke / (3 * w.n - 3),
+                                "pe_per_particle": pe / w.n, "wall_s": time.time() - t0}
+        ctx.rescale_box(1.1)
+        ke1, pe1 = ctx.energy()
+        res["after_expansion"] = {"box": w.box[0] * 1.1, "density": w.n / (w.box[0] * 1.1) ** 3,
+                                  "T": 2.0 * ke1 / (3 * w.n - 3), "pe_per_particle": pe1 / w.n,
+                                  "ke_unchanged": bool(abs(ke1 - ke) <= 1e-9 * abs(ke))}
+        p0, v0 = ctx.get_state()
+        hist = {"0": list_histogram(ctx)}
+        for name, prec in (("fp32_mixed", B.MD_PREC_FP32_MIXED), ("fp64", B.MD_PREC_FP64)):
+            c2 = B.Context(B.make_params(w.n, (w.box[0] * 1.1,) * 3, rc=w.rc, skin=w.skin, dt=w.dt,
+                                         precision=prec, flags=B.MD_F_GRAPH), stream=stream)
+            c2.set_state(p0, v0)
+            st0 = c2.stats()
+            ms1 = timed_steps(c2, torch, stream, 1000, 10)
+            if name == "fp32_mixed":
+                hist["1000"] = list_histogram(c2)
+            ms2 = timed_steps(c2, torch, stream, args.cav_steps - 1000, 10)
+            if name == "fp32_mixed":
+                hist[str(args.cav_steps)] = list_histogram(c2)
+            ke, pe = c2.energy_series()
+            st = c2.stats()
+            ke_end, pe_end = c2.energy()
+            c2.close()
+            res[name] = {"ms_per_step": (ms1 + ms2) / args.cav_steps,
+                         "particle_steps_per_s": w.n * args.cav_steps / ((ms1 + ms2) / 1e3),
+                         "rebuilds": st["rebuilds"] - st0["rebuilds"], "list_regrows": st["list_regrows"],
+                         "drift_%d_steps" % args.cav_steps: drift_stats(ke[:, 0], pe[:, 0], w.n, w.dt, 10),
+                         "T_end": 2.0 * ke_end / (3 * w.n - 3), "pe_per_particle_end": pe_end / w.n}
+        ctx.close()
+    res["list_length_histograms_nve_step"] = hist
+    return {"metric": "particle-steps/s, cavitation box (uneven lists), FP32-mixed on 1 MI355X",
+            "value": res["fp32_mixed"]["particle_steps_per_s"], "unit": "particle-steps/s", "n_gpus": 1,
+            "steps": args.cav_steps, "higher_is_better": True, "dtype": "f32 pair forces / f64 state",
+            "data": "synthetic", "config": {"workload": "sc%d^3_rho0.7_T0.9_rc3.0_expand1.1" % args.cav_side},
+            "results": res}
+
+
+def workload_batch(B, torch, args):
+    """256 independent boxes: N_b ~ U{2000..65536}, density ~ U[0.3, 0.8],
+    T ~ U[0.7, 1.2] (seed 5), rc = 2.5, FP32-mixed, all advanced together in captured
+    graphs after autotuning; baseline: the same boxes one at a time."""
+    from paper_1210_3450_amd import inputs
+    spec = inputs.batch_spec(args.nbox)
+    boxes = [inputs.batch_box(spec, b) for b in range(args.nbox)]
+    ntot = int(sum(p.shape[0] for p, _, _ in boxes))
+    pos = np.concatenate([p for p, _, _ in boxes])
+    vel = np.concatenate([v for _, v, _ in boxes])
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        params = [B.make_params(p.shape[0], L, precision=B.MD_PREC_FP32_MIXED, flags=B.MD_F_GRAPH)
+                  for p, _, L in boxes]
+        ctx = B.Context(params, stream=stream)
+        ctx.set_state(pos, vel)
+        ctx.autotune(args.tune_cache)
+        ctx.step(args.warmup)
+        ms = timed_steps(ctx, torch, stream, args.batch_steps, 100)
+        ke, pe = ctx.energy_series()
+        st = ctx.stats()
+        ctx.close()
+        # baseline: one box at a time through the single-box path, same kernels
+        t_one = 0.0
+        n_one = 0
+        for k, (p, v, L) in enumerate(boxes[: args.baseline_boxes]):
+            c1 = B.Context(B.make_params(p.shape[0], L, precision=B.MD_PREC_FP32_MIXED, flags=B.MD_F_GRAPH),
+                           stream=stream)
+            c1.set_state(p, v)
+            c1.step(5)
+            t_one += timed_steps(c1, torch, stream, args.baseline_steps)
+            n_one += p.shape[0] * args.baseline_steps
+            c1.close()
+    drift = [drift_stats(ke[:, b], pe[:, b], boxes[b][0].shape[0], 0.005, 100)["max_rel_dev"]
+             for b in range(args.nbox)]
+    return {"metric": "particle-steps/s, 256-box LJ ensemble, FP32-mixed on 1 MI355X",
+            "value": ntot * args.batch_steps / (ms / 1e3), "unit": "particle-steps/s", "n_gpus": 1,
+            "steps": args.batch_steps, "ms_per_step": ms / args.batch_steps, "higher_is_better": True,
+            "dtype": "f32 pair forces / f64 state", "data": "synthetic",
+            "config": {"workload": "ensemble%d_N2000-65536_rho0.3-0.8_T0.7-1.2" % args.nbox, "n_particles": ntot,
+                       "graphs": True, "threads_per_key": st["threads_per_key"]},
+            "one_box_at_a_time": {"particle_steps_per_s": n_one / (t_one / 1e3), "boxes": args.baseline_boxes,
+                                  "steps_each": args.baseline_steps},
+            "rebuilds": st["rebuilds"], "max_rel_energy_dev_over_boxes": float(max(drift))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,6 +292,19 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--workload", default="fcc32m",
+                    choices=["fcc32m", "fcc4000", "fcc1m", "cavitation", "batch256"])
+    ap.add_argument("--drift-steps", type=int, default=10000)
+    ap.add_argument("--cav-side", type=int, default=128)
+    ap.add_argument("--cav-equil", type=int, default=2000)
+    ap.add_argument("--cav-steps", type=int, default=5000)
+    ap.add_argument("--nbox", type=int, default=256)
+    ap.add_argument("--batch-steps", type=int, default=1000)
+    ap.add_argument("--baseline-boxes", type=int, default=256)
+    ap.add_argument("--baseline-steps", type=int, default=100)
+    ap.add_argument("--tune-cache", default=None)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the path has no multi-GPU form in this build "
@@ -117,6 +316,20 @@ def main():
     from paper_1210_3450_amd import inputs
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    if args.workload != "fcc32m":
+        if args.tune_cache is None:
+            import tempfile
+            args.tune_cache = os.path.join(tempfile.gettempdir(), "mdgpu_tune_%d.txt" % os.getpid())
+        fn = {"fcc4000": workload_small, "fcc1m": workload_medium, "cavitation": workload_cavitation,
+              "batch256": workload_batch}[args.workload]
+        print(json.dumps(fn(B, torch, args)), flush=True)
+        return
     w = inputs.fcc_workload("fcc%d^3_rho0.5" % args.ncell, args.ncell, seed=3, nsteps=args.steps)
     print("bench: %s, N = %d, L = %g, %d warm-up + %d timed steps" % (w.name, w.n, w.box[0], args.warmup,
                                                                        args.steps), file=sys.stderr, flush=True)

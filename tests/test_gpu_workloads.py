@@ -1,0 +1,120 @@
+"""GPU workload checks against the FP64 oracle: energy drift of the 4000-particle
+NVE run, the cavitation protocol (uneven lists after expansion) at reduced size,
+and the 1M-particle force error at checkpoints of each path's own trajectory.
+Measured figures are printed (pytest -s) for the design notes."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1210_3450_amd import inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def B():
+    from paper_1210_3450_amd import binding
+    return binding
+
+
+def _maxdev(ke, pe):
+    E = np.asarray(ke) + np.asarray(pe)
+    return float(np.abs(E - E[0]).max() / abs(E[0]))
+
+
+def test_small_nve_energy_drift_matches_oracle():
+    """2000 steps (t = 10 tau) at N = 4000: the GPU FP64 energy series follows the
+    oracle's while the trajectories agree, and all three paths keep the energy
+    bounded at the same level (Eq. 1 makes V and F continuous at rc)."""
+    b = B()
+    w = inputs.small_nve()
+    steps, every = 2000, 10
+    r = oracle.run(w.pos, w.vel, w.box, steps, energy_every=every)
+    dev = {"oracle": _maxdev(r.ke, r.pe)}
+    series = {}
+    for name, prec in (("fp64", 0), ("fp32_mixed", 1)):
+        with b.Context(b.make_params(w.n, w.box, precision=prec, flags=b.MD_F_GRAPH)) as c:
+            c.set_state(w.pos, w.vel)
+            c.step(steps, every)
+            ke, pe = c.energy_series()
+        series[name] = (ke[:, 0], pe[:, 0])
+        dev[name] = _maxdev(ke[:, 0], pe[:, 0])
+    print("max |E(t)-E(0)|/|E(0)| over %d steps:" % steps, dev)
+    E64 = series["fp64"][0] + series["fp64"][1]
+    Er = r.ke + r.pe
+    np.testing.assert_allclose(E64[:20], Er[:20], rtol=1e-9)  # first 200 steps: same trajectory
+    for k in ("fp64", "fp32_mixed"):
+        assert dev[k] < 5e-3
+        assert dev[k] < 3.0 * dev["oracle"] + 1e-5
+
+
+def test_cavitation_protocol_reduced_size():
+    """24^3 simple-cubic sites at density 0.7 (13,824 particles, rc = 3.0):
+    equilibrate at T = 0.9 by rescaling, expand every length by 1.1, run NVE.
+    Neighbour sets stay bit-exact and FP32-mixed forces within 1e-5 on the
+    expanded, uneven state; energy stays bounded."""
+    b = B()
+    w = inputs.cavitation_liquid(n_side=24)
+    p = b.make_params(w.n, w.box, rc=3.0, precision=b.MD_PREC_FP32_MIXED, flags=b.MD_F_GRAPH)
+    with b.Context(p) as c:
+        c.set_state(w.pos, w.vel)
+        for _ in range(30):
+            c.step(10)
+            ke, _ = c.energy()
+            c.scale_velocities(math.sqrt(0.9 / (2.0 * ke / (3 * w.n - 3))))
+        ke0, _ = c.energy()
+        c.rescale_box(1.1)
+        ke1, _ = c.energy()
+        assert ke1 == pytest.approx(ke0, rel=1e-12)  # expansion keeps the momenta
+        c.step(400, 10)
+        kes, pes = c.energy_series()
+        q, _ = c.get_state()
+        c.build_neighbors()
+        kp, pl = c.get_neighbors()
+        F = c.compute_forces().cpu().numpy()
+    L = w.box[0] * 1.1
+    q = q.cpu().numpy()
+    kpr, plr = oracle.neighbors(q, L, 3.3)
+    np.testing.assert_array_equal(kp.cpu().numpy(), kpr)
+    np.testing.assert_array_equal(pl.cpu().numpy(), plr)
+    cnt = np.diff(kpr)
+    print("list lengths after expansion: mean %.1f std %.1f min %d max %d" % (cnt.mean(), cnt.std(), cnt.min(),
+                                                                               cnt.max()))
+    Fr, _, A = oracle.forces(q, L, 3.0, 0.3)
+    err = (np.linalg.norm(F - Fr, axis=1) / A).max()
+    print("FP32-mixed normalised force error on the expanded state: %.3e" % err)
+    assert err <= 1e-5
+    assert _maxdev(kes[:, 0], pes[:, 0]) < 1e-2
+
+
+def test_fcc1m_force_error_at_checkpoints():
+    """1,048,576 particles, each path on its own trajectory: normalised force error
+    against the oracle at steps 0, 100, 500 and 1000."""
+    b = B()
+    w = inputs.medium_1m()
+    report = {}
+    for name, prec, tol in (("fp64", 0, 1e-12), ("fp32_mixed", 1, 1e-5)):
+        errs = []
+        with b.Context(b.make_params(w.n, w.box, precision=prec, flags=b.MD_F_GRAPH)) as c:
+            c.set_state(w.pos, w.vel)
+            done = 0
+            for chk in (0, 100, 500, 1000):
+                c.step(chk - done)
+                done = chk
+                q, _ = c.get_state()
+                F = c.compute_forces().cpu().numpy()
+                Fr, _, A = oracle.forces(q.cpu().numpy(), w.box, 2.5, 0.3)
+                e = np.linalg.norm(F - Fr, axis=1) / A
+                top = e[np.linalg.norm(Fr, axis=1) > np.median(np.linalg.norm(Fr, axis=1))]
+                errs.append((chk, float(e.max()), float(np.percentile(top, 99))))
+                assert e.max() <= tol
+        report[name] = errs
+    print("force error (step, max normalised, p99 over |F| above median):", report)
