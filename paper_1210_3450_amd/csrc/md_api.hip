@@ -295,7 +295,7 @@ void drop_graphs(md_ctx* c) {
 md_status alloc_list(md_ctx* c, int32_t cap) {
     drop_graphs(c);
     const int tpk = c->P.tpk;
-    cap = (cap + 4 * tpk - 1) / (4 * tpk) * (4 * tpk);  // rows = cap / tpk is a multiple of 4
+    cap = (cap + 8 * tpk - 1) / (8 * tpk) * (8 * tpk);  // rows = cap / tpk is a multiple of 8
     dfree(c->D.list);
     const int64_t entries = (int64_t)c->nslot * cap;
     md_status s = dalloc(c, &c->D.list, (size_t)entries);
@@ -540,9 +540,13 @@ md_status enqueue_mid_steps(md_ctx* c, int n) {
 }
 
 md_status status_from_states(md_ctx* c) {
-    for (int b = 0; b < c->nbox; ++b)
-        if (c->st_h[b].err)
+    for (int b = 0; b < c->nbox; ++b) {
+        if (c->st_h[b].err & 1)
             return fail(c, MD_ENUMERIC, "box %d: a position is not finite or lies outside [-L, 2L)", b);
+        if (c->st_h[b].err & 2)
+            return fail(c, MD_ENUMERIC, "box %d: a cell holds more than %d particles (overlapping particles?)", b,
+                        kMaxCellCount);
+    }
     return MD_OK;
 }
 

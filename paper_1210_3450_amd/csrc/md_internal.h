@@ -5,8 +5,9 @@
 //   slots     particles live in "slots" sorted by cell; box b owns slots
 //             [slot_off, slot_off + nslot), nslot = npart rounded up to 64, so a
 //             64-lane wavefront never spans two boxes.  Padding slots are idle.
-//   q[2]      double4 positions (x, y, z, unused), ping-pong: the force kernel
-//             gathers partners from q[sq] and writes drifted positions to q[1-sq].
+//   q[2]      Pos records (x, y, z in FP64, the packed cell coordinates of the last
+//             build, the list length), 32 bytes, ping-pong: the force kernel gathers
+//             partners from q[sq] and writes drifted positions to q[1-sq].
 //   u[2]      int4 cell-relative positions in fixed point (FP32-mixed path),
 //             ping-pong with q: u = rint((x - (c + 1/2) cs) * 2^28 / cs) per axis,
 //             c = the particle's cell at the last build.  A pair's separation
@@ -15,15 +16,14 @@
 //   v*[2]     float64 velocity components (SoA), ping-pong only across a re-sort.
 //   id[2]     caller index of the particle in each slot.
 //   cellc[2]  packed cell coordinates at the last build: cx | cy << 10 | cz << 20.
-//   list      wave-blocked ELL pair list.  A list wave holds K = 64 / tpk keys and
-//             rows * 64 words (rows = cap / tpk, a multiple of 4).  Key k's entry e
-//             belongs to lane ln = (k % K) * tpk + e % tpk as that lane's entry
-//             m = e / tpk; each lane's entries sit in 4-word chunks, chunk c of all
-//             64 lanes side by side, so one 16-byte load per lane reads 4 entries.
-//             Entry = partner slot (27 bits) | shift code << 27.
-//             Shift code: FP64 path = periodic image r in {-1,0,1}^3 as
-//             (rz+1)*9 + (ry+1)*3 + (rx+1); FP32-mixed path = stencil offset o of
-//             the partner's cell, same encoding.
+//   list      wave-blocked ELL pair list of 16-bit entries.  A list wave holds
+//             K = 64 / tpk keys and rows * 64 entries (rows = cap / tpk, a multiple
+//             of 8).  Key k's entry e belongs to lane ln = (k % K) * tpk + e % tpk as
+//             that lane's entry m = e / tpk; each lane's entries sit in 8-entry
+//             chunks, chunk c of all 64 lanes side by side, so one 16-byte load per
+//             lane reads 8 entries.  Entry = s << 11 | offset: s = stencil cell of
+//             the partner (z-major over offsets (ox, oy, oz) in {-1,0,1}^3, 0..26)
+//             and the partner's rank within that cell (cells hold at most 2048).
 //   cells     per box ncell counters and starts, box ranges aligned to 1024-cell tiles.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -40,8 +40,19 @@ constexpr int kMaxSeries = 4096;         // energy samples kept per box
 constexpr int kMaxCellsPerAxis = 1023;   // 10-bit packed cell coordinates
 constexpr int kUnitBits = 28;            // fixed-point units per cell side: 2^28
 constexpr int kUnitClamp = 1 << 29;      // |u| bound (two cell sides): pair sums stay in int32
+constexpr int kOffBits = 11;             // list entry: partner rank within its cell
+constexpr int kMaxCellCount = 1 << kOffBits;
 constexpr int kStripes = 1024;           // slots per box for per-step maxima
 constexpr int kStripeStride = 16;        // 128 bytes between slots
+
+// Position record of one slot.  cc and cnt ride in the 8 bytes a double4
+// would leave unused, so streaming a key's position also brings its cell and
+// its list length.
+struct __align__(32) Pos {
+    double x, y, z;
+    uint32_t cc;   // cx | cy << 10 | cz << 20 at the last build
+    int32_t cnt;   // list length at the last build
+};
 
 struct BoxGeom {
     double L[3];
@@ -66,7 +77,7 @@ struct BoxState {
     int32_t rebuild;           // list build pending for this box
     int32_t sq;                // current q / u buffer
     int32_t sp;                // current v / id / cellc buffer
-    int32_t err;               // bit 0: bad position at binning
+    int32_t err;               // bit 0: bad position at binning; bit 1: a cell over 2048 particles
     int32_t need;              // longest list seen at any build (for overflow detection)
     int32_t built;             // builds done
     unsigned long long missed; // verifier: pairs within rc absent from the list
@@ -78,9 +89,9 @@ struct BoxState {
 struct Params {
     double rc2, rl2, c2, c0, dt, h, mass, skin;  // h = dt / (2 m)
     float rc2f, c2f, c0f, padf;
-    int32_t cap;        // list entries per key (multiple of tpk)
+    int32_t cap;        // list entries per key (multiple of 8 * tpk)
     int32_t tpk;        // lanes per key
-    int32_t rows;       // cap / tpk
+    int32_t rows;       // cap / tpk, a multiple of 8
     int32_t policy;     // MD_REBUILD_*
     int32_t nbox;
     int32_t nwave;      // 64-slot wavefronts over all boxes
@@ -96,7 +107,7 @@ struct Dev {
     int32_t* any;        // nonzero while some box has a list build pending this step
     int32_t* wave_box;   // box of each 64-slot wavefront
     int32_t* tile_box;   // box of each cell tile
-    double4* q[2];
+    Pos* q[2];
     int4* u[2];
     double* vx[2];
     double* vy[2];
@@ -108,7 +119,7 @@ struct Dev {
     double* fy;
     double* fz;
     int32_t* cnt;        // list length per slot
-    uint32_t* list;
+    uint16_t* list;
     int32_t* cell_tmp;   // cell of each (old) slot at binning
     int32_t* ticket;     // arrival rank within the cell at binning
     int32_t* perm;       // new slot -> old slot

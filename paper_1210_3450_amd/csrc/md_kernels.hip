@@ -83,7 +83,17 @@ __device__ __forceinline__ int to_units(double x, int c, double cs, double ucs) 
     return (int)t;
 }
 
-__device__ __forceinline__ int4 units3(const double4& x, uint32_t cc, const BoxGeom& g) {
+__device__ __forceinline__ Pos make_pos(double x, double y, double z, uint32_t cc, int32_t cnt) {
+    Pos r;
+    r.x = x;
+    r.y = y;
+    r.z = z;
+    r.cc = cc;
+    r.cnt = cnt;
+    return r;
+}
+
+__device__ __forceinline__ int4 units3(const Pos& x, uint32_t cc, const BoxGeom& g) {
     return make_int4(to_units(x.x, cc & 1023, g.cs[0], g.ucs[0]), to_units(x.y, (cc >> 10) & 1023, g.cs[1], g.ucs[1]),
                      to_units(x.z, cc >> 20, g.cs[2], g.ucs[2]), 0);
 }
@@ -116,7 +126,7 @@ __global__ __launch_bounds__(kBlock) void k_set_state(Dev d, Params p, const dou
         const int k = s - g.slot_off;
         if (k >= g.npart) continue;
         const int64_t i = (int64_t)g.id_off + k;
-        d.q[0][s] = make_double4(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], 0.0);
+        d.q[0][s] = make_pos(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], 0u, 0);
         d.vx[0][s] = vel[3 * i];
         d.vy[0][s] = vel[3 * i + 1];
         d.vz[0][s] = vel[3 * i + 2];
@@ -135,7 +145,7 @@ __global__ __launch_bounds__(kBlock) void k_get_state(Dev d, Params p, double* _
         const int sq = d.st[b].sq, sp = d.st[b].sp;
         const int64_t i = d.id[sp][s];
         if (pos) {
-            const double4 x = d.q[sq][s];
+            const Pos x = d.q[sq][s];
             pos[3 * i] = x.x;
             pos[3 * i + 1] = x.y;
             pos[3 * i + 2] = x.z;
@@ -191,20 +201,42 @@ __global__ __launch_bounds__(kBlock) void k_list_counts(Dev d, Params p, int64_t
 template <int TPK>
 __device__ __forceinline__ uint32_t list_off(int e) {
     const int m = e / TPK;
-    return ((uint32_t)(m & ~3) << 6) + (uint32_t)((e % TPK) << 2) + (uint32_t)(m & 3);
+    return ((uint32_t)(m & ~7) << 6) + (uint32_t)((e % TPK) << 3) + (uint32_t)(m & 7);
 }
 
-// Address of entry e of key slot s in the chunked wave-blocked list: a list wave
-// of K = 64 / tpk keys owns rows * 64 words; lane ln = (s % K) * tpk + e % tpk
-// keeps its per-lane entries m = e / tpk in 4-word chunks, chunk c of every lane
-// stored side by side (one 16-byte load per lane reads 4 entries).
+// Index of entry e of key slot s in the chunked wave-blocked list: a list wave
+// of K = 64 / tpk keys owns rows * 64 entries; lane ln = (s % K) * tpk + e % tpk
+// keeps its per-lane entries m = e / tpk in 8-entry chunks, chunk c of every
+// lane stored side by side (one 16-byte load per lane reads 8 entries).
 __device__ __forceinline__ size_t list_addr(int s, int e, int tpk, int rows) {
     const int K = kWave / tpk;
     const int lw = s / K;
     const int kl = s - lw * K;
     const int m = e / tpk;
     const int ln = kl * tpk + (e - m * tpk);
-    return ((size_t)lw * rows + (m & ~3)) * kWave + ln * 4 + (m & 3);
+    return ((size_t)lw * rows + (m & ~7)) * kWave + ln * 8 + (m & 7);
+}
+
+// Stencil cell s (0..26, z-major over offsets in {-1,0,1}^3) of the cell with
+// packed coordinates cc: its global cell index, and the periodic image r of the
+// partner's position as code (rz+1)*9 + (ry+1)*3 + (rx+1), where r = +1 on an
+// axis means the oracle's minimum image subtracts +L there.
+__device__ __forceinline__ int stencil_cell(uint32_t cc, int s, const BoxGeom& g, uint32_t* img) {
+    int x = (int)(cc & 1023) + (s % 3 - 1);
+    int y = (int)((cc >> 10) & 1023) + ((s / 3) % 3 - 1);
+    int z = (int)(cc >> 20) + (s / 9 - 1);
+    int rx = 0, ry = 0, rz = 0;
+    if (x < 0) { x += g.n[0]; rx = 1; } else if (x >= g.n[0]) { x -= g.n[0]; rx = -1; }
+    if (y < 0) { y += g.n[1]; ry = 1; } else if (y >= g.n[1]) { y -= g.n[1]; ry = -1; }
+    if (z < 0) { z += g.n[2]; rz = 1; } else if (z >= g.n[2]) { z -= g.n[2]; rz = -1; }
+    *img = (uint32_t)((rz + 1) * 9 + (ry + 1) * 3 + (rx + 1));
+    return g.cell_off + (z * g.n[1] + y) * g.n[0] + x;
+}
+
+// Partner slot of a 16-bit list entry of a key whose cell is cc.
+__device__ __forceinline__ int entry_slot(const Dev& d, uint32_t cc, uint32_t e, const BoxGeom& g) {
+    uint32_t img;
+    return d.cell_start[stencil_cell(cc, (int)(e >> kOffBits), g, &img)] + (int)(e & (kMaxCellCount - 1));
 }
 
 __global__ __launch_bounds__(kBlock) void k_list_export(Dev d, Params p, const int64_t* __restrict__ key_ptr,
@@ -219,10 +251,9 @@ __global__ __launch_bounds__(kBlock) void k_list_export(Dev d, Params p, const i
         const int32_t* id = d.id[sp];
         const int64_t base = key_ptr[id[s]];
         const int n = d.cnt[s];
-        for (int e = 0; e < n; ++e) {
-            const uint32_t ent = d.list[list_addr(s, e, p.tpk, p.rows)];
-            partners[base + e] = id[ent & kIdxMask];
-        }
+        const uint32_t cc = d.q[d.st[b].sq][s].cc;
+        for (int e = 0; e < n; ++e)
+            partners[base + e] = id[entry_slot(d, cc, d.list[list_addr(s, e, p.tpk, p.rows)], g)];
         for (int a = 1; a < n; ++a) {  // ascending, insertion sort
             const int32_t x = partners[base + a];
             int c = a - 1;
@@ -358,7 +389,7 @@ __global__ __launch_bounds__(kBlock) void k_bin(Dev d, Params p) {
         int cid = -1;
         if (valid) {
             const int sq = d.st[b].sq;
-            double4 x = d.q[sq][s];
+            Pos x = d.q[sq][s];
             bool bad = false;
             const int cx = bin_axis(x.x, g.L[0], g.inv[0], g.n[0], bad);
             const int cy = bin_axis(x.y, g.L[1], g.inv[1], g.n[1], bad);
@@ -483,8 +514,7 @@ __global__ __launch_bounds__(kBlock) void k_permute(Dev d, Params p) {
         if (s - g.slot_off >= g.npart) continue;
         const int sq = st.sq, sp = st.sp, nq = sq ^ 1, np = sp ^ 1;
         const int o = d.perm[s];
-        const double4 x = d.q[sq][o];
-        d.q[nq][s] = x;
+        Pos x = d.q[sq][o];
         d.vx[np][s] = d.vx[sp][o];
         d.vy[np][s] = d.vy[sp][o];
         d.vz[np][s] = d.vz[sp][o];
@@ -493,9 +523,12 @@ __global__ __launch_bounds__(kBlock) void k_permute(Dev d, Params p) {
         const int cx = cid % g.n[0], tq = cid / g.n[0];
         const int cy = tq % g.n[1], cz = tq / g.n[1];
         const uint32_t cc = (uint32_t)cx | ((uint32_t)cy << 10) | ((uint32_t)cz << 20);
+        x.cc = cc;
+        x.cnt = 0;
+        d.q[nq][s] = x;
         d.cellc[np][s] = cc;
         if (p.precision == MD_PREC_FP32_MIXED) d.u[nq][s] = units3(x, cc, g);
-        if (d.qb) d.qb[s] = x;
+        if (d.qb) d.qb[s] = make_double4(x.x, x.y, x.z, 0.0);
     }
 }
 
@@ -505,8 +538,8 @@ __global__ __launch_bounds__(kBlock) void k_permute(Dev d, Params p) {
 // d = (x_j - x_i) - L * rint((x_j - x_i) / L) per axis, where the subtracted
 // image term is known from the stencil, then dx*dx + dy*dy + dz*dz left to
 // right.  No contraction, so the accept decision matches the CPU bit for bit.
-__device__ __forceinline__ double dist2_exact(const double4& qi, const double4& qj, double shx, double shy,
-                                              double shz) {
+template <class A, class B>
+__device__ __forceinline__ double dist2_exact(const A& qi, const B& qj, double shx, double shy, double shz) {
 #pragma clang fp contract(off)
     const double dx = (qj.x - qi.x) - shx;
     const double dy = (qj.y - qi.y) - shy;
@@ -514,7 +547,8 @@ __device__ __forceinline__ double dist2_exact(const double4& qi, const double4& 
     return dx * dx + dy * dy + dz * dz;
 }
 // The same value when every image term is zero (t - 0 is t exactly).
-__device__ __forceinline__ double dist2_exact0(const double4& qi, const double4& qj) {
+template <class A, class B>
+__device__ __forceinline__ double dist2_exact0(const A& qi, const B& qj) {
 #pragma clang fp contract(off)
     const double dx = qj.x - qi.x;
     const double dy = qj.y - qi.y;
@@ -564,7 +598,6 @@ __global__ __launch_bounds__(kBlock) void k_list(Dev d, Params p) {
     if (!*d.any) return;  // no box rebuilds this step
     const int l = lane_id();
     const int ncells = p.ntile * kTile;
-    const bool fp64 = p.precision == MD_PREC_FP64;
     const double nan = __longlong_as_double(0x7ff8000000000000ll);
     const double rl2 = p.rl2;
     const int cap = p.cap, rows = p.rows;
@@ -579,11 +612,10 @@ __global__ __launch_bounds__(kBlock) void k_list(Dev d, Params p) {
         const int m = __builtin_amdgcn_readfirstlane(d.cell_cnt[c]);
         if (m == 0) continue;
         const int cs0 = __builtin_amdgcn_readfirstlane(d.cell_start[c]);
-        const double4* __restrict__ q = d.q[__builtin_amdgcn_readfirstlane(st.sq)];
+        Pos* __restrict__ q = d.q[__builtin_amdgcn_readfirstlane(st.sq)];
         const int cx = local % g.n[0], cy = (local / g.n[0]) % g.n[1], cz = local / (g.n[0] * g.n[1]);
-        // stencil cell s = lane s < 27: start, count, image term and shift code
+        // stencil cell s = lane s < 27: start, count and image term
         int start = 0, cnt = 0;
-        uint32_t code = 0;
         double shx = 0.0, shy = 0.0, shz = 0.0;
         if (l < 27) {
             const int ox = l % 3 - 1, oy = (l / 3) % 3 - 1, oz = l / 9 - 1;
@@ -594,7 +626,7 @@ __global__ __launch_bounds__(kBlock) void k_list(Dev d, Params p) {
             const int nc = g.cell_off + (z * g.n[1] + y) * g.n[0] + x;
             start = d.cell_start[nc];
             cnt = d.cell_cnt[nc];
-            code = (fp64 ? (uint32_t)((rz + 1) * 9 + (ry + 1) * 3 + (rx + 1)) : (uint32_t)l) << kIdxBits;
+            if (cnt > kMaxCellCount) atomicOr(&d.st[b].err, 2);  // ranks would not fit 11 bits
         }
         const int incl = wave_incl_scan(cnt);
         const int pre = incl - cnt;
@@ -616,9 +648,9 @@ __global__ __launch_bounds__(kBlock) void k_list(Dev d, Params p) {
                 // shuffles run on every lane: a bpermute from an inactive lane reads 0
                 const int st_sc = __shfl(start, sc), pre_sc = __shfl(pre, sc);
                 const int j = valid ? st_sc + ci - pre_sc : -1;
-                const uint32_t ent = (uint32_t)j | (uint32_t)__shfl((int)code, sc);
+                const uint16_t ent = (uint16_t)((sc << kOffBits) | ((ci - pre_sc) & (kMaxCellCount - 1)));
                 const double sx = __shfl(shx, sc), sy = __shfl(shy, sc), sz = __shfl(shz, sc);
-                double4 qj = q[valid ? j : cs0];
+                Pos qj = q[valid ? j : cs0];
                 if (!valid) qj.x = nan;  // NaN distance: never accepted
                 const bool wrapped = __ballot(valid && (sx != 0.0 || sy != 0.0 || sz != 0.0)) != 0ull;
                 // The candidate loads must land before the key loop: a wait placed
@@ -651,7 +683,11 @@ __global__ __launch_bounds__(kBlock) void k_list(Dev d, Params p) {
                     }
                 }
             }
-            if (l < mb) d.cnt[cs0 + kb + l] = n_own < cap ? n_own : cap;
+            if (l < mb) {
+                const int nk = n_own < cap ? n_own : cap;
+                d.cnt[cs0 + kb + l] = nk;
+                q[cs0 + kb + l].cnt = nk;
+            }
             need = max(need, wave_max_i(n_own));
         }
         if (l == 0) atomicMax(&d.tile_need[t], need);
@@ -701,19 +737,25 @@ __device__ __forceinline__ void stripe_put(unsigned long long* base, int b, int 
 
 // Algorithm 1 on the GPU.  PREC: MD_PREC_FP64 or MD_PREC_FP32_MIXED.
 // MODE: kForceOnly / kForceEnd / kForceMid.  ENERGY: per-wave KE and PE partials.
-// Each lane reads 4 list entries per 16-byte load and keeps 8 partner gathers in
-// flight (Algorithm 1's unrolling for latency hiding, in GPU form).
+// Each lane reads 8 list entries per 16-byte load and keeps 8 partner gathers in
+// flight (Algorithm 1's unrolling for latency hiding, in GPU form).  A list
+// entry names a stencil cell and a rank in it; the wavefront first tabulates, in
+// LDS, the 27 stencil-cell starts of each distinct cell its keys live in.
+constexpr int kHomeMax = 16;  // distinct key cells per wavefront served from LDS
+
 template <int PREC, int MODE, int TPK, bool ENERGY>
 __global__ __launch_bounds__(kBlock) void k_force(Dev d, Params p) {
     constexpr int K = kWave / TPK;
-    constexpr int U = 8;  // entries per iteration
+    constexpr int U = 8;  // entries per iteration (one 16-byte chunk)
     using V4 = typename ShiftT<PREC>::V;
     __shared__ V4 shift[kBlock / kWave][27];
+    __shared__ uint32_t home_cc[kBlock / kWave][kWave];
+    __shared__ uint32_t tab[kBlock / kWave][kHomeMax * 27];
     const int l = lane_id(), wib = threadIdx.x >> 6, sub = l % TPK;
     const int lw = xcd_block(blockIdx.x, gridDim.x) * 4 + wib;
     const int nlw = p.nwave * TPK;
     const bool wave_ok = lw < nlw;
-    const int b = wave_ok ? d.wave_box[(lw * K) >> 6] : 0;
+    const int b = __builtin_amdgcn_readfirstlane(wave_ok ? d.wave_box[(lw * K) >> 6] : 0);
     if (l < 27) {
         if constexpr (PREC == MD_PREC_FP64)
             shift[wib][l] = d.dshift[b * 27 + l];
@@ -723,39 +765,81 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Params p) {
     __syncthreads();
     if (!wave_ok) return;
 
-    const BoxGeom& g = d.geom[b];
+    const BoxGeom& g = d.geom[b];  // b is uniform: scalar loads
     const int sq = d.st[b].sq, sp = d.st[b].sp;
     const int key = lw * K + l / TPK;
     const bool active = key - g.slot_off < g.npart;
+    const Pos qi = d.q[sq][active ? key : g.slot_off];
+    const uint32_t cc = active ? qi.cc : 0xffffffffu;
+
+    // distinct cells of this wavefront's keys (keys are sorted by cell), and for
+    // each the start slot and image code of its 27 stencil cells
+    const uint32_t cprev = __shfl_up(cc, TPK);
+    const bool head = active && sub == 0 && (l < TPK || cprev != cc);
+    const unsigned long long hm = __ballot(head);
+    const int nhome = __popcll(hm);
+    const int h = __popcll(hm & (l == 63 ? ~0ull : ((2ull << l) - 1ull))) - 1;
+    const bool tabled = nhome <= kHomeMax;  // uniform
+    if (tabled) {
+        if (head) home_cc[wib][h] = cc;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int idx = l; idx < nhome * 27; idx += kWave) {
+            const int hh = idx / 27, s = idx - hh * 27;
+            uint32_t img;
+            const int nc = stencil_cell(home_cc[wib][hh], s, g, &img);
+            tab[wib][idx] = (uint32_t)d.cell_start[nc] | (img << kIdxBits);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+
     double Fx = 0.0, Fy = 0.0, Fz = 0.0, pe = 0.0;
-    if (active) {
-        const int n_i = d.cnt[key];
+    // The pair loop, instantiated twice so the choice between the LDS table and
+    // direct lookups is made once per wavefront, outside the loop.
+    auto pair_loop = [&](auto tabled_c) {
+        constexpr bool TB = decltype(tabled_c)::value;
+        const int n_i = qi.cnt;
         const int nl = n_i > sub ? (n_i - sub + TPK - 1) / TPK : 0;  // this lane's entries
         const uint4* __restrict__ l4 = reinterpret_cast<const uint4*>(d.list + (size_t)lw * p.rows * kWave) + l;
-        const uint32_t self = (uint32_t)key | (13u << kIdxBits);  // padding: zero shift, masked below
+        const uint32_t* __restrict__ tb = tab[wib] + h * 27;
+        // slot (27 bits) | image code << 27 of stencil cell s of this key's cell
+        auto lookup = [&](uint32_t s) -> uint32_t {
+            if constexpr (TB) {
+                return tb[s];
+            } else {
+                uint32_t img;
+                const int nc = stencil_cell(cc, (int)s, g, &img);
+                return (uint32_t)d.cell_start[nc] | (img << kIdxBits);
+            }
+        };
         if constexpr (PREC == MD_PREC_FP64) {
-            const double4* __restrict__ q = d.q[sq];
-            const double4 qi = q[key];
+            const Pos* __restrict__ q = d.q[sq];
             const double rc2 = p.rc2, c2x8 = 8.0 * p.c2;
+            uint4 raw_next = nl > 0 ? l4[0] : make_uint4(0u, 0u, 0u, 0u);
             for (int m0 = 0; m0 < nl; m0 += U) {
-                uint32_t e[U];
-                const uint4 a0 = l4[(size_t)(m0 >> 2) * kWave];
-                e[0] = a0.x; e[1] = a0.y; e[2] = a0.z; e[3] = a0.w;
-                if (m0 + 4 < nl) {
-                    const uint4 a1 = l4[(size_t)((m0 >> 2) + 1) * kWave];
-                    e[4] = a1.x; e[5] = a1.y; e[6] = a1.z; e[7] = a1.w;
-                } else {
-                    e[4] = e[5] = e[6] = e[7] = self;
-                }
-#pragma unroll
-                for (int k = 0; k < U; ++k)
-                    if (m0 + k >= nl) e[k] = self;
-                double4 qj[U];
-#pragma unroll
-                for (int k = 0; k < U; ++k) qj[k] = q[e[k] & kIdxMask];
+                const uint4 raw = raw_next;
+                const uint32_t w[4] = {raw.x, raw.y, raw.z, raw.w};
+                uint32_t js[U], img[U];
 #pragma unroll
                 for (int k = 0; k < U; ++k) {
-                    const double4 sh = shift[wib][e[k] >> kIdxBits];
+                    const uint32_t e = (w[k >> 1] >> ((k & 1) * 16)) & 0xffffu;
+                    const bool ok = m0 + k < nl;  // entries past the list end are padding
+                    const uint32_t t = lookup(ok ? e >> kOffBits : 13u);
+                    js[k] = ok ? (t & kIdxMask) + (e & (kMaxCellCount - 1)) : (uint32_t)key;
+                    img[k] = ok ? t >> kIdxBits : 13u;
+                }
+                Pos qj[U];
+#pragma unroll
+                for (int k = 0; k < U; ++k) qj[k] = q[js[k]];
+                // next chunk's entries, issued after the gathers: the load counter
+                // retires in order, so this load does not delay them
+                if (m0 + U < nl) raw_next = l4[(size_t)((m0 >> 3) + 1) * kWave];
+#pragma unroll
+                for (int k = 0; k < U; ++k) {
+                    const double4 sh = shift[wib][img[k]];
                     const double dx = (qj[k].x - qi.x) - sh.x;
                     const double dy = (qj[k].y - qi.y) - sh.y;
                     const double dz = (qj[k].z - qi.z) - sh.z;
@@ -773,30 +857,30 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Params p) {
             }
         } else {
             const int4* __restrict__ u = d.u[sq];
-            const int4 ui = u[key];
+            const int4 ui = units3(qi, cc, g);  // own coordinate from the record: no extra load
             const float ux = g.usc[0], uy = g.usc[1], uz = g.usc[2];
             const float rc2 = p.rc2f, c2x8 = 8.0f * p.c2f;
             float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f, pes = 0.f;
+            uint4 raw_next = nl > 0 ? l4[0] : make_uint4(0u, 0u, 0u, 0u);
             for (int m0 = 0; m0 < nl; m0 += U) {
-                uint32_t e[U];
-                const uint4 a0 = l4[(size_t)(m0 >> 2) * kWave];
-                e[0] = a0.x; e[1] = a0.y; e[2] = a0.z; e[3] = a0.w;
-                if (m0 + 4 < nl) {
-                    const uint4 a1 = l4[(size_t)((m0 >> 2) + 1) * kWave];
-                    e[4] = a1.x; e[5] = a1.y; e[6] = a1.z; e[7] = a1.w;
-                } else {
-                    e[4] = e[5] = e[6] = e[7] = self;
-                }
+                const uint4 raw = raw_next;
+                const uint32_t w[4] = {raw.x, raw.y, raw.z, raw.w};
+                uint32_t js[U], st[U];
 #pragma unroll
-                for (int k = 0; k < U; ++k)
-                    if (m0 + k >= nl) e[k] = self;
+                for (int k = 0; k < U; ++k) {
+                    const uint32_t e = (w[k >> 1] >> ((k & 1) * 16)) & 0xffffu;
+                    const bool ok = m0 + k < nl;
+                    st[k] = ok ? e >> kOffBits : 13u;
+                    js[k] = ok ? (lookup(st[k]) & kIdxMask) + (e & (kMaxCellCount - 1)) : (uint32_t)key;
+                }
                 int4 uj[U];
 #pragma unroll
-                for (int k = 0; k < U; ++k) uj[k] = u[e[k] & kIdxMask];
+                for (int k = 0; k < U; ++k) uj[k] = u[js[k]];
+                if (m0 + U < nl) raw_next = l4[(size_t)((m0 >> 3) + 1) * kWave];
                 float bx = 0.f, by = 0.f, bz = 0.f;  // plain FP32 sum of this batch
 #pragma unroll
                 for (int k = 0; k < U; ++k) {
-                    const int4 sh = shift[wib][e[k] >> kIdxBits];
+                    const int4 sh = shift[wib][st[k]];
                     // exact integer separation, one rounding to FP32, one scaling
                     const float dx = (float)(uj[k].x - ui.x + sh.x) * ux;
                     const float dy = (float)(uj[k].y - ui.y + sh.y) * uy;
@@ -821,6 +905,12 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Params p) {
             Fz = (double)sz - (double)cz;
             pe = (double)pes;
         }
+    };
+    if (active) {
+        if (tabled)
+            pair_loop(std::true_type{});
+        else
+            pair_loop(std::false_type{});
     }
     if (TPK > 1) {
 #pragma unroll
@@ -861,10 +951,10 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Params p) {
             d.vx[sp][key] = vx;
             d.vy[sp][key] = vy;
             d.vz[sp][key] = vz;
-            const double4 x = d.q[sq][key];
-            const double4 xn = make_double4(drift(x.x, p.dt, vx), drift(x.y, p.dt, vy), drift(x.z, p.dt, vz), 0.0);
+            const Pos xn = make_pos(drift(qi.x, p.dt, vx), drift(qi.y, p.dt, vy), drift(qi.z, p.dt, vz), qi.cc,
+                                    qi.cnt);
             d.q[sq ^ 1][key] = xn;
-            if (PREC == MD_PREC_FP32_MIXED) d.u[sq ^ 1][key] = units3(xn, d.cellc[sp][key], g);
+            if (PREC == MD_PREC_FP32_MIXED) d.u[sq ^ 1][key] = units3(xn, cc, g);
             w2 = norm2(vx, vy, vz);
             if (d.qb) {
                 const double4 xb = d.qb[key];
@@ -906,10 +996,10 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(Dev d, Params p) {
             d.vx[sp][s] = vx;
             d.vy[sp][s] = vy;
             d.vz[sp][s] = vz;
-            const double4 x = d.q[sq][s];
-            const double4 xn = make_double4(drift(x.x, p.dt, vx), drift(x.y, p.dt, vy), drift(x.z, p.dt, vz), 0.0);
+            const Pos x = d.q[sq][s];
+            const Pos xn = make_pos(drift(x.x, p.dt, vx), drift(x.y, p.dt, vy), drift(x.z, p.dt, vz), x.cc, x.cnt);
             d.q[sq ^ 1][s] = xn;
-            if (p.precision == MD_PREC_FP32_MIXED) d.u[sq ^ 1][s] = units3(xn, d.cellc[sp][s], g);
+            if (p.precision == MD_PREC_FP32_MIXED) d.u[sq ^ 1][s] = units3(xn, x.cc, g);
             w2 = norm2(vx, vy, vz);
             if (d.qb) {
                 const double4 xb = d.qb[s];
@@ -970,13 +1060,13 @@ __global__ __launch_bounds__(kBlock) void k_verify(Dev d, Params p) {
         const BoxGeom& g = d.geom[b];
         const int s = w * kWave + l;
         if (s - g.slot_off >= g.npart) continue;
-        const double4* q = d.q[d.st[b].sq];
-        const double4 qi = q[s];
+        const Pos* q = d.q[d.st[b].sq];
+        const Pos qi = q[s];
         const int n = d.cnt[s];
         unsigned long long missed = 0;
         for (int j = g.slot_off; j < g.slot_off + g.npart; ++j) {
             if (j == s) continue;
-            const double4 qj = q[j];
+            const Pos qj = q[j];
             double t[3] = {qj.x - qi.x, qj.y - qi.y, qj.z - qi.z};
             double r2 = 0.0;
             for (int a = 0; a < 3; ++a) {
@@ -986,7 +1076,7 @@ __global__ __launch_bounds__(kBlock) void k_verify(Dev d, Params p) {
             if (r2 < p.rc2) {
                 bool found = false;
                 for (int e = 0; e < n && !found; ++e)
-                    found = (d.list[list_addr(s, e, p.tpk, p.rows)] & kIdxMask) == (uint32_t)j;
+                    found = entry_slot(d, qi.cc, d.list[list_addr(s, e, p.tpk, p.rows)], g) == j;
                 if (!found) ++missed;
             }
         }
@@ -1005,7 +1095,7 @@ __global__ __launch_bounds__(kBlock) void k_scale(Dev d, Params p, const double*
         const int sq = d.st[b].sq, sp = d.st[b].sp;
         if (alpha_q) {
             const double a = alpha_q[b];
-            double4 x = d.q[sq][s];
+            Pos x = d.q[sq][s];
             x.x *= a;
             x.y *= a;
             x.z *= a;

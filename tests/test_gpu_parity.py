@@ -358,7 +358,7 @@ def test_list_overflow_regrows_at_build_and_during_steps():
     # a lattice fills exactly 42 entries per key; heating it makes lists longer
     q0, v0 = inputs.fcc_positions(5, 2.0), inputs.maxwell_boltzmann(500, 3.0, 1.0, rng(11))
     r = oracle.run(q0, v0, 10.0, 120)
-    with make_ctx(q0, v0, 10.0, list_cap=48) as c:
+    with make_ctx(q0, v0, 10.0, list_cap=48, threads_per_key=1) as c:  # capacity stays 48
         c.step(120)
         pos, _ = c.get_state()
         st = c.stats()
