@@ -45,6 +45,37 @@ def pairs_within_rc_per_particle(rho, rc):
     return rho * (2.0 * math.pi / 3.0) * rc ** 3
 
 
+REBUILD_BYTES_PER_PARTICLE = 260.0  # binning 32, permute 104, list build 124 (per particle per rebuild)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_force_mixed_fcc32m_hbm_traffic.txt")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1210_3450_amd", "csrc", f) for f in ("md_kernels.hip", "md_internal.h")]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per force launch from the committed counter summary, or None when
+    the kernel sources changed since the counters were taken."""
+    try:
+        kv = {}
+        with open(TRAFFIC_FILE) as fh:
+            for line in fh:
+                parts = line.split()
+                if len(parts) == 2 and parts[0].endswith(":"):
+                    kv[parts[0][:-1]] = parts[1]
+        if kv.get("kernel_sources_sha256") != kernel_source_hash():
+            return None
+        return float(kv["hbm_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def run_gpu(B, torch, w, precision, steps, warmup, tpk=0):
     stream = torch.cuda.Stream()
     p = B.make_params(w.n, w.box, rc=w.rc, skin=w.skin, dt=w.dt, precision=precision, threads_per_key=tpk)
@@ -347,6 +378,10 @@ def main():
     force_bytes = bpp * w.n
     achieved = force_bytes / (mixed["force_ms_avg"] / 1e3) / 1e9
     gflops = FLOP_PER_PAIR * pairs / (mixed["ms_per_step"] / 1e3) / 1e9
+    interval = args.steps / mixed["rebuilds"] if mixed["rebuilds"] else float("inf")
+    step_bpp = bpp + REBUILD_BYTES_PER_PARTICLE / interval
+    step_achieved = step_bpp * w.n / (mixed["ms_per_step"] / 1e3) / 1e9
+    traffic = measured_traffic() if args.ncell == 200 else None
 
     out = {
         "metric": "particle-steps/s + Gflop/s, 32M LJ, FP32-mixed vs FP64 on 1 MI355X",
@@ -368,9 +403,13 @@ def main():
         "pair_flop_convention": "25 flop per unordered pair within rc",
         "mixed": mixed,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_unit": "HBM bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, copy-calibrated)",
                      "kernel": "k_force<FP32_MIXED> (pair forces + kicks + drift)",
                      "bytes_per_particle": bpp, "launch_ms_avg": mixed["force_ms_avg"]},
+        "step_roofline": {"bound": "hbm", "achieved": step_achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": step_achieved / HBM_PEAK_GBS, "bytes_per_particle_step": step_bpp,
+                          "rebuild_interval_steps": interval},
     }
     if fp64 is not None:
         out["fp64"] = dict(fp64, gflops=FLOP_PER_PAIR * pairs / (fp64["ms_per_step"] / 1e3) / 1e9,

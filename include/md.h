@@ -14,7 +14,7 @@
  *     Sec. II.A;
  *   - force: the scalar f(r) = (24 r^6 - 48) / r^14 + 8 c2 of Algorithm 1
  *     (Sec. III.C), F_i += f (q_j - q_i), full list, no scattered stores;
- *   - integrator: second-order symplectic (velocity Verlet), Sec. III.A.
+ *   - integrator: second-order symplectic (velocity Verlet), Sec. III.B.
  * Reduced LJ units: sigma = epsilon = k_B = 1 (Sec. II.A).
  *
  * Conventions for every entry point:
@@ -172,7 +172,7 @@ md_status md_build_neighbors(md_ctx *ctx);
  * force: device [n][3] in caller order, or NULL (forces kept internally). */
 md_status md_compute_forces(md_ctx *ctx, double *force);
 
-/* Advances nsteps velocity-Verlet steps (Sec. III.A).  Per step: half kick,
+/* Advances nsteps velocity-Verlet steps (Sec. III.B).  Per step: half kick,
  * drift, DUTC check (Sec. II.A), list rebuild when needed, forces, half kick.
  * energy_every > 0 records KE and PE every energy_every steps (read back with
  * md_energy_series).  With MD_F_VERIFY_LIST returns MD_ELIST if the verifier

@@ -15,7 +15,7 @@
  *     as the sorted list of Fig. 1: KeyPointer[N+1] + SortedList[], key = the
  *     smaller index; the full (both-direction) form is also produced;
  *   - a second-order symplectic step (velocity Verlet, kick-drift-kick), the
- *     benchmark integrator of Sec. III.A;
+ *     benchmark integrator of Sec. III.B;
  *   - the list-validity check of Sec. II.A (dynamic upper time cutoff): the
  *     accumulated bound D += dt * max|v| after each drift, rebuild when
  *     2D > skin.

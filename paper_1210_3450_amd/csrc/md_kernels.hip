@@ -1,6 +1,6 @@
 // md_kernels.hip -- gfx950 kernels of the short-range LJ hot path.
 //
-// Per step (velocity Verlet, Sec. III.A; list validity by DUTC, Sec. II.A):
+// Per step (velocity Verlet, Sec. III.B; list validity by DUTC, Sec. II.A):
 //   k_force<kForceMid>  close step n (v += hF), open step n+1 (v += hF, q += dt v),
 //                       per-box max |v|^2 for the DUTC bound
 //   k_dutc              D += dt * max|v|; flag a rebuild when 2D > skin

@@ -5,7 +5,7 @@ oracle's tests.  It holds none of the method's arithmetic (no potential, no
 neighbour search, no integration): only the initial states the paper's
 benchmarks and cavitation runs start from.
 
-Workload shapes follow the paper's benchmark conditions (Sec. III.A: FCC
+Workload shapes follow the paper's benchmark conditions (Sec. III.B: FCC
 lattice, number density 0.5, periodic cube, cutoff 2.5, Eq. 1 truncation) and
 its cavitation protocol (Sec. IV.A: liquid at density 0.7, T = 0.9, cutoff 3.0,
 uniform expansion of all lengths).  Velocities are Maxwell-Boltzmann at the
