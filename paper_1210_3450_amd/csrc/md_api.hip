@@ -345,7 +345,6 @@ void free_all(md_ctx* c) {
         dfree(D.vy[k]);
         dfree(D.vz[k]);
         dfree(D.id[k]);
-        dfree(D.cellc[k]);
     }
     dfree(D.qb);
     dfree(D.fx);
@@ -399,7 +398,6 @@ md_status alloc_all(md_ctx* c) {
         A(D.vy[k], ns);
         A(D.vz[k], ns);
         A(D.id[k], ns);
-        A(D.cellc[k], ns);
     }
     if (c->prm.rebuild == MD_REBUILD_DISPLACEMENT) A(D.qb, ns);
     A(D.fx, ns);

@@ -15,7 +15,6 @@
 //             converted to FP32 once and scaled by cs / 2^28.
 //   v*[2]     float64 velocity components (SoA), ping-pong only across a re-sort.
 //   id[2]     caller index of the particle in each slot.
-//   cellc[2]  packed cell coordinates at the last build: cx | cy << 10 | cz << 20.
 //   list      wave-blocked ELL pair list of 16-bit entries.  A list wave holds
 //             K = 64 / tpk keys and rows * 64 entries (rows = cap / tpk, a multiple
 //             of 8).  Key k's entry e belongs to lane ln = (k % K) * tpk + e % tpk as
@@ -76,7 +75,7 @@ struct BoxState {
     double D;                  // DUTC bound since the last build
     int32_t rebuild;           // list build pending for this box
     int32_t sq;                // current q / u buffer
-    int32_t sp;                // current v / id / cellc buffer
+    int32_t sp;                // current v / id buffer
     int32_t err;               // bit 0: bad position at binning; bit 1: a cell over 2048 particles
     int32_t need;              // longest list seen at any build (for overflow detection)
     int32_t built;             // builds done
@@ -113,7 +112,6 @@ struct Dev {
     double* vy[2];
     double* vz[2];
     int32_t* id[2];
-    uint32_t* cellc[2];
     double4* qb;         // positions at the last build (displacement policy only)
     double* fx;
     double* fy;
@@ -121,7 +119,7 @@ struct Dev {
     int32_t* cnt;        // list length per slot
     uint16_t* list;
     int32_t* cell_tmp;   // cell of each (old) slot at binning
-    int32_t* ticket;     // arrival rank within the cell at binning
+    int32_t* ticket;     // arrival rank within the cell at binning; then the ordered source slots
     int32_t* perm;       // new slot -> old slot
     int32_t* cell_cnt;
     int32_t* cell_start;

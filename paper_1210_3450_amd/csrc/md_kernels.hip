@@ -179,10 +179,9 @@ __global__ __launch_bounds__(kBlock) void k_get_cells(Dev d, Params p, int32_t* 
         const BoxGeom& g = d.geom[b];
         const int s = w * kWave + l;
         if (s - g.slot_off >= g.npart) continue;
-        const int sp = d.st[b].sp;
-        const uint32_t cc = d.cellc[sp][s];
+        const uint32_t cc = d.q[d.st[b].sq][s].cc;
         const int cx = cc & 1023, cy = (cc >> 10) & 1023, cz = cc >> 20;
-        out[d.id[sp][s]] = (cz * g.n[1] + cy) * g.n[0] + cx;
+        out[d.id[d.st[b].sp][s]] = (cz * g.n[1] + cy) * g.n[0] + cx;
     }
 }
 
@@ -202,6 +201,16 @@ template <int TPK>
 __device__ __forceinline__ uint32_t list_off(int e) {
     const int m = e / TPK;
     return ((uint32_t)(m & ~7) << 6) + (uint32_t)((e % TPK) << 3) + (uint32_t)(m & 7);
+}
+
+// The same offset in bytes, for an entry count that is known non-negative.
+template <int TPK>
+__device__ __forceinline__ uint32_t list_off_bytes(uint32_t e) {
+    if constexpr (TPK == 1) {
+        return (uint32_t)__umul24(e >> 3, 1008u) + (e << 1);  // (e & ~7) * 128 + (e & 7) * 2
+    } else {
+        return list_off<TPK>((int)e) * 2u;
+    }
 }
 
 // Index of entry e of key slot s in the chunked wave-blocked list: a list wave
@@ -390,12 +399,18 @@ __global__ __launch_bounds__(kBlock) void k_bin(Dev d, Params p) {
         if (valid) {
             const int sq = d.st[b].sq;
             Pos x = d.q[sq][s];
+            const double x0 = x.x, y0 = x.y, z0 = x.z;
             bool bad = false;
             const int cx = bin_axis(x.x, g.L[0], g.inv[0], g.n[0], bad);
             const int cy = bin_axis(x.y, g.L[1], g.inv[1], g.n[1], bad);
             const int cz = bin_axis(x.z, g.L[2], g.inv[2], g.n[2], bad);
             if (bad) atomicOr(&d.st[b].err, 1);
-            d.q[sq][s] = x;
+            // only particles that crossed the box boundary change: write those back
+            if (x.x != x0 || x.y != y0 || x.z != z0) {
+                d.q[sq][s].x = x.x;
+                d.q[sq][s].y = x.y;
+                d.q[sq][s].z = x.z;
+            }
             cid = (cz * g.n[1] + cy) * g.n[0] + cx;
             d.cell_tmp[s] = cid;
         }
@@ -473,30 +488,27 @@ __global__ __launch_bounds__(kBlock) void k_scatter(Dev d, Params p) {
 }
 
 // Arrival order within a cell depends on atomics; order each cell's members by
-// caller id so the sorted layout is a function of the positions alone.
-__global__ __launch_bounds__(kBlock) void k_cell_sort(Dev d, Params p) {
+// caller id so the sorted layout is a function of the positions alone.  One lane
+// per new slot: its rank among the cell's members by caller id is its place.
+// The ordered source slots go to d.ticket (free once k_scatter has run).
+__global__ __launch_bounds__(kBlock) void k_cell_rank(Dev d, Params p) {
     if (!*d.any) return;  // no box rebuilds this step
-    for (int t = blockIdx.x; t < p.ntile; t += gridDim.x) {
-        const int b = d.tile_box[t];
-        if (!d.st[b].rebuild) continue;
+    const int l = lane_id();
+    for (int w = xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6); w < p.nwave; w += gridDim.x * 4) {
+        const int b = d.wave_box[w];
+        const BoxState& st = d.st[b];
+        if (!st.rebuild) continue;
         const BoxGeom& g = d.geom[b];
-        const int32_t* id = d.id[d.st[b].sp];
-        for (int k = threadIdx.x; k < kTile; k += kBlock) {
-            const int c = t * kTile + k;
-            if (c - g.cell_off >= g.ncell) continue;
-            const int start = d.cell_start[c], m = d.cell_cnt[c];
-            int32_t* pm = d.perm + start;
-            for (int a = 1; a < m; ++a) {
-                const int x = pm[a];
-                const int key = id[x];
-                int e = a - 1;
-                while (e >= 0 && id[pm[e]] > key) {
-                    pm[e + 1] = pm[e];
-                    --e;
-                }
-                pm[e + 1] = x;
-            }
-        }
+        const int s = w * kWave + l;
+        if (s - g.slot_off >= g.npart) continue;
+        const int32_t* __restrict__ id = d.id[st.sp];
+        const int o = d.perm[s];
+        const int key = id[o];
+        const int c = g.cell_off + d.cell_tmp[o];
+        const int a = d.cell_start[c], m = d.cell_cnt[c];
+        int rank = 0;
+        for (int t = a; t < a + m; ++t) rank += id[d.perm[t]] < key ? 1 : 0;
+        d.ticket[a + rank] = o;
     }
 }
 
@@ -513,7 +525,7 @@ __global__ __launch_bounds__(kBlock) void k_permute(Dev d, Params p) {
         const int s = w * kWave + l;
         if (s - g.slot_off >= g.npart) continue;
         const int sq = st.sq, sp = st.sp, nq = sq ^ 1, np = sp ^ 1;
-        const int o = d.perm[s];
+        const int o = d.ticket[s];  // source slot, ordered within the cell by k_cell_rank
         Pos x = d.q[sq][o];
         d.vx[np][s] = d.vx[sp][o];
         d.vy[np][s] = d.vy[sp][o];
@@ -526,7 +538,6 @@ __global__ __launch_bounds__(kBlock) void k_permute(Dev d, Params p) {
         x.cc = cc;
         x.cnt = 0;
         d.q[nq][s] = x;
-        d.cellc[np][s] = cc;
         if (p.precision == MD_PREC_FP32_MIXED) d.u[nq][s] = units3(x, cc, g);
         if (d.qb) d.qb[s] = make_double4(x.x, x.y, x.z, 0.0);
     }
@@ -583,25 +594,110 @@ __device__ __forceinline__ int nb_axis(int c, int o, int n, double L, double& su
 
 // A4, one wavefront per home cell.  All keys of a cell share one candidate set:
 // the particles of its 27 stencil cells, concatenated in stencil order.  Lane l
-// holds candidate l of each 64-wide chunk (loads are contiguous runs), and the
-// wavefront walks the cell's keys: an exact FP64 test per (key, candidate), a
-// ballot, a popcount prefix, and the accepted partners appended in candidate
-// order.  The distance test is the plain definition with no contraction, so the
+// holds candidate l of each 64-wide chunk (loads are contiguous runs).  A pass
+// loads up to G chunks into registers, then the wavefront walks the cell's keys:
+// per (key, chunk) an exact FP64 test, a ballot, an mbcnt prefix on the key's
+// running count, and the accepted partners appended in candidate order.  The
+// running count is wave-uniform (SGPR), so no lane bookkeeping sits in the inner
+// loop.  The distance test is the plain definition with no contraction, so the
 // accepted set is the CPU's bit for bit.
 
 // Positions seen through the constant address space: in the list build they are
 // read-only, and uniform indices then become scalar loads into SGPRs.
 typedef const __attribute__((address_space(4))) double const_double;
 
+// One pass over the keys kb .. kb+mb-1 of a home cell against candidate chunks
+// [c0, c0 + G*64).  WRAP: some stencil cell is a periodic image, so every lane
+// subtracts its image term (a zero term leaves t unchanged bit for bit).
+template <int TPK, bool WRAP>
+__device__ __forceinline__ void list_pass(const Dev& d, const Params& p, const Pos* __restrict__ q,
+                                          const const_double* qc, int cs0, int kb, int mb, int c0, int total,
+                                          int start, int pre, double shx, double shy, double shz, int pre13,
+                                          int& n_own) {
+    constexpr int G = WRAP ? 3 : 6;
+    const int l = lane_id();
+    const double nan = __longlong_as_double(0x7ff8000000000000ll);
+    const int nch = min(G, (total - c0 + kWave - 1) >> 6);  // uniform, >= 1
+    double cx[G], cy[G], cz[G], sx[G], sy[G], sz[G];
+    uint32_t ent[G];
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+        if (k < nch) {
+            const int ci = c0 + k * kWave + l;
+            const bool valid = ci < total;
+            int sc = 0;  // last stencil cell whose range starts at or before ci
+            for (int step = 16; step > 0; step >>= 1) {
+                const int tt = sc + step;
+                const int pv = __shfl(pre, tt < 27 ? tt : 26);
+                if (tt < 27 && pv <= ci) sc = tt;
+            }
+            // shuffles run on every lane: a bpermute from an inactive lane reads 0
+            const int st_sc = __shfl(start, sc), pre_sc = __shfl(pre, sc);
+            ent[k] = (uint32_t)((sc << kOffBits) | ((ci - pre_sc) & (kMaxCellCount - 1)));
+            const Pos qj = q[valid ? st_sc + ci - pre_sc : cs0];
+            cx[k] = valid ? qj.x : nan;  // NaN distance: never accepted
+            cy[k] = qj.y;
+            cz[k] = qj.z;
+            if (WRAP) {
+                sx[k] = __shfl(shx, sc);
+                sy[k] = __shfl(shy, sc);
+                sz[k] = __shfl(shz, sc);
+            }
+        }
+    }
+    // The candidate loads must land before the key loop: a wait placed inside it
+    // would also wait on the list stores issued there.
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    const double rl2 = p.rl2;
+    const int cap = p.cap, rows = p.rows;
+    double nx = qc[4 * (cs0 + kb)], ny = qc[4 * (cs0 + kb) + 1], nz = qc[4 * (cs0 + kb) + 2];
+    for (int a = 0; a < mb; ++a) {
+        const int key = cs0 + kb + a;
+        double4 qi;  // scalar loads, one key ahead
+        qi.x = nx;
+        qi.y = ny;
+        qi.z = nz;
+        if (a + 1 < mb) {
+            nx = qc[4 * (key + 1)];
+            ny = qc[4 * (key + 1) + 1];
+            nz = qc[4 * (key + 1) + 2];
+        }
+        int cnt = c0 == 0 ? 0 : __builtin_amdgcn_readlane(n_own, a);  // uniform running count
+        // the key's own candidate: chunk sk, bit sb (scalar)
+        const int self = pre13 + kb + a - c0;
+        const int sk = self >> 6;
+        const unsigned long long sb = 1ull << (self & 63);
+        char* __restrict__ kp = reinterpret_cast<char*>(d.list + list_addr(key, 0, TPK, rows));
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            if (k < nch) {
+                const double r2 = WRAP ? dist2_exact(qi, make_double3(cx[k], cy[k], cz[k]), sx[k], sy[k], sz[k])
+                                       : dist2_exact0(qi, make_double3(cx[k], cy[k], cz[k]));
+                // lanes within the list radius, minus the key itself
+                const unsigned long long mask = __builtin_amdgcn_ballot_w64(r2 < rl2) & ~(k == sk ? sb : 0ull);
+                const uint32_t pos = __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
+                                                               __builtin_amdgcn_mbcnt_lo((unsigned)mask, (unsigned)cnt));
+                unsigned long long sm = mask;
+                if (cnt + __popcll(mask) > cap)  // overflow: keep the entries that fit (rare)
+                    sm = __builtin_amdgcn_ballot_w64(__builtin_amdgcn_inverse_ballot_w64(mask) && pos < (uint32_t)cap);
+                if (__builtin_amdgcn_inverse_ballot_w64(sm))
+                    *reinterpret_cast<uint16_t*>(kp + list_off_bytes<TPK>(pos)) = (uint16_t)ent[k];
+                cnt += __popcll(mask);
+            }
+        }
+        if (l == a) n_own = cnt;
+    }
+}
+
 template <int TPK>
 __global__ __launch_bounds__(kBlock) void k_list(Dev d, Params p) {
     if (!*d.any) return;  // no box rebuilds this step
     const int l = lane_id();
     const int ncells = p.ntile * kTile;
-    const double nan = __longlong_as_double(0x7ff8000000000000ll);
-    const double rl2 = p.rl2;
-    const int cap = p.cap, rows = p.rows;
-    for (int c = blockIdx.x * 4 + (threadIdx.x >> 6); c < ncells; c += gridDim.x * 4) {
+    const int cap = p.cap;
+    // XCD-aware: each XCD sweeps a contiguous run of cells, so the stencil rows a
+    // cell loads are still in that XCD's L2 for its neighbours
+    for (int c = xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6); c < ncells; c += gridDim.x * 4) {
         const int t = c / kTile;
         const int b = d.tile_box[t];
         const BoxState& st = d.st[b];
@@ -617,78 +713,44 @@ __global__ __launch_bounds__(kBlock) void k_list(Dev d, Params p) {
         // stencil cell s = lane s < 27: start, count and image term
         int start = 0, cnt = 0;
         double shx = 0.0, shy = 0.0, shz = 0.0;
+        bool img = false;
         if (l < 27) {
             const int ox = l % 3 - 1, oy = (l / 3) % 3 - 1, oz = l / 9 - 1;
             int rx, ry, rz;
             const int x = nb_axis(cx, ox, g.n[0], g.L[0], shx, rx);
             const int y = nb_axis(cy, oy, g.n[1], g.L[1], shy, ry);
             const int z = nb_axis(cz, oz, g.n[2], g.L[2], shz, rz);
+            img = (rx | ry | rz) != 0;
             const int nc = g.cell_off + (z * g.n[1] + y) * g.n[0] + x;
             start = d.cell_start[nc];
             cnt = d.cell_cnt[nc];
             if (cnt > kMaxCellCount) atomicOr(&d.st[b].err, 2);  // ranks would not fit 11 bits
         }
+        const bool wrap = __ballot(img) != 0ull;  // uniform: this cell touches the box boundary
         const int incl = wave_incl_scan(cnt);
         const int pre = incl - cnt;
         const int total = __builtin_amdgcn_readlane(incl, 26);
+        const int pre13 = __builtin_amdgcn_readlane(pre, 13);  // the home cell's first candidate
+        const const_double* qc = (const const_double*)q;     // 4 doubles per particle
         int need = 0;
         for (int kb = 0; kb < m; kb += kWave) {
             const int mb = min(kWave, m - kb);
-            int n_own = 0;  // lane a counts the partners of key kb + a
-            const const_double* qc = (const const_double*)q;  // 4 doubles per particle
-            for (int c0 = 0; c0 < total; c0 += kWave) {
-                const int ci = c0 + l;
-                const bool valid = ci < total;
-                int sc = 0;  // last stencil cell whose range starts at or before ci
-                for (int step = 16; step > 0; step >>= 1) {
-                    const int tt = sc + step;
-                    const int pv = __shfl(pre, tt < 27 ? tt : 26);
-                    if (tt < 27 && pv <= ci) sc = tt;
-                }
-                // shuffles run on every lane: a bpermute from an inactive lane reads 0
-                const int st_sc = __shfl(start, sc), pre_sc = __shfl(pre, sc);
-                const int j = valid ? st_sc + ci - pre_sc : -1;
-                const uint16_t ent = (uint16_t)((sc << kOffBits) | ((ci - pre_sc) & (kMaxCellCount - 1)));
-                const double sx = __shfl(shx, sc), sy = __shfl(shy, sc), sz = __shfl(shz, sc);
-                Pos qj = q[valid ? j : cs0];
-                if (!valid) qj.x = nan;  // NaN distance: never accepted
-                const bool wrapped = __ballot(valid && (sx != 0.0 || sy != 0.0 || sz != 0.0)) != 0ull;
-                // The candidate loads must land before the key loop: a wait placed
-                // inside it would also wait on the list stores issued there.
-                __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
-                double nx = qc[4 * (cs0 + kb)], ny = qc[4 * (cs0 + kb) + 1], nz = qc[4 * (cs0 + kb) + 2];
-                for (int a = 0; a < mb; ++a) {
-                    const int key = cs0 + kb + a;
-                    double4 qi;  // scalar loads, one key ahead
-                    qi.x = nx;
-                    qi.y = ny;
-                    qi.z = nz;
-                    if (a + 1 < mb) {
-                        nx = qc[4 * (key + 1)];
-                        ny = qc[4 * (key + 1) + 1];
-                        nz = qc[4 * (key + 1) + 2];
-                    }
-                    const double r2 = wrapped ? dist2_exact(qi, qj, sx, sy, sz) : dist2_exact0(qi, qj);
-                    const bool acc = r2 < rl2 && j != key;
-                    const unsigned long long mask = __ballot(acc);
-                    if (mask) {
-                        const int na = __builtin_amdgcn_readlane(n_own, a);
-                        if (acc) {
-                            const int pos = na + (int)__builtin_amdgcn_mbcnt_hi(
-                                                     (unsigned)(mask >> 32),
-                                                     __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
-                            if (pos < cap) d.list[list_addr(key, pos, TPK, rows)] = ent;
-                        }
-                        if (l == a) n_own += __popcll(mask);
-                    }
-                }
+            int n_own = 0;  // lane a: partners of key kb + a so far
+            if (wrap) {
+                for (int c0 = 0; c0 < total; c0 += 3 * kWave)
+                    list_pass<TPK, true>(d, p, q, qc, cs0, kb, mb, c0, total, start, pre, shx, shy, shz, pre13,
+                                         n_own);
+            } else {
+                for (int c0 = 0; c0 < total; c0 += 6 * kWave)
+                    list_pass<TPK, false>(d, p, q, qc, cs0, kb, mb, c0, total, start, pre, shx, shy, shz, pre13,
+                                          n_own);
             }
             if (l < mb) {
                 const int nk = n_own < cap ? n_own : cap;
                 d.cnt[cs0 + kb + l] = nk;
                 q[cs0 + kb + l].cnt = nk;
             }
-            need = max(need, wave_max_i(n_own));
+            need = max(need, wave_max_i(l < mb ? n_own : 0));
         }
         if (l == 0) atomicMax(&d.tile_need[t], need);
     }
@@ -1160,7 +1222,7 @@ void launch_rebuild_chain(const Dev& d, const Params& p, bool with_list, hipStre
     k_scan_box<<<p.nbox < 1024 ? p.nbox : 1024, kBlock, 0, s>>>(d, p);
     k_scan_add<<<gt, kBlock, 0, s>>>(d, p);
     k_scatter<<<gw, kBlock, 0, s>>>(d, p);
-    k_cell_sort<<<gt, kBlock, 0, s>>>(d, p);
+    k_cell_rank<<<gw, kBlock, 0, s>>>(d, p);
     k_permute<<<gw, kBlock, 0, s>>>(d, p);
     k_flip<<<1, kBlock, 0, s>>>(d, p);
     if (with_list) {
