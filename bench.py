@@ -378,8 +378,8 @@ def main():
     force_bytes = bpp * w.n
     achieved = force_bytes / (mixed["force_ms_avg"] / 1e3) / 1e9
     gflops = FLOP_PER_PAIR * pairs / (mixed["ms_per_step"] / 1e3) / 1e9
-    interval = args.steps / mixed["rebuilds"] if mixed["rebuilds"] else float("inf")
-    step_bpp = bpp + REBUILD_BYTES_PER_PARTICLE / interval
+    interval = args.steps / mixed["rebuilds"] if mixed["rebuilds"] else None  # null in JSON: no rebuild
+    step_bpp = bpp + (REBUILD_BYTES_PER_PARTICLE / interval if interval else 0.0)
     step_achieved = step_bpp * w.n / (mixed["ms_per_step"] / 1e3) / 1e9
     traffic = measured_traffic() if args.ncell == 200 else None
 

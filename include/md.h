@@ -74,6 +74,10 @@ typedef enum {
 #define MD_F_VERIFY_LIST 1u        /* debug: after every force evaluation count pairs within
                                       rc missing from the list (O(n^2) per box) */
 #define MD_F_GRAPH 2u              /* replay md_step chunks as captured HIP graphs */
+#define MD_F_TILE_ON 4u            /* FP32-mixed, one lane per key: always use the force pass with
+                                      LDS-staged partner tiles (it falls back per block / wavefront
+                                      where a tile does not apply); default: chosen from the geometry */
+#define MD_F_TILE_OFF 8u           /* never use the staged-tile force pass (testing, tuning) */
 
 typedef struct {
     int64_t n;            /* particles in the box, >= 2 */

@@ -141,7 +141,9 @@ md_status validate(const md_params* b, int32_t nbox, std::string& why) {
         if (p.precision != MD_PREC_FP64 && p.precision != MD_PREC_FP32_MIXED) return bad("unknown precision");
         if (p.cutoff < MD_CUT_EQ1 || p.cutoff > MD_CUT_RAW) return bad("unknown cutoff scheme");
         if (p.rebuild < MD_REBUILD_DUTC || p.rebuild > MD_REBUILD_NEVER) return bad("unknown rebuild policy");
-        if (p.flags & ~(uint32_t)(MD_F_VERIFY_LIST | MD_F_GRAPH)) return bad("unknown flag bits");
+        if (p.flags & ~(uint32_t)(MD_F_VERIFY_LIST | MD_F_GRAPH | MD_F_TILE_ON | MD_F_TILE_OFF))
+            return bad("unknown flag bits");
+        if ((p.flags & MD_F_TILE_ON) && (p.flags & MD_F_TILE_OFF)) return bad("MD_F_TILE_ON with MD_F_TILE_OFF");
         if (!(p.threads_per_key == 0 || p.threads_per_key == 1 || p.threads_per_key == 2 ||
               p.threads_per_key == 4 || p.threads_per_key == 8))
             return bad("threads_per_key must be 0, 1, 2, 4 or 8");
@@ -193,14 +195,22 @@ void layout(md_ctx* c) {
     for (int b = 0; b < c->nbox; ++b) {
         BoxGeom& g = c->geom[b];
         const md_params& p = c->boxes[b];
+        double csmax = 0.0;
         for (int a = 0; a < 3; ++a) {
             g.L[a] = p.box[a];
             g.n[a] = (int32_t)std::floor(p.box[a] / rl);
             g.inv[a] = (double)g.n[a] / p.box[a];
             g.cs[a] = p.box[a] / (double)g.n[a];
-            g.ucs[a] = std::ldexp(1.0, kUnitBits) / g.cs[a];
-            g.usc[a] = (float)std::ldexp(g.cs[a], -kUnitBits);
+            csmax = std::max(csmax, g.cs[a]);
         }
+        // fixed-point unit: a power of two, one cell side = 2^27 .. 2^28 units
+        int e;
+        (void)std::frexp(csmax, &e);  // csmax in [2^(e-1), 2^e)
+        g.ucs = std::ldexp(1.0, kUnitBits - e);
+        for (int a = 0; a < 3; ++a) g.uoff[a] = (int32_t)std::lrint(g.cs[a] * g.ucs);
+        g.lam = (float)std::ldexp(1.0, e - kUnitBits);
+        g.lam2inv = (float)(g.ucs * g.ucs);
+        g.rc2u = (float)(p.rc * p.rc * g.ucs * g.ucs);
         g.ncell = g.n[0] * g.n[1] * g.n[2];
         g.ntile = (g.ncell + kTile - 1) / kTile;
         g.tile_off = tile;
@@ -241,17 +251,14 @@ md_status upload_geometry(md_ctx* c) {
         for (int t = 0; t < g.ntile; ++t) tb[g.tile_off + t] = b;
     }
     std::vector<double4> dsh(27 * c->nbox);
-    std::vector<int4> ish(27);
     for (int b = 0; b < c->nbox; ++b) {
         const BoxGeom& g = c->geom[b];
         for (int z = -1; z <= 1; ++z)
             for (int y = -1; y <= 1; ++y)
                 for (int x = -1; x <= 1; ++x) {
                     const int code = (z + 1) * 9 + (y + 1) * 3 + (x + 1);
-                    // FP64 list: code = periodic image r; the force subtracts r * L.
+                    // code = periodic image r; the FP64 force subtracts r * L.
                     dsh[b * 27 + code] = make_double4(x * g.L[0], y * g.L[1], z * g.L[2], 0.0);
-                    // FP32 list: code = stencil offset o; the force adds o * 2^28 units.
-                    ish[code] = make_int4(x * (1 << kUnitBits), y * (1 << kUnitBits), z * (1 << kUnitBits), 0);
                 }
     }
     HIPCHK(c, hipMemcpyAsync(c->D.wave_box, wb.data(), sizeof(int32_t) * wb.size(), hipMemcpyHostToDevice,
@@ -259,8 +266,6 @@ md_status upload_geometry(md_ctx* c) {
     HIPCHK(c, hipMemcpyAsync(c->D.tile_box, tb.data(), sizeof(int32_t) * tb.size(), hipMemcpyHostToDevice,
                              c->stream));
     HIPCHK(c, hipMemcpyAsync(c->D.dshift, dsh.data(), sizeof(double4) * dsh.size(), hipMemcpyHostToDevice,
-                             c->stream));
-    HIPCHK(c, hipMemcpyAsync(c->D.ishift, ish.data(), sizeof(int4) * ish.size(), hipMemcpyHostToDevice,
                              c->stream));
     // the vectors above are pageable: finish the copies before they go away
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -328,6 +333,17 @@ void params_refresh(md_ctx* c) {
     P.nwave = c->nwave;
     P.ntile = c->ntile;
     P.precision = p.precision;
+    // Staged tiles pay off when a block's 256 keys span at most two rows of cells
+    // and their partners fit the tile (about 9 * 256 partners per key row, at most
+    // 20 particles per cell); otherwise the force pass gathers from global memory.
+    bool tile = p.precision == MD_PREC_FP32_MIXED;
+    for (const BoxGeom& g : c->geom) {
+        const double ppc = (double)g.npart / (double)g.ncell;
+        tile = tile && ppc <= 20.0 && (double)g.n[0] >= (double)kBlock / ppc + 3.0;
+    }
+    if (p.flags & MD_F_TILE_ON) tile = p.precision == MD_PREC_FP32_MIXED;
+    if (p.flags & MD_F_TILE_OFF) tile = false;
+    P.tile = tile ? 1 : 0;
 }
 
 void free_all(md_ctx* c) {
@@ -365,7 +381,6 @@ void free_all(md_ctx* c) {
     dfree(D.ke_part);
     dfree(D.pe_part);
     dfree(D.dshift);
-    dfree(D.ishift);
     dfree(D.series_ke);
     dfree(D.series_pe);
     dfree(c->bk_pos);
@@ -412,7 +427,6 @@ md_status alloc_all(md_ctx* c) {
     A(D.ke_part, (size_t)c->nwave * 8);
     A(D.pe_part, (size_t)c->nwave * 8);
     A(D.dshift, (size_t)27 * c->nbox);
-    A(D.ishift, (size_t)27);
     A(D.series_ke, (size_t)kMaxSeries * c->nbox);
     A(D.series_pe, (size_t)kMaxSeries * c->nbox);
     A(c->bk_pos, (size_t)c->ntotal * 3);

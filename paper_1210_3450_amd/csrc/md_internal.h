@@ -9,10 +9,12 @@
 //             build, the list length), 32 bytes, ping-pong: the force kernel gathers
 //             partners from q[sq] and writes drifted positions to q[1-sq].
 //   u[2]      int4 cell-relative positions in fixed point (FP32-mixed path),
-//             ping-pong with q: u = rint((x - (c + 1/2) cs) * 2^28 / cs) per axis,
-//             c = the particle's cell at the last build.  A pair's separation
-//             u_j - u_i + o * 2^28 (o = stencil offset) is exact in int32; it is
-//             converted to FP32 once and scaled by cs / 2^28.
+//             ping-pong with q: u = rint((x - (c + 1/2) cs) * ucs) per axis,
+//             c = the particle's cell at the last build, ucs a power of two
+//             (units per length, the same on every axis).  A pair's separation
+//             u_j - u_i + o * uoff (o = stencil offset, uoff = one cell side in
+//             units) is exact in int32; it is converted to FP32 once, and lengths
+//             stay in units until the per-particle force is scaled back.
 //   v*[2]     float64 velocity components (SoA), ping-pong only across a re-sort.
 //   id[2]     caller index of the particle in each slot.
 //   list      wave-blocked ELL pair list of 16-bit entries.  A list wave holds
@@ -37,7 +39,7 @@ constexpr int kIdxBits = 27;
 constexpr uint32_t kIdxMask = (1u << kIdxBits) - 1u;
 constexpr int kMaxSeries = 4096;         // energy samples kept per box
 constexpr int kMaxCellsPerAxis = 1023;   // 10-bit packed cell coordinates
-constexpr int kUnitBits = 28;            // fixed-point units per cell side: 2^28
+constexpr int kUnitBits = 28;            // fixed-point units per cell side: at most 2^28
 constexpr int kUnitClamp = 1 << 29;      // |u| bound (two cell sides): pair sums stay in int32
 constexpr int kOffBits = 11;             // list entry: partner rank within its cell
 constexpr int kMaxCellCount = 1 << kOffBits;
@@ -57,8 +59,13 @@ struct BoxGeom {
     double L[3];
     double inv[3];   // n / L, rounded once on the host
     double cs[3];    // L / n
-    double ucs[3];   // 2^28 / cs: fixed-point units per length
-    float usc[4];    // cs / 2^28 (FP32): length per fixed-point unit
+    double ucs;      // fixed-point units per length, a power of two with cs * ucs in [2^27, 2^28)
+                     // for the largest cell side (the same unit on every axis)
+    int32_t uoff[3]; // one cell side in units, per axis: rint(cs * ucs)
+    float lam;       // length per unit, 1 / ucs (exact)
+    float lam2inv;   // ucs^2 (exact)
+    float rc2u;      // rc^2 in units^2
+    float pad_f;
     int32_t n[3];
     int32_t ncell;
     int32_t cell_off;  // first global cell (multiple of kTile)
@@ -97,7 +104,7 @@ struct Params {
     int32_t ntile;      // cell tiles over all boxes
     int32_t precision;  // MD_PREC_*
     int32_t record;     // energy reduction appends to the series
-    int32_t pad;
+    int32_t tile;       // FP32-mixed forces from LDS-staged partner tiles (one lane per key)
 };
 
 struct Dev {
@@ -131,7 +138,6 @@ struct Dev {
     double* ke_part;     // per list wave
     double* pe_part;
     double4* dshift;     // [nbox][27] FP64 image shift s * L
-    int4* ishift;        // [27] fixed-point stencil shift o * 2^28
     double* series_ke;   // [kMaxSeries][nbox]
     double* series_pe;
 };

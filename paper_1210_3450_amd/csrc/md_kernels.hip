@@ -94,8 +94,9 @@ __device__ __forceinline__ Pos make_pos(double x, double y, double z, uint32_t c
 }
 
 __device__ __forceinline__ int4 units3(const Pos& x, uint32_t cc, const BoxGeom& g) {
-    return make_int4(to_units(x.x, cc & 1023, g.cs[0], g.ucs[0]), to_units(x.y, (cc >> 10) & 1023, g.cs[1], g.ucs[1]),
-                     to_units(x.z, cc >> 20, g.cs[2], g.ucs[2]), 0);
+    return make_int4(to_units(x.x, cc & 1023, g.cs[0], g.ucs), to_units(x.y, (cc >> 10) & 1023, g.cs[1], g.ucs),
+                     to_units(x.z, cc >> 20, g.cs[2], g.ucs), (int)(cc & 1023));  // w: the cell's x index
+
 }
 
 // Wrap one coordinate into [0, L) and return its cell index, exactly as the
@@ -609,11 +610,17 @@ typedef const __attribute__((address_space(4))) double const_double;
 // One pass over the keys kb .. kb+mb-1 of a home cell against candidate chunks
 // [c0, c0 + G*64).  WRAP: some stencil cell is a periodic image, so every lane
 // subtracts its image term (a zero term leaves t unchanged bit for bit).
-template <int TPK, bool WRAP>
+// STAGED: accepted entries go to the wavefront's LDS buffer (key a's entry e at
+// a * cap + (e % TPK) * (cap / TPK) + e / TPK, i.e. already in per-lane chunk
+// order) and leave in whole 16-byte chunks afterwards; otherwise each entry is
+// stored to the list directly.
+constexpr int kStage = 4096;  // LDS list entries per wavefront
+
+template <int TPK, bool WRAP, bool STAGED>
 __device__ __forceinline__ void list_pass(const Dev& d, const Params& p, const Pos* __restrict__ q,
                                           const const_double* qc, int cs0, int kb, int mb, int c0, int total,
                                           int start, int pre, double shx, double shy, double shz, int pre13,
-                                          int& n_own) {
+                                          int& n_own, uint16_t* stage) {
     constexpr int G = WRAP ? 3 : 6;
     const int l = lane_id();
     const double nan = __longlong_as_double(0x7ff8000000000000ll);
@@ -667,7 +674,8 @@ __device__ __forceinline__ void list_pass(const Dev& d, const Params& p, const P
         const int self = pre13 + kb + a - c0;
         const int sk = self >> 6;
         const unsigned long long sb = 1ull << (self & 63);
-        char* __restrict__ kp = reinterpret_cast<char*>(d.list + list_addr(key, 0, TPK, rows));
+        char* __restrict__ kp = STAGED ? reinterpret_cast<char*>(stage + a * cap)
+                                       : reinterpret_cast<char*>(d.list + list_addr(key, 0, TPK, rows));
 #pragma unroll
         for (int k = 0; k < G; ++k) {
             if (k < nch) {
@@ -680,8 +688,11 @@ __device__ __forceinline__ void list_pass(const Dev& d, const Params& p, const P
                 unsigned long long sm = mask;
                 if (cnt + __popcll(mask) > cap)  // overflow: keep the entries that fit (rare)
                     sm = __builtin_amdgcn_ballot_w64(__builtin_amdgcn_inverse_ballot_w64(mask) && pos < (uint32_t)cap);
-                if (__builtin_amdgcn_inverse_ballot_w64(sm))
-                    *reinterpret_cast<uint16_t*>(kp + list_off_bytes<TPK>(pos)) = (uint16_t)ent[k];
+                if (__builtin_amdgcn_inverse_ballot_w64(sm)) {
+                    const uint32_t off = STAGED ? ((pos % TPK) * (uint32_t)(cap / TPK) + pos / TPK) * 2u
+                                                : list_off_bytes<TPK>(pos);
+                    *reinterpret_cast<uint16_t*>(kp + off) = (uint16_t)ent[k];
+                }
                 cnt += __popcll(mask);
             }
         }
@@ -692,9 +703,11 @@ __device__ __forceinline__ void list_pass(const Dev& d, const Params& p, const P
 template <int TPK>
 __global__ __launch_bounds__(kBlock) void k_list(Dev d, Params p) {
     if (!*d.any) return;  // no box rebuilds this step
+    __shared__ __align__(16) uint16_t stage_all[kBlock / kWave][kStage];
+    uint16_t* stage = stage_all[threadIdx.x >> 6];
     const int l = lane_id();
     const int ncells = p.ntile * kTile;
-    const int cap = p.cap;
+    const int cap = p.cap, rows = p.rows;
     // XCD-aware: each XCD sweeps a contiguous run of cells, so the stencil rows a
     // cell loads are still in that XCD's L2 for its neighbours
     for (int c = xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6); c < ncells; c += gridDim.x * 4) {
@@ -736,14 +749,46 @@ __global__ __launch_bounds__(kBlock) void k_list(Dev d, Params p) {
         for (int kb = 0; kb < m; kb += kWave) {
             const int mb = min(kWave, m - kb);
             int n_own = 0;  // lane a: partners of key kb + a so far
-            if (wrap) {
+            const bool staged = mb * cap <= kStage;  // uniform
+            if (staged) {
+                if (wrap) {
+                    for (int c0 = 0; c0 < total; c0 += 3 * kWave)
+                        list_pass<TPK, true, true>(d, p, q, qc, cs0, kb, mb, c0, total, start, pre, shx, shy, shz,
+                                                   pre13, n_own, stage);
+                } else {
+                    for (int c0 = 0; c0 < total; c0 += 6 * kWave)
+                        list_pass<TPK, false, true>(d, p, q, qc, cs0, kb, mb, c0, total, start, pre, shx, shy, shz,
+                                                    pre13, n_own, stage);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                // write-out: item (a, t, c) = chunk c of key a's lane t, 16 bytes; lanes
+                // of consecutive keys write consecutive chunks of the list
+                const int cpt = cap / TPK / 8;  // chunks per key lane in the buffer
+                const int nitem = mb * TPK * cpt;
+                for (int i0 = 0; i0 < nitem; i0 += kWave) {  // same trip count on every lane
+                    const int it = i0 + l;
+                    const int c = it / (mb * TPK), at = it - c * (mb * TPK);
+                    const int a = at / TPK, t = at - a * TPK;
+                    const int na = __shfl(n_own, a & 63);  // every lane takes part in the shuffle
+                    const int nlane = na > t ? (na - t + TPK - 1) / TPK : 0;
+                    if (it < nitem && c * 8 < nlane) {
+                        const uint4 v = *reinterpret_cast<const uint4*>(stage + a * cap + t * (cap / TPK) + c * 8);
+                        *reinterpret_cast<uint4*>(d.list + list_addr(cs0 + kb + a, 8 * c * TPK + t, TPK, rows)) = v;
+                    }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            } else if (wrap) {
                 for (int c0 = 0; c0 < total; c0 += 3 * kWave)
-                    list_pass<TPK, true>(d, p, q, qc, cs0, kb, mb, c0, total, start, pre, shx, shy, shz, pre13,
-                                         n_own);
+                    list_pass<TPK, true, false>(d, p, q, qc, cs0, kb, mb, c0, total, start, pre, shx, shy, shz,
+                                                pre13, n_own, stage);
             } else {
                 for (int c0 = 0; c0 < total; c0 += 6 * kWave)
-                    list_pass<TPK, false>(d, p, q, qc, cs0, kb, mb, c0, total, start, pre, shx, shy, shz, pre13,
-                                          n_own);
+                    list_pass<TPK, false, false>(d, p, q, qc, cs0, kb, mb, c0, total, start, pre, shx, shy, shz,
+                                                 pre13, n_own, stage);
             }
             if (l < mb) {
                 const int nk = n_own < cap ? n_own : cap;
@@ -797,183 +842,14 @@ __device__ __forceinline__ void stripe_put(unsigned long long* base, int b, int 
               (unsigned long long)__double_as_longlong(v));
 }
 
-// Algorithm 1 on the GPU.  PREC: MD_PREC_FP64 or MD_PREC_FP32_MIXED.
-// MODE: kForceOnly / kForceEnd / kForceMid.  ENERGY: per-wave KE and PE partials.
-// Each lane reads 8 list entries per 16-byte load and keeps 8 partner gathers in
-// flight (Algorithm 1's unrolling for latency hiding, in GPU form).  A list
-// entry names a stencil cell and a rank in it; the wavefront first tabulates, in
-// LDS, the 27 stencil-cell starts of each distinct cell its keys live in.
-constexpr int kHomeMax = 16;  // distinct key cells per wavefront served from LDS
-
+// The end of a force pass for one key: reduce the lanes of a key, then store F,
+// or kick (closing half kick; mid-step: closing and opening kicks, drift and the
+// fixed-point re-encoding), DUTC maximum and energy partials per wavefront.
 template <int PREC, int MODE, int TPK, bool ENERGY>
-__global__ __launch_bounds__(kBlock) void k_force(Dev d, Params p) {
-    constexpr int K = kWave / TPK;
-    constexpr int U = 8;  // entries per iteration (one 16-byte chunk)
-    using V4 = typename ShiftT<PREC>::V;
-    __shared__ V4 shift[kBlock / kWave][27];
-    __shared__ uint32_t home_cc[kBlock / kWave][kWave];
-    __shared__ uint32_t tab[kBlock / kWave][kHomeMax * 27];
-    const int l = lane_id(), wib = threadIdx.x >> 6, sub = l % TPK;
-    const int lw = xcd_block(blockIdx.x, gridDim.x) * 4 + wib;
-    const int nlw = p.nwave * TPK;
-    const bool wave_ok = lw < nlw;
-    const int b = __builtin_amdgcn_readfirstlane(wave_ok ? d.wave_box[(lw * K) >> 6] : 0);
-    if (l < 27) {
-        if constexpr (PREC == MD_PREC_FP64)
-            shift[wib][l] = d.dshift[b * 27 + l];
-        else
-            shift[wib][l] = d.ishift[l];
-    }
-    __syncthreads();
-    if (!wave_ok) return;
-
-    const BoxGeom& g = d.geom[b];  // b is uniform: scalar loads
-    const int sq = d.st[b].sq, sp = d.st[b].sp;
-    const int key = lw * K + l / TPK;
-    const bool active = key - g.slot_off < g.npart;
-    const Pos qi = d.q[sq][active ? key : g.slot_off];
-    const uint32_t cc = active ? qi.cc : 0xffffffffu;
-
-    // distinct cells of this wavefront's keys (keys are sorted by cell), and for
-    // each the start slot and image code of its 27 stencil cells
-    const uint32_t cprev = __shfl_up(cc, TPK);
-    const bool head = active && sub == 0 && (l < TPK || cprev != cc);
-    const unsigned long long hm = __ballot(head);
-    const int nhome = __popcll(hm);
-    const int h = __popcll(hm & (l == 63 ? ~0ull : ((2ull << l) - 1ull))) - 1;
-    const bool tabled = nhome <= kHomeMax;  // uniform
-    if (tabled) {
-        if (head) home_cc[wib][h] = cc;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        for (int idx = l; idx < nhome * 27; idx += kWave) {
-            const int hh = idx / 27, s = idx - hh * 27;
-            uint32_t img;
-            const int nc = stencil_cell(home_cc[wib][hh], s, g, &img);
-            tab[wib][idx] = (uint32_t)d.cell_start[nc] | (img << kIdxBits);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
-
-    double Fx = 0.0, Fy = 0.0, Fz = 0.0, pe = 0.0;
-    // The pair loop, instantiated twice so the choice between the LDS table and
-    // direct lookups is made once per wavefront, outside the loop.
-    auto pair_loop = [&](auto tabled_c) {
-        constexpr bool TB = decltype(tabled_c)::value;
-        const int n_i = qi.cnt;
-        const int nl = n_i > sub ? (n_i - sub + TPK - 1) / TPK : 0;  // this lane's entries
-        const uint4* __restrict__ l4 = reinterpret_cast<const uint4*>(d.list + (size_t)lw * p.rows * kWave) + l;
-        const uint32_t* __restrict__ tb = tab[wib] + h * 27;
-        // slot (27 bits) | image code << 27 of stencil cell s of this key's cell
-        auto lookup = [&](uint32_t s) -> uint32_t {
-            if constexpr (TB) {
-                return tb[s];
-            } else {
-                uint32_t img;
-                const int nc = stencil_cell(cc, (int)s, g, &img);
-                return (uint32_t)d.cell_start[nc] | (img << kIdxBits);
-            }
-        };
-        if constexpr (PREC == MD_PREC_FP64) {
-            const Pos* __restrict__ q = d.q[sq];
-            const double rc2 = p.rc2, c2x8 = 8.0 * p.c2;
-            uint4 raw_next = nl > 0 ? l4[0] : make_uint4(0u, 0u, 0u, 0u);
-            for (int m0 = 0; m0 < nl; m0 += U) {
-                const uint4 raw = raw_next;
-                const uint32_t w[4] = {raw.x, raw.y, raw.z, raw.w};
-                uint32_t js[U], img[U];
-#pragma unroll
-                for (int k = 0; k < U; ++k) {
-                    const uint32_t e = (w[k >> 1] >> ((k & 1) * 16)) & 0xffffu;
-                    const bool ok = m0 + k < nl;  // entries past the list end are padding
-                    const uint32_t t = lookup(ok ? e >> kOffBits : 13u);
-                    js[k] = ok ? (t & kIdxMask) + (e & (kMaxCellCount - 1)) : (uint32_t)key;
-                    img[k] = ok ? t >> kIdxBits : 13u;
-                }
-                Pos qj[U];
-#pragma unroll
-                for (int k = 0; k < U; ++k) qj[k] = q[js[k]];
-                // next chunk's entries, issued after the gathers: the load counter
-                // retires in order, so this load does not delay them
-                if (m0 + U < nl) raw_next = l4[(size_t)((m0 >> 3) + 1) * kWave];
-#pragma unroll
-                for (int k = 0; k < U; ++k) {
-                    const double4 sh = shift[wib][img[k]];
-                    const double dx = (qj[k].x - qi.x) - sh.x;
-                    const double dy = (qj[k].y - qi.y) - sh.y;
-                    const double dz = (qj[k].z - qi.z) - sh.z;
-                    const double r2 = dx * dx + dy * dy + dz * dz;
-                    if (m0 + k < nl && r2 < rc2) {
-                        const double inv = 1.0 / r2;
-                        const double inv3 = inv * inv * inv;
-                        const double f = (24.0 * inv3 - 48.0 * inv3 * inv3) * inv + c2x8;
-                        Fx += f * dx;
-                        Fy += f * dy;
-                        Fz += f * dz;
-                        if (ENERGY) pe += 2.0 * (inv3 * inv3 - inv3 + p.c2 * r2 + p.c0);
-                    }
-                }
-            }
-        } else {
-            const int4* __restrict__ u = d.u[sq];
-            const int4 ui = units3(qi, cc, g);  // own coordinate from the record: no extra load
-            const float ux = g.usc[0], uy = g.usc[1], uz = g.usc[2];
-            const float rc2 = p.rc2f, c2x8 = 8.0f * p.c2f;
-            float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f, pes = 0.f;
-            uint4 raw_next = nl > 0 ? l4[0] : make_uint4(0u, 0u, 0u, 0u);
-            for (int m0 = 0; m0 < nl; m0 += U) {
-                const uint4 raw = raw_next;
-                const uint32_t w[4] = {raw.x, raw.y, raw.z, raw.w};
-                uint32_t js[U], st[U];
-#pragma unroll
-                for (int k = 0; k < U; ++k) {
-                    const uint32_t e = (w[k >> 1] >> ((k & 1) * 16)) & 0xffffu;
-                    const bool ok = m0 + k < nl;
-                    st[k] = ok ? e >> kOffBits : 13u;
-                    js[k] = ok ? (lookup(st[k]) & kIdxMask) + (e & (kMaxCellCount - 1)) : (uint32_t)key;
-                }
-                int4 uj[U];
-#pragma unroll
-                for (int k = 0; k < U; ++k) uj[k] = u[js[k]];
-                if (m0 + U < nl) raw_next = l4[(size_t)((m0 >> 3) + 1) * kWave];
-                float bx = 0.f, by = 0.f, bz = 0.f;  // plain FP32 sum of this batch
-#pragma unroll
-                for (int k = 0; k < U; ++k) {
-                    const int4 sh = shift[wib][st[k]];
-                    // exact integer separation, one rounding to FP32, one scaling
-                    const float dx = (float)(uj[k].x - ui.x + sh.x) * ux;
-                    const float dy = (float)(uj[k].y - ui.y + sh.y) * uy;
-                    const float dz = (float)(uj[k].z - ui.z + sh.z) * uz;
-                    const float r2 = dx * dx + dy * dy + dz * dz;
-                    if (m0 + k < nl && r2 < rc2) {
-                        const float inv = __builtin_amdgcn_rcpf(r2);
-                        const float inv3 = inv * inv * inv;
-                        const float f = (24.0f * inv3 - 48.0f * inv3 * inv3) * inv + c2x8;
-                        bx += f * dx;
-                        by += f * dy;
-                        bz += f * dz;
-                        if (ENERGY) pes += 2.0f * (inv3 * inv3 - inv3 + p.c2f * r2 + p.c0f);
-                    }
-                }
-                kahan_add(sx, cx, bx);  // compensated across batches
-                kahan_add(sy, cy, by);
-                kahan_add(sz, cz, bz);
-            }
-            Fx = (double)sx - (double)cx;
-            Fy = (double)sy - (double)cy;
-            Fz = (double)sz - (double)cz;
-            pe = (double)pes;
-        }
-    };
-    if (active) {
-        if (tabled)
-            pair_loop(std::true_type{});
-        else
-            pair_loop(std::false_type{});
-    }
+__device__ __forceinline__ void force_finish(const Dev& d, const Params& p, const BoxGeom& g, int b, int lw, int key,
+                                             bool owner, const Pos& qi, uint32_t cc, int sq, int sp, double Fx,
+                                             double Fy, double Fz, double pe) {
+    const int l = lane_id();
     if (TPK > 1) {
 #pragma unroll
         for (int o = 1; o < TPK; o <<= 1) {
@@ -983,7 +859,6 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Params p) {
             if (ENERGY) pe += __shfl_xor(pe, o);
         }
     }
-    const bool owner = active && sub == 0;
     double ke = 0.0, w2 = 0.0, m2 = 0.0;
     if (MODE == kForceOnly) {
         if (owner) {
@@ -1040,6 +915,477 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Params p) {
             d.pe_part[lw] = ps;
         }
     }
+}
+
+// Algorithm 1 on the GPU.  PREC: MD_PREC_FP64 or MD_PREC_FP32_MIXED.
+// MODE: kForceOnly / kForceEnd / kForceMid.  ENERGY: per-wave KE and PE partials.
+// Each lane reads 8 list entries per 16-byte load and keeps 8 partner gathers in
+// flight (Algorithm 1's unrolling for latency hiding, in GPU form).  A list
+// entry names a stencil cell and a rank in it; the wavefront first tabulates, in
+// LDS, the 27 stencil cells of each distinct cell its keys live in: FP64 keeps
+// the start slot and the periodic image code, FP32-mixed the start slot and the
+// fixed-point stencil offset (one 16-byte record).  The cutoff test is a select,
+// not a branch (as Algorithm 1's mask w), and only a lane's last, partial chunk
+// of entries pays for an end-of-list check.
+constexpr int kHomeMax = 12;  // distinct key cells per wavefront served from LDS
+
+template <int PREC>
+struct ForceTab {
+    using Rec = uint32_t;  // FP64: start slot | image code << 27
+};
+template <>
+struct ForceTab<MD_PREC_FP32_MIXED> {
+    using Rec = int4;  // FP32-mixed: start slot, stencil offset o * uoff per axis
+};
+
+// Record of stencil cell s of the cell with packed coordinates cc.
+template <int PREC>
+__device__ __forceinline__ typename ForceTab<PREC>::Rec force_rec(const Dev& d, uint32_t cc, int s,
+                                                                  const BoxGeom& g) {
+    uint32_t img;
+    const int nc = stencil_cell(cc, s, g, &img);
+    if constexpr (PREC == MD_PREC_FP64) {
+        return (uint32_t)d.cell_start[nc] | (img << kIdxBits);
+    } else {
+        return make_int4(d.cell_start[nc], (s % 3 - 1) * g.uoff[0], ((s / 3) % 3 - 1) * g.uoff[1],
+                         (s / 9 - 1) * g.uoff[2]);
+    }
+}
+
+template <int PREC, int MODE, int TPK, bool ENERGY>
+__global__ __launch_bounds__(kBlock) void k_force(Dev d, Params p) {
+    constexpr int K = kWave / TPK;
+    constexpr int U = 8;  // entries per iteration (one 16-byte chunk)
+    constexpr bool MIX = PREC == MD_PREC_FP32_MIXED;
+    using Rec = typename ForceTab<PREC>::Rec;
+    __shared__ double4 shift[MIX ? 1 : kBlock / kWave][27];  // FP64: image term per code
+    __shared__ uint32_t home_cc[kBlock / kWave][kWave];
+    __shared__ Rec tab[kBlock / kWave][kHomeMax * 27];
+    const int l = lane_id(), wib = threadIdx.x >> 6, sub = l % TPK;
+    const int lw = xcd_block(blockIdx.x, gridDim.x) * 4 + wib;
+    const int nlw = p.nwave * TPK;
+    const bool wave_ok = lw < nlw;
+    const int b = __builtin_amdgcn_readfirstlane(wave_ok ? d.wave_box[(lw * K) >> 6] : 0);
+    if constexpr (!MIX) {
+        if (l < 27) shift[wib][l] = d.dshift[b * 27 + l];
+    }
+    __syncthreads();
+    if (!wave_ok) return;
+
+    const BoxGeom& g = d.geom[b];  // b is uniform: scalar loads
+    const int sq = d.st[b].sq, sp = d.st[b].sp;
+    const int key = lw * K + l / TPK;
+    const bool active = key - g.slot_off < g.npart;
+    const Pos qi = d.q[sq][active ? key : g.slot_off];
+    const uint32_t cc = active ? qi.cc : 0xffffffffu;
+
+    // distinct cells of this wavefront's keys (keys are sorted by cell)
+    const uint32_t cprev = __shfl_up(cc, TPK);
+    const bool head = active && sub == 0 && (l < TPK || cprev != cc);
+    const unsigned long long hm = __ballot(head);
+    const int nhome = __popcll(hm);
+    const int h = __popcll(hm & (l == 63 ? ~0ull : ((2ull << l) - 1ull))) - 1;
+    const bool tabled = nhome <= kHomeMax;  // uniform
+    if (tabled) {
+        if (head) home_cc[wib][h] = cc;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int idx = l; idx < nhome * 27; idx += kWave) {
+            const int hh = idx / 27;
+            tab[wib][idx] = force_rec<PREC>(d, home_cc[wib][hh], idx - hh * 27, g);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+
+    double Fx = 0.0, Fy = 0.0, Fz = 0.0, pe = 0.0;
+    // The pair loop, instantiated twice so the choice between the LDS table and
+    // direct lookups is made once per wavefront, outside the loop.
+    auto pair_loop = [&](auto tabled_c) {
+        constexpr bool TB = decltype(tabled_c)::value;
+        const int n_i = qi.cnt;
+        const int nl = n_i > sub ? (n_i - sub + TPK - 1) / TPK : 0;  // this lane's entries
+        const int nfull = nl >> 3, ntail = nl & 7;
+        const uint4* __restrict__ l4 = reinterpret_cast<const uint4*>(d.list + (size_t)lw * p.rows * kWave) + l;
+        const Rec* __restrict__ tb = tab[wib] + h * 27;
+        auto rec = [&](uint32_t s) -> Rec {
+            if constexpr (TB)
+                return tb[s];
+            else
+                return force_rec<PREC>(d, cc, (int)s, g);
+        };
+        // entry k of a chunk: stencil cell and rank (8 entries in 4 words)
+        auto ent_s = [](const uint4& raw, int k) -> uint32_t {
+            const uint32_t w = k < 2 ? raw.x : k < 4 ? raw.y : k < 6 ? raw.z : raw.w;
+            return (k & 1) ? w >> 27 : (w >> kOffBits) & 31u;
+        };
+        auto ent_r = [](const uint4& raw, int k) -> uint32_t {
+            const uint32_t w = k < 2 ? raw.x : k < 4 ? raw.y : k < 6 ? raw.z : raw.w;
+            return (k & 1) ? (w >> 16) & (kMaxCellCount - 1) : w & (kMaxCellCount - 1);
+        };
+        uint4 raw_next = nl > 0 ? l4[0] : make_uint4(0u, 0u, 0u, 0u);
+        if constexpr (!MIX) {
+            const Pos* __restrict__ q = d.q[sq];
+            const double rc2 = p.rc2, c2x8 = 8.0 * p.c2;
+            // CHK: the lane's last chunk, entries from `valid` on are padding
+            auto chunk = [&](int c, auto chk_c, int valid) {
+                constexpr bool CHK = decltype(chk_c)::value;
+                const uint4 raw = raw_next;
+                uint32_t js[U], img[U];
+#pragma unroll
+                for (int k = 0; k < U; ++k) {
+                    const bool ok = !CHK || k < valid;
+                    const uint32_t t = rec(ok ? ent_s(raw, k) : 13u);
+                    js[k] = ok ? (t & kIdxMask) + ent_r(raw, k) : (uint32_t)key;
+                    img[k] = ok ? t >> kIdxBits : 13u;
+                }
+                Pos qj[U];
+#pragma unroll
+                for (int k = 0; k < U; ++k)  // 32-bit byte offsets: slots < 2^27
+                    qj[k] = *reinterpret_cast<const Pos*>(reinterpret_cast<const char*>(q) + (js[k] << 5));
+                // next chunk's entries, issued after the gathers: the load counter
+                // retires in order, so this load does not delay them
+                if (!CHK && (c + 1 < nfull || ntail)) raw_next = l4[(size_t)(c + 1) * kWave];
+#pragma unroll
+                for (int k = 0; k < U; ++k) {
+                    const double4 sh = shift[wib][img[k]];
+                    const double dx = (qj[k].x - qi.x) - sh.x;
+                    const double dy = (qj[k].y - qi.y) - sh.y;
+                    const double dz = (qj[k].z - qi.z) - sh.z;
+                    const double r2 = dx * dx + dy * dy + dz * dz;
+                    const bool in = (!CHK || k < valid) && r2 < rc2;
+                    const double inv = 1.0 / r2;
+                    const double inv3 = inv * inv * inv;
+                    const double f = in ? (24.0 * inv3 - 48.0 * inv3 * inv3) * inv + c2x8 : 0.0;
+                    Fx += f * dx;
+                    Fy += f * dy;
+                    Fz += f * dz;
+                    if (ENERGY) pe += in ? 2.0 * (inv3 * inv3 - inv3 + p.c2 * r2 + p.c0) : 0.0;
+                }
+            };
+            for (int c = 0; c < nfull; ++c) chunk(c, std::false_type{}, U);
+            if (ntail) chunk(nfull, std::true_type{}, ntail);
+        } else {
+            const int4* __restrict__ u = d.u[sq];
+            const int4 ui = units3(qi, cc, g);  // own coordinate from the record: no extra load
+            const int nux = -ui.x, nuy = -ui.y, nuz = -ui.z;
+            // lengths stay in fixed-point units: r^2 in units^2, 1/r^2 rescaled once
+            const float rc2u = g.rc2u, lam2inv = g.lam2inv, lam2 = g.lam * g.lam, c2x8 = 8.0f * p.c2f;
+            float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f, pes = 0.f;
+            auto chunk = [&](int c, auto chk_c, int valid) {
+                constexpr bool CHK = decltype(chk_c)::value;
+                const uint4 raw = raw_next;
+                uint32_t st[U], js[U];
+#pragma unroll
+                for (int k = 0; k < U; ++k) {
+                    const bool ok = !CHK || k < valid;
+                    st[k] = ok ? ent_s(raw, k) : 13u;
+                    js[k] = ok ? (uint32_t)rec(st[k]).x + ent_r(raw, k) : (uint32_t)key;
+                }
+                int4 uj[U];
+#pragma unroll
+                for (int k = 0; k < U; ++k)  // 32-bit byte offsets: slots < 2^27
+                    uj[k] = *reinterpret_cast<const int4*>(reinterpret_cast<const char*>(u) + (js[k] << 4));
+                if (!CHK && (c + 1 < nfull || ntail)) raw_next = l4[(size_t)(c + 1) * kWave];
+                // the stencil offsets are read again below rather than held across the gathers
+                __builtin_amdgcn_sched_barrier(0);
+                float bx = 0.f, by = 0.f, bz = 0.f;  // plain FP32 sum of this batch
+#pragma unroll
+                for (int k = 0; k < U; ++k) {
+                    const int4 rk = rec(st[k]);
+                    // exact integer separation in units, one rounding to FP32
+                    const float dx = (float)(uj[k].x + rk.y + nux);
+                    const float dy = (float)(uj[k].y + rk.z + nuy);
+                    const float dz = (float)(uj[k].z + rk.w + nuz);
+                    const float r2 = dx * dx + dy * dy + dz * dz;
+                    const bool in = (!CHK || k < valid) && r2 < rc2u;
+                    const float inv = __builtin_amdgcn_rcpf(r2) * lam2inv;  // 1/r^2 in length units
+                    const float inv3 = inv * inv * inv;
+                    const float f = in ? (inv3 * inv) * (24.0f - 48.0f * inv3) + c2x8 : 0.0f;
+                    bx += f * dx;
+                    by += f * dy;
+                    bz += f * dz;
+                    if (ENERGY) pes += in ? 2.0f * (inv3 * inv3 - inv3 + p.c2f * (r2 * lam2) + p.c0f) : 0.0f;
+                }
+                kahan_add(sx, cx, bx);  // compensated across batches
+                kahan_add(sy, cy, by);
+                kahan_add(sz, cz, bz);
+            };
+            for (int c = 0; c < nfull; ++c) chunk(c, std::false_type{}, U);
+            if (ntail) chunk(nfull, std::true_type{}, ntail);
+            const double lam = (double)g.lam;  // units back to lengths (a power of two)
+            Fx = ((double)sx - (double)cx) * lam;
+            Fy = ((double)sy - (double)cy) * lam;
+            Fz = ((double)sz - (double)cz) * lam;
+            pe = (double)pes;
+        }
+    };
+    if (active) {
+        if (tabled)
+            pair_loop(std::true_type{});
+        else
+            pair_loop(std::false_type{});
+    }
+    force_finish<PREC, MODE, TPK, ENERGY>(d, p, g, b, lw, key, active && sub == 0, qi, cc, sq, sp, Fx, Fy, Fz, pe);
+}
+
+// FP32-mixed force pass with LDS-staged partner tiles (one lane per key).  The
+// 256 keys of a block live in one or two rows of cells; every partner of theirs
+// lies in the 9 neighbouring rows (dy, dz in {-1,0,1}) of each home row, over the
+// x range of the home cells widened by one cell each side (periodic wrap adds at
+// most one cell per end).  Those row pieces are contiguous runs of slots: the
+// block copies them once, coalesced, into LDS, already shifted into the home
+// row's frame (fixed-point units; x measured from the first home cell, y and z
+// from the home row), so a pair separation is one integer subtraction with
+// wrap-around and partner reads are LDS reads.  Blocks whose keys span more rows,
+// two boxes, or more than kTileCap partners, and wavefronts with more than
+// kHomeMax home cells, gather from global memory instead.
+constexpr int kTileCap = 3072;    // staged partner records per block
+constexpr int kTileParts = 64;    // pieces: 2 home rows x 9 rows x (left wrap, main, right wrap)
+constexpr int kTileChunks = 128;  // 64-record copy chunks
+
+template <int MODE, bool ENERGY>
+__global__ __launch_bounds__(kBlock) void k_force_tile(Dev d, Params p) {
+    constexpr int U = 8;
+    __shared__ int32_t tx[kTileCap], ty[kTileCap], tz[kTileCap];
+    __shared__ uint16_t ltab[kBlock / kWave][kHomeMax * 27];
+    __shared__ uint32_t home_cc[kBlock / kWave][kWave];
+    __shared__ int32_t pt_s0[kTileParts], pt_len[kTileParts], pt_lds[kTileParts];
+    __shared__ int32_t pt_ay[kTileParts], pt_az[kTileParts], pt_xk[kTileParts];
+    __shared__ int32_t ch_part[kTileChunks], ch_off[kTileChunks];
+    __shared__ int32_t blk[8];  // tiled flag, chunk count, x of the first home cell per home row, first home row
+    const int l = lane_id(), wib = threadIdx.x >> 6;
+    const int lw0 = xcd_block(blockIdx.x, gridDim.x) * 4;
+    const int lw = lw0 + wib;
+    const bool wave_ok = lw < p.nwave;
+    const int b = __builtin_amdgcn_readfirstlane(wave_ok ? d.wave_box[lw] : 0);
+    const BoxGeom& g = d.geom[b];  // b is uniform: scalar loads
+    const int sq = d.st[b].sq, sp = d.st[b].sp;
+    const int nx = g.n[0], ny = g.n[1];
+
+    // ---- block geometry and the piece table (wavefront 0)
+    if (wib == 0) {
+        bool ok = lw0 + 3 < p.nwave && d.wave_box[lw0 + 3] == b;  // four full wavefronts of one box
+        const int kf = lw0 * kWave, kl = min(kf + kBlock - 1, g.slot_off + g.npart - 1);
+        const uint32_t ccf = __builtin_amdgcn_readfirstlane(d.q[sq][kf].cc);
+        const uint32_t ccl = __builtin_amdgcn_readfirstlane(d.q[sq][kl].cc);
+        const int cxf = ccf & 1023, cyf = (ccf >> 10) & 1023, czf = ccf >> 20;
+        const int cxl = ccl & 1023, cyl = (ccl >> 10) & 1023, czl = ccl >> 20;
+        const int rowf = czf * ny + cyf, nhr = czl * ny + cyl - rowf + 1;
+        const int xa0 = cxf, xb0 = nhr == 1 ? cxl : nx - 1, xa1 = 0, xb1 = cxl;
+        ok = ok && (nhr == 1 || nhr == 2) && xb0 - xa0 + 3 <= nx && (nhr == 1 || xb1 - xa1 + 3 <= nx);
+        int len = 0, s0 = 0, ay = 0, az = 0, xk = 0;
+        if (ok && l < nhr * 27) {
+            const int hr = l / 27, rr = (l % 27) / 3, side = l % 3;
+            const int dy = rr % 3 - 1, dz = rr / 3 - 1;
+            const int xa = hr == 0 ? xa0 : xa1, xb = hr == 0 ? xb0 : xb1;
+            int y = (hr == 0 ? cyf : cyl) + dy, z = (hr == 0 ? czf : czl) + dz;
+            y = y < 0 ? y + ny : (y >= ny ? y - ny : y);
+            z = z < 0 ? z + g.n[2] : (z >= g.n[2] ? z - g.n[2] : z);
+            // side 0: virtual x = -1 is real nx - 1; side 2: virtual x = nx is real 0
+            const bool has = side == 1 || (side == 0 && xa == 0) || (side == 2 && xb == nx - 1);
+            if (has) {
+                const int x0 = side == 0 ? nx - 1 : (side == 2 ? 0 : max(xa - 1, 0));
+                const int x1 = side == 0 ? nx - 1 : (side == 2 ? 0 : min(xb + 1, nx - 1));
+                const int rowc = g.cell_off + (z * ny + y) * nx;
+                s0 = d.cell_start[rowc + x0];
+                len = d.cell_start[rowc + x1] + d.cell_cnt[rowc + x1] - s0;
+                ay = dy * g.uoff[1];
+                az = dz * g.uoff[2];
+                xk = (side == 0 ? -nx : (side == 2 ? nx : 0)) - xa;
+            }
+        }
+        const int incl = wave_incl_scan(len);
+        const int nchk = (len + kWave - 1) >> 6;
+        const int cincl = wave_incl_scan(nchk);
+        const int T = __builtin_amdgcn_readlane(incl, 63), NC = __builtin_amdgcn_readlane(cincl, 63);
+        ok = ok && T <= kTileCap && NC <= kTileChunks;
+        if (ok) {
+            pt_s0[l] = s0;
+            pt_len[l] = len;
+            pt_lds[l] = incl - len;
+            pt_ay[l] = ay;
+            pt_az[l] = az;
+            pt_xk[l] = xk;
+            for (int c = 0; c < nchk; ++c) {
+                ch_part[cincl - nchk + c] = l;
+                ch_off[cincl - nchk + c] = c * kWave;
+            }
+        }
+        if (l == 0) {
+            blk[0] = ok ? 1 : 0;
+            blk[1] = NC;
+            blk[2] = xa0;
+            blk[3] = xa1;
+            blk[4] = rowf;
+        }
+    }
+    __syncthreads();
+    const bool tiled = blk[0] != 0;  // uniform over the block
+    if (tiled) {
+        // ---- copy the pieces: wavefront w takes chunks w, w + 4, ..., 8 loads in flight
+        const int NC = blk[1];
+        const int4* __restrict__ u = d.u[sq];
+        const uint32_t uox = (uint32_t)g.uoff[0];
+        for (int c0 = wib; c0 < NC; c0 += 4 * 8) {
+            int4 v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int c = c0 + 4 * k;
+                if (c < NC) {
+                    const int pp = ch_part[c], i = ch_off[c] + l;
+                    if (i < pt_len[pp]) v[k] = u[pt_s0[pp] + i];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int c = c0 + 4 * k;
+                if (c < NC) {
+                    const int pp = ch_part[c], i = ch_off[c] + l;
+                    if (i < pt_len[pp]) {
+                        const int li = pt_lds[pp] + i;
+                        // x in the home row's frame, modulo 2^32 (differences stay exact)
+                        tx[li] = (int)((uint32_t)v[k].x + (uint32_t)(v[k].w + pt_xk[pp]) * uox);
+                        ty[li] = v[k].y + pt_ay[pp];
+                        tz[li] = v[k].z + pt_az[pp];
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (!wave_ok) return;
+
+    const int key = lw * kWave + l;
+    const bool active = key - g.slot_off < g.npart;
+    const Pos qi = d.q[sq][active ? key : g.slot_off];
+    const uint32_t cc = active ? qi.cc : 0xffffffffu;
+    const uint32_t cprev = __shfl_up(cc, 1);
+    const bool head = active && (l == 0 || cprev != cc);
+    const unsigned long long hm = __ballot(head);
+    const int nhome = __popcll(hm);
+    const int h = __popcll(hm & (l == 63 ? ~0ull : ((2ull << l) - 1ull))) - 1;
+    const bool use_tile = tiled && nhome <= kHomeMax;  // uniform over the wavefront
+    if (use_tile) {
+        if (head) home_cc[wib][h] = cc;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int idx = l; idx < nhome * 27; idx += kWave) {
+            const int hh = idx / 27, st = idx - hh * 27;
+            const uint32_t hc = home_cc[wib][hh];
+            const int hx = hc & 1023, hy = (hc >> 10) & 1023, hz = hc >> 20;
+            const int hr = hz * ny + hy == blk[4] ? 0 : 1;
+            const int v = hx + st % 3 - 1;
+            const int pp = hr * 27 + (st / 3) * 3 + (v < 0 ? 0 : (v >= nx ? 2 : 1));
+            uint32_t img;
+            const int nc = stencil_cell(hc, st, g, &img);
+            ltab[wib][idx] = (uint16_t)(pt_lds[pp] + d.cell_start[nc] - pt_s0[pp]);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+
+    double Fx = 0.0, Fy = 0.0, Fz = 0.0, pe = 0.0;
+    if (active) {
+        const int nl = qi.cnt;
+        const int nfull = nl >> 3, ntail = nl & 7;
+        const uint4* __restrict__ l4 = reinterpret_cast<const uint4*>(d.list + (size_t)lw * p.rows * kWave) + l;
+        auto ent_s = [](const uint4& raw, int k) -> uint32_t {
+            const uint32_t w = k < 2 ? raw.x : k < 4 ? raw.y : k < 6 ? raw.z : raw.w;
+            return (k & 1) ? w >> 27 : (w >> kOffBits) & 31u;
+        };
+        auto ent_r = [](const uint4& raw, int k) -> uint32_t {
+            const uint32_t w = k < 2 ? raw.x : k < 4 ? raw.y : k < 6 ? raw.z : raw.w;
+            return (k & 1) ? (w >> 16) & (kMaxCellCount - 1) : w & (kMaxCellCount - 1);
+        };
+        const int4 ui = units3(qi, cc, g);
+        const float rc2u = g.rc2u, lam2inv = g.lam2inv, lam2 = g.lam * g.lam, c2x8 = 8.0f * p.c2f;
+        float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f, pes = 0.f;
+        uint4 raw_next = nl > 0 ? l4[0] : make_uint4(0u, 0u, 0u, 0u);
+        // one chunk of 8 entries: fetch the 8 partners, then the pair math on exact
+        // integer separations (one rounding to FP32 each)
+        auto pairs = [&](auto tile_c) {
+            constexpr bool TL = decltype(tile_c)::value;
+            const uint16_t* __restrict__ tb = ltab[wib] + h * 27;
+            // this key in the frame of the staged partners
+            const int hr = (int)((cc >> 20) * ny + ((cc >> 10) & 1023)) == blk[4] ? 0 : 1;
+            const uint32_t kx = (uint32_t)ui.x + (uint32_t)(ui.w - blk[2 + hr]) * (uint32_t)g.uoff[0];
+            const int4* __restrict__ u = d.u[sq];
+            auto chunk = [&](int c, auto chk_c, int valid) {
+                constexpr bool CHK = decltype(chk_c)::value;
+                const uint4 raw = raw_next;
+                int dxi[U], dyi[U], dzi[U];
+                if constexpr (TL) {
+                    int li[U];
+#pragma unroll
+                    for (int k = 0; k < U; ++k) {
+                        const bool ok = !CHK || k < valid;
+                        li[k] = (int)tb[ok ? ent_s(raw, k) : 13u] + (ok ? (int)ent_r(raw, k) : 0);
+                    }
+                    if (!CHK && (c + 1 < nfull || ntail)) raw_next = l4[(size_t)(c + 1) * kWave];
+#pragma unroll
+                    for (int k = 0; k < U; ++k) {
+                        dxi[k] = (int)((uint32_t)tx[li[k]] - kx);
+                        dyi[k] = ty[li[k]] - ui.y;
+                        dzi[k] = tz[li[k]] - ui.z;
+                    }
+                } else {
+                    uint32_t st[U], js[U];
+#pragma unroll
+                    for (int k = 0; k < U; ++k) {
+                        const bool ok = !CHK || k < valid;
+                        st[k] = ok ? ent_s(raw, k) : 13u;
+                        js[k] = ok ? (uint32_t)force_rec<MD_PREC_FP32_MIXED>(d, cc, (int)st[k], g).x + ent_r(raw, k)
+                                   : (uint32_t)key;
+                    }
+                    int4 uj[U];
+#pragma unroll
+                    for (int k = 0; k < U; ++k) uj[k] = u[js[k]];
+                    if (!CHK && (c + 1 < nfull || ntail)) raw_next = l4[(size_t)(c + 1) * kWave];
+#pragma unroll
+                    for (int k = 0; k < U; ++k) {
+                        const int so = (int)st[k];
+                        dxi[k] = uj[k].x - ui.x + (so % 3 - 1) * g.uoff[0];
+                        dyi[k] = uj[k].y - ui.y + ((so / 3) % 3 - 1) * g.uoff[1];
+                        dzi[k] = uj[k].z - ui.z + (so / 9 - 1) * g.uoff[2];
+                    }
+                }
+                float bx = 0.f, by = 0.f, bz = 0.f;  // plain FP32 sum of this batch
+#pragma unroll
+                for (int k = 0; k < U; ++k) {
+                    const float dx = (float)dxi[k], dy = (float)dyi[k], dz = (float)dzi[k];
+                    const float r2 = dx * dx + dy * dy + dz * dz;
+                    const bool in = (!CHK || k < valid) && r2 < rc2u;
+                    const float inv = __builtin_amdgcn_rcpf(r2) * lam2inv;  // 1/r^2 in length units
+                    const float inv3 = inv * inv * inv;
+                    const float f = in ? (inv3 * inv) * (24.0f - 48.0f * inv3) + c2x8 : 0.0f;
+                    bx += f * dx;
+                    by += f * dy;
+                    bz += f * dz;
+                    if (ENERGY) pes += in ? 2.0f * (inv3 * inv3 - inv3 + p.c2f * (r2 * lam2) + p.c0f) : 0.0f;
+                }
+                kahan_add(sx, cx, bx);  // compensated across batches
+                kahan_add(sy, cy, by);
+                kahan_add(sz, cz, bz);
+            };
+            for (int c = 0; c < nfull; ++c) chunk(c, std::false_type{}, U);
+            if (ntail) chunk(nfull, std::true_type{}, ntail);
+        };
+        if (use_tile)
+            pairs(std::true_type{});
+        else
+            pairs(std::false_type{});
+        const double lam = (double)g.lam;  // units back to lengths (a power of two)
+        Fx = ((double)sx - (double)cx) * lam;
+        Fy = ((double)sy - (double)cy) * lam;
+        Fz = ((double)sz - (double)cz) * lam;
+        pe = (double)pes;
+    }
+    force_finish<MD_PREC_FP32_MIXED, MODE, 1, ENERGY>(d, p, g, b, lw, key, active, qi, cc, sq, sp, Fx, Fy, Fz, pe);
 }
 
 // First half kick and drift from stored forces (start of a chunk of steps).
@@ -1254,8 +1600,26 @@ static void launch_force_pt(const Dev& d, const Params& p, int mode, bool energy
     }
 }
 
+static void launch_force_tile(const Dev& d, const Params& p, int mode, bool energy, hipStream_t s) {
+    const int nb = (p.nwave + 3) / 4;
+    if (mode == kForceOnly) {
+        if (energy)
+            k_force_tile<kForceOnly, true><<<nb, kBlock, 0, s>>>(d, p);
+        else
+            k_force_tile<kForceOnly, false><<<nb, kBlock, 0, s>>>(d, p);
+    } else if (mode == kForceEnd) {
+        if (energy)
+            k_force_tile<kForceEnd, true><<<nb, kBlock, 0, s>>>(d, p);
+        else
+            k_force_tile<kForceEnd, false><<<nb, kBlock, 0, s>>>(d, p);
+    } else {
+        k_force_tile<kForceMid, false><<<nb, kBlock, 0, s>>>(d, p);
+    }
+}
+
 template <int PREC>
 static void launch_force_p(const Dev& d, const Params& p, int mode, bool energy, hipStream_t s) {
+    if (PREC == MD_PREC_FP32_MIXED && p.tpk == 1 && p.tile) return launch_force_tile(d, p, mode, energy, s);
     switch (p.tpk) {
         case 1: launch_force_pt<PREC, 1>(d, p, mode, energy, s); break;
         case 2: launch_force_pt<PREC, 2>(d, p, mode, energy, s); break;

@@ -60,6 +60,7 @@ BAD = [
     dict(cutoff=9),
     dict(rebuild=5),
     dict(flags=1 << 7),
+    dict(flags=4 | 8),                    # tile on and off together
     dict(threads_per_key=3),
     dict(list_cap=-1),
     dict(box=(3000.0, 20.0, 20.0)),       # > 1023 cells on one axis

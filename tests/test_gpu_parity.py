@@ -164,6 +164,75 @@ def test_forces_mixed(name, tpk):
     assert pe == pytest.approx(per, rel=1e-6, abs=1e-9)
 
 
+def tile_case(name):
+    """Boxes for the FP32-mixed force pass with LDS-staged partner tiles: wide
+    rows (26-30 cells) so that a block's keys span one or two rows, with x-wrap
+    pieces; a dilute box where a wavefront's keys span more home cells than the
+    tile table holds; and a small box where blocks span many rows (fallback)."""
+    def grid(L, rho, seed):  # jittered grid with about rho per unit volume, spacing per axis ~ equal
+        Lv = np.asarray(L, dtype=np.float64)
+        a = rho ** (-1.0 / 3.0)
+        m = np.maximum(np.rint(Lv / a).astype(int), 1)
+        idx = np.indices(tuple(m[::-1])).reshape(3, -1).T[:, ::-1].astype(np.float64)
+        sp = Lv / m
+        q = (idx + 0.5) * sp + rng(seed).uniform(-0.15, 0.15, size=idx.shape) * sp
+        return np.ascontiguousarray(np.mod(q, Lv))
+    if name == "rows26":  # ~11 per cell, blocks over one or two rows of 26 cells
+        L = (26 * 2.85, 3 * 2.85 + 0.1, 4 * 2.85 + 0.2)
+        return grid(L, 0.48, 31), L
+    if name == "dilute":  # ~4 per cell: a block spans one or two rows, a wavefront 16 home cells
+        L = (70 * 2.85, 3 * 2.85, 3 * 2.85)
+        return grid(L, 0.173, 32), L
+    if name == "small":
+        q, _, L = case("jitter_ragged")
+        return q, L
+    raise KeyError(name)
+
+
+@pytest.mark.parametrize("name", ["rows26", "dilute", "small"])
+def test_forces_mixed_tiles_equal_global_gathers(name):
+    """The staged-tile pass computes the same integer separations and FP32
+    arithmetic in the same order as the global-gather pass: forces equal bit for
+    bit, and both meet the FP32-mixed bar against the oracle."""
+    b = B()
+    q, L = tile_case(name)
+    v = inputs.maxwell_boltzmann(q.shape[0], 1.0, 1.0, rng(7))
+    F = {}
+    for flag in (b.MD_F_TILE_ON, b.MD_F_TILE_OFF):
+        with make_ctx(q, v, L, precision=1, threads_per_key=1, flags=flag) as c:
+            F[flag] = c.compute_forces().cpu().numpy()
+            e = c.energy()
+        if flag == b.MD_F_TILE_ON:
+            e_on = e
+        else:
+            e_off = e
+    np.testing.assert_array_equal(F[b.MD_F_TILE_ON], F[b.MD_F_TILE_OFF])
+    assert e_on == e_off
+    Fr, _, A = oracle.forces(q, L, 2.5, 0.3)
+    assert norm_err(F[b.MD_F_TILE_ON], Fr, A) <= 1e-5
+
+
+def test_steps_mixed_tiles_equal_global_gathers():
+    """Stepping with the staged-tile pass (drift, kicks, re-encoding, rebuilds)
+    follows the global-gather pass bit for bit."""
+    b = B()
+    q, L = tile_case("rows26")
+    v = inputs.maxwell_boltzmann(q.shape[0], 1.0, 1.0, rng(8))
+    out = {}
+    for flag in (b.MD_F_TILE_ON, b.MD_F_TILE_OFF):
+        with make_ctx(q, v, L, precision=1, threads_per_key=1, flags=flag) as c:
+            c.step(60, 10)
+            pos, vel = c.get_state()
+            ke, pe = c.energy_series()
+            out[flag] = (pos.cpu().numpy(), vel.cpu().numpy(), ke, pe, c.stats()["rebuilds"])
+    a, t = out[b.MD_F_TILE_ON], out[b.MD_F_TILE_OFF]
+    np.testing.assert_array_equal(a[0], t[0])
+    np.testing.assert_array_equal(a[1], t[1])
+    np.testing.assert_array_equal(a[2], t[2])
+    np.testing.assert_array_equal(a[3], t[3])
+    assert a[4] == t[4] and a[4] > 0
+
+
 @pytest.mark.parametrize("mode", [1, 2])
 def test_forces_other_cutoff_schemes_fp64(mode):
     q, v, L = case("jitter_ragged")
