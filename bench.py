@@ -76,9 +76,10 @@ def measured_traffic():
         return None
 
 
-def run_gpu(B, torch, w, precision, steps, warmup, tpk=0):
+def run_gpu(B, torch, w, precision, steps, warmup, tpk=0, flags=0):
     stream = torch.cuda.Stream()
-    p = B.make_params(w.n, w.box, rc=w.rc, skin=w.skin, dt=w.dt, precision=precision, threads_per_key=tpk)
+    p = B.make_params(w.n, w.box, rc=w.rc, skin=w.skin, dt=w.dt, precision=precision, threads_per_key=tpk,
+                      flags=flags)
     with torch.cuda.stream(stream):
         ctx = B.Context(p, stream=stream)
         ctx.set_state(w.pos, w.vel)
@@ -334,6 +335,8 @@ def main():
     ap.add_argument("--baseline-boxes", type=int, default=256)
     ap.add_argument("--baseline-steps", type=int, default=100)
     ap.add_argument("--tune-cache", default=None)
+    ap.add_argument("--tile", choices=["auto", "on", "off"], default="auto",
+                    help="FP32-mixed force pass with LDS-staged partner tiles")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -364,7 +367,8 @@ def main():
     w = inputs.fcc_workload("fcc%d^3_rho0.5" % args.ncell, args.ncell, seed=3, nsteps=args.steps)
     print("bench: %s, N = %d, L = %g, %d warm-up + %d timed steps" % (w.name, w.n, w.box[0], args.warmup,
                                                                        args.steps), file=sys.stderr, flush=True)
-    mixed = run_gpu(B, torch, w, B.MD_PREC_FP32_MIXED, args.steps, args.warmup, args.tpk)
+    tile_flag = {"auto": 0, "on": B.MD_F_TILE_ON, "off": B.MD_F_TILE_OFF}[args.tile]
+    mixed = run_gpu(B, torch, w, B.MD_PREC_FP32_MIXED, args.steps, args.warmup, args.tpk, tile_flag)
     print("bench: FP32-mixed %.3f ms/step" % mixed["ms_per_step"], file=sys.stderr, flush=True)
     fp64 = None
     if not args.no_fp64:

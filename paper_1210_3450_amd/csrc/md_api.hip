@@ -336,7 +336,7 @@ void params_refresh(md_ctx* c) {
     // Staged tiles pay off when a block's 256 keys span at most two rows of cells
     // and their partners fit the tile (about 9 * 256 partners per key row, at most
     // 20 particles per cell); otherwise the force pass gathers from global memory.
-    bool tile = p.precision == MD_PREC_FP32_MIXED;
+    bool tile = p.precision == MD_PREC_FP32_MIXED && kTileByDefault;
     for (const BoxGeom& g : c->geom) {
         const double ppc = (double)g.npart / (double)g.ncell;
         tile = tile && ppc <= 20.0 && (double)g.n[0] >= (double)kBlock / ppc + 3.0;
@@ -650,7 +650,10 @@ md_status create_impl(const md_params* boxes, int32_t nbox, void* stream, md_ctx
     }
     layout(c);
     int tpk = c->prm.threads_per_key;
-    if (tpk == 0) tpk = c->ntotal < 262144 ? 4 : 1;
+    // default layout (md_autotune measures instead): small systems need more lanes
+    // per key to fill the chip; large ones are bound by partner gathers, where the
+    // FP64 path's 32-byte records gain from two lanes reading adjacent entries
+    if (tpk == 0) tpk = c->ntotal < 262144 ? 4 : (c->prm.precision == MD_PREC_FP64 ? 2 : 1);
     c->P.tpk = tpk;
     params_refresh(c);
     if ((s = alloc_all(c)) != MD_OK || (s = upload_geometry(c)) != MD_OK ||

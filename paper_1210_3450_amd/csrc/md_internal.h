@@ -45,6 +45,7 @@ constexpr int kOffBits = 11;             // list entry: partner rank within its 
 constexpr int kMaxCellCount = 1 << kOffBits;
 constexpr int kStripes = 1024;           // slots per box for per-step maxima
 constexpr int kStripeStride = 16;        // 128 bytes between slots
+constexpr bool kTileByDefault = false;   // staged-tile force pass chosen from the geometry
 
 // Position record of one slot.  cc and cnt ride in the 8 bytes a double4
 // would leave unused, so streaming a key's position also brings its cell and

@@ -1149,44 +1149,83 @@ constexpr int kTileChunks = 128;  // 64-record copy chunks
 template <int MODE, bool ENERGY>
 __global__ __launch_bounds__(kBlock) void k_force_tile(Dev d, Params p) {
     constexpr int U = 8;
+    constexpr int kTabPer = (kHomeMax * 27 + kWave - 1) / kWave;  // table entries per lane
     __shared__ int32_t tx[kTileCap], ty[kTileCap], tz[kTileCap];
     __shared__ uint16_t ltab[kBlock / kWave][kHomeMax * 27];
-    __shared__ uint32_t home_cc[kBlock / kWave][kWave];
-    __shared__ int32_t pt_s0[kTileParts], pt_len[kTileParts], pt_lds[kTileParts];
+    __shared__ uint32_t home_cc[kBlock / kWave][kHomeMax];
+    __shared__ int32_t pt_s0[kTileParts], pt_len[kTileParts], pt_base[kTileParts];
     __shared__ int32_t pt_ay[kTileParts], pt_az[kTileParts], pt_xk[kTileParts];
     __shared__ int32_t ch_part[kTileChunks], ch_off[kTileChunks];
-    __shared__ int32_t blk[8];  // tiled flag, chunk count, x of the first home cell per home row, first home row
+    __shared__ int32_t blk[4];  // tiled flag, chunk count, first home row, x of the first home cell
     const int l = lane_id(), wib = threadIdx.x >> 6;
     const int lw0 = xcd_block(blockIdx.x, gridDim.x) * 4;
     const int lw = lw0 + wib;
     const bool wave_ok = lw < p.nwave;
-    const int b = __builtin_amdgcn_readfirstlane(wave_ok ? d.wave_box[lw] : 0);
-    const BoxGeom& g = d.geom[b];  // b is uniform: scalar loads
-    const int sq = d.st[b].sq, sp = d.st[b].sp;
-    const int nx = g.n[0], ny = g.n[1];
 
-    // ---- block geometry and the piece table (wavefront 0)
+    // this wavefront's keys, their box and their home cells
+    const int b = __builtin_amdgcn_readfirstlane(d.wave_box[wave_ok ? lw : lw0]);
+    const BoxGeom& g = d.geom[b];  // b is uniform: scalar loads
+    const int sq = d.st[b].sq;
+    const int nx = g.n[0], ny = g.n[1];
+    const int key = lw * kWave + l;
+    const bool active = wave_ok && key - g.slot_off < g.npart;
+    const Pos qi = d.q[sq][active ? key : g.slot_off];
+    const uint32_t cc = active ? qi.cc : 0xffffffffu;
+    const uint32_t cprev = __shfl_up(cc, 1);
+    const bool head = active && (l == 0 || cprev != cc);
+    const unsigned long long hm = __ballot(head);
+    const int nhome = __popcll(hm);
+    const int h = __popcll(hm & (l == 63 ? ~0ull : ((2ull << l) - 1ull))) - 1;
+    const bool few_homes = nhome <= kHomeMax;  // uniform over the wavefront
+    // stencil-cell starts for this wavefront's table, fetched while the block
+    // geometry is worked out: tcs = start slot, tpp = piece without the home row
+    // term, trow = the home cell's row
+    int tcs[kTabPer], tpp[kTabPer], trow[kTabPer];
+    if (few_homes) {
+        if (head) home_cc[wib][h] = cc;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int k = 0; k < kTabPer; ++k) {
+            const int idx = l + k * kWave;
+            tpp[k] = 0;
+            tcs[k] = 0;
+            trow[k] = 0;
+            if (idx < nhome * 27) {
+                const int hh = idx / 27, st = idx - hh * 27;
+                const uint32_t hc = home_cc[wib][hh];
+                const int v = (int)(hc & 1023) + st % 3 - 1;
+                tpp[k] = (st / 3) * 3 + (v < 0 ? 0 : (v >= nx ? 2 : 1));
+                trow[k] = (int)(hc >> 20) * ny + (int)((hc >> 10) & 1023);
+                uint32_t img;
+                tcs[k] = d.cell_start[stencil_cell(hc, st, g, &img)];
+            }
+        }
+    }
+
+    // ---- block geometry and the piece table (wavefront 0); piece lane
+    // hr * 27 + rr * 3 + side = (home row hr, stencil row rr, side)
     if (wib == 0) {
         bool ok = lw0 + 3 < p.nwave && d.wave_box[lw0 + 3] == b;  // four full wavefronts of one box
         const int kf = lw0 * kWave, kl = min(kf + kBlock - 1, g.slot_off + g.npart - 1);
         const uint32_t ccf = __builtin_amdgcn_readfirstlane(d.q[sq][kf].cc);
         const uint32_t ccl = __builtin_amdgcn_readfirstlane(d.q[sq][kl].cc);
-        const int cxf = ccf & 1023, cyf = (ccf >> 10) & 1023, czf = ccf >> 20;
+        const int cyf = (ccf >> 10) & 1023, czf = ccf >> 20;
         const int cxl = ccl & 1023, cyl = (ccl >> 10) & 1023, czl = ccl >> 20;
         const int rowf = czf * ny + cyf, nhr = czl * ny + cyl - rowf + 1;
-        const int xa0 = cxf, xb0 = nhr == 1 ? cxl : nx - 1, xa1 = 0, xb1 = cxl;
-        ok = ok && (nhr == 1 || nhr == 2) && xb0 - xa0 + 3 <= nx && (nhr == 1 || xb1 - xa1 + 3 <= nx);
+        const int xa0 = ccf & 1023, xb0 = nhr == 1 ? cxl : nx - 1, xb1 = cxl;  // home row 1 starts at x = 0
+        ok = ok && (nhr == 1 || nhr == 2) && xb0 - xa0 + 3 <= nx && (nhr == 1 || xb1 + 3 <= nx);
         int len = 0, s0 = 0, ay = 0, az = 0, xk = 0;
         if (ok && l < nhr * 27) {
             const int hr = l / 27, rr = (l % 27) / 3, side = l % 3;
             const int dy = rr % 3 - 1, dz = rr / 3 - 1;
-            const int xa = hr == 0 ? xa0 : xa1, xb = hr == 0 ? xb0 : xb1;
+            const int xa = hr == 0 ? xa0 : 0, xb = hr == 0 ? xb0 : xb1;
             int y = (hr == 0 ? cyf : cyl) + dy, z = (hr == 0 ? czf : czl) + dz;
             y = y < 0 ? y + ny : (y >= ny ? y - ny : y);
             z = z < 0 ? z + g.n[2] : (z >= g.n[2] ? z - g.n[2] : z);
             // side 0: virtual x = -1 is real nx - 1; side 2: virtual x = nx is real 0
-            const bool has = side == 1 || (side == 0 && xa == 0) || (side == 2 && xb == nx - 1);
-            if (has) {
+            if (side == 1 || (side == 0 && xa == 0) || (side == 2 && xb == nx - 1)) {
                 const int x0 = side == 0 ? nx - 1 : (side == 2 ? 0 : max(xa - 1, 0));
                 const int x1 = side == 0 ? nx - 1 : (side == 2 ? 0 : min(xb + 1, nx - 1));
                 const int rowc = g.cell_off + (z * ny + y) * nx;
@@ -1200,12 +1239,12 @@ __global__ __launch_bounds__(kBlock) void k_force_tile(Dev d, Params p) {
         const int incl = wave_incl_scan(len);
         const int nchk = (len + kWave - 1) >> 6;
         const int cincl = wave_incl_scan(nchk);
-        const int T = __builtin_amdgcn_readlane(incl, 63), NC = __builtin_amdgcn_readlane(cincl, 63);
-        ok = ok && T <= kTileCap && NC <= kTileChunks;
+        const int NC = __builtin_amdgcn_readlane(cincl, 63);
+        ok = ok && __builtin_amdgcn_readlane(incl, 63) <= kTileCap && NC <= kTileChunks;
         if (ok) {
             pt_s0[l] = s0;
             pt_len[l] = len;
-            pt_lds[l] = incl - len;
+            pt_base[l] = incl - len;
             pt_ay[l] = ay;
             pt_az[l] = az;
             pt_xk[l] = xk;
@@ -1217,78 +1256,60 @@ __global__ __launch_bounds__(kBlock) void k_force_tile(Dev d, Params p) {
         if (l == 0) {
             blk[0] = ok ? 1 : 0;
             blk[1] = NC;
-            blk[2] = xa0;
-            blk[3] = xa1;
-            blk[4] = rowf;
+            blk[2] = rowf;
+            blk[3] = xa0;
         }
     }
     __syncthreads();
     const bool tiled = blk[0] != 0;  // uniform over the block
+    const int rowf = blk[2], xa0 = blk[3];
+    const bool use_tile = tiled && few_homes;  // uniform over the wavefront
     if (tiled) {
-        // ---- copy the pieces: wavefront w takes chunks w, w + 4, ..., 8 loads in flight
+        // ---- copy the pieces: chunk c (64 records of one piece) goes to wavefront c % 4
         const int NC = blk[1];
         const int4* __restrict__ u = d.u[sq];
         const uint32_t uox = (uint32_t)g.uoff[0];
         for (int c0 = wib; c0 < NC; c0 += 4 * 8) {
             int4 v[8];
+            int li[8], pcs[8];
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
                 const int c = c0 + 4 * k;
-                if (c < NC) {
-                    const int pp = ch_part[c], i = ch_off[c] + l;
-                    if (i < pt_len[pp]) v[k] = u[pt_s0[pp] + i];
+                li[k] = -1;
+                if (c < NC) {  // uniform
+                    const int pc = ch_part[c], i = ch_off[c] + l;
+                    pcs[k] = pc;
+                    if (i < pt_len[pc]) {
+                        v[k] = u[pt_s0[pc] + i];
+                        li[k] = pt_base[pc] + i;
+                    }
                 }
             }
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
-                const int c = c0 + 4 * k;
-                if (c < NC) {
-                    const int pp = ch_part[c], i = ch_off[c] + l;
-                    if (i < pt_len[pp]) {
-                        const int li = pt_lds[pp] + i;
-                        // x in the home row's frame, modulo 2^32 (differences stay exact)
-                        tx[li] = (int)((uint32_t)v[k].x + (uint32_t)(v[k].w + pt_xk[pp]) * uox);
-                        ty[li] = v[k].y + pt_ay[pp];
-                        tz[li] = v[k].z + pt_az[pp];
-                    }
+                if (li[k] >= 0) {
+                    // x in the home row's frame, modulo 2^32 (differences stay exact)
+                    const int pc = pcs[k];
+                    tx[li[k]] = (int)((uint32_t)v[k].x + (uint32_t)(v[k].w + pt_xk[pc]) * uox);
+                    ty[li[k]] = v[k].y + pt_ay[pc];
+                    tz[li[k]] = v[k].z + pt_az[pc];
                 }
+            }
+        }
+    }
+    if (use_tile) {
+#pragma unroll
+        for (int k = 0; k < kTabPer; ++k) {
+            const int idx = l + k * kWave;
+            if (idx < nhome * 27) {
+                const int pp = (trow[k] == rowf ? 0 : 27) + tpp[k];
+                ltab[wib][idx] = (uint16_t)(pt_base[pp] + tcs[k] - pt_s0[pp]);
             }
         }
     }
     __syncthreads();
     if (!wave_ok) return;
-
-    const int key = lw * kWave + l;
-    const bool active = key - g.slot_off < g.npart;
-    const Pos qi = d.q[sq][active ? key : g.slot_off];
-    const uint32_t cc = active ? qi.cc : 0xffffffffu;
-    const uint32_t cprev = __shfl_up(cc, 1);
-    const bool head = active && (l == 0 || cprev != cc);
-    const unsigned long long hm = __ballot(head);
-    const int nhome = __popcll(hm);
-    const int h = __popcll(hm & (l == 63 ? ~0ull : ((2ull << l) - 1ull))) - 1;
-    const bool use_tile = tiled && nhome <= kHomeMax;  // uniform over the wavefront
-    if (use_tile) {
-        if (head) home_cc[wib][h] = cc;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        for (int idx = l; idx < nhome * 27; idx += kWave) {
-            const int hh = idx / 27, st = idx - hh * 27;
-            const uint32_t hc = home_cc[wib][hh];
-            const int hx = hc & 1023, hy = (hc >> 10) & 1023, hz = hc >> 20;
-            const int hr = hz * ny + hy == blk[4] ? 0 : 1;
-            const int v = hx + st % 3 - 1;
-            const int pp = hr * 27 + (st / 3) * 3 + (v < 0 ? 0 : (v >= nx ? 2 : 1));
-            uint32_t img;
-            const int nc = stencil_cell(hc, st, g, &img);
-            ltab[wib][idx] = (uint16_t)(pt_lds[pp] + d.cell_start[nc] - pt_s0[pp]);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
-
+    const int sp = d.st[b].sp;
     double Fx = 0.0, Fy = 0.0, Fz = 0.0, pe = 0.0;
     if (active) {
         const int nl = qi.cnt;
@@ -1312,8 +1333,8 @@ __global__ __launch_bounds__(kBlock) void k_force_tile(Dev d, Params p) {
             constexpr bool TL = decltype(tile_c)::value;
             const uint16_t* __restrict__ tb = ltab[wib] + h * 27;
             // this key in the frame of the staged partners
-            const int hr = (int)((cc >> 20) * ny + ((cc >> 10) & 1023)) == blk[4] ? 0 : 1;
-            const uint32_t kx = (uint32_t)ui.x + (uint32_t)(ui.w - blk[2 + hr]) * (uint32_t)g.uoff[0];
+            const int hr = (int)((cc >> 20) * ny + ((cc >> 10) & 1023)) == rowf ? 0 : 1;
+            const uint32_t kx = (uint32_t)ui.x + (uint32_t)(ui.w - (hr == 0 ? xa0 : 0)) * (uint32_t)g.uoff[0];
             const int4* __restrict__ u = d.u[sq];
             auto chunk = [&](int c, auto chk_c, int valid) {
                 constexpr bool CHK = decltype(chk_c)::value;
