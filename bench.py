@@ -322,6 +322,8 @@ def main():
     ap.add_argument("--ncell", type=int, default=200, help="FCC cells per side (200 -> 32M particles)")
     ap.add_argument("--tpk", type=int, default=0)
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-fast-rcp", action="store_true",
+                    help="skip the FP64 run with the hardware reciprocal and its correction")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--workload", default="fcc32m",
@@ -374,6 +376,11 @@ def main():
     if not args.no_fp64:
         fp64 = run_gpu(B, torch, w, B.MD_PREC_FP64, args.steps, args.warmup, args.tpk)
         print("bench: FP64 %.3f ms/step" % fp64["ms_per_step"], file=sys.stderr, flush=True)
+    fp64_fast = None
+    if not args.no_fp64 and not args.no_fast_rcp:
+        fp64_fast = run_gpu(B, torch, w, B.MD_PREC_FP64, args.steps, args.warmup, args.tpk, B.MD_F_FAST_RCP)
+        print("bench: FP64 with the corrected hardware reciprocal %.3f ms/step" % fp64_fast["ms_per_step"],
+              file=sys.stderr, flush=True)
 
     rho = 0.5
     rl = w.rc + w.skin
@@ -418,6 +425,10 @@ def main():
     if fp64 is not None:
         out["fp64"] = dict(fp64, gflops=FLOP_PER_PAIR * pairs / (fp64["ms_per_step"] / 1e3) / 1e9,
                            force_achieved_gbs=force_bytes / (fp64["force_ms_avg"] / 1e3) / 1e9)
+    if fp64_fast is not None:
+        out["fp64_fast_rcp"] = dict(fp64_fast, gflops=FLOP_PER_PAIR * pairs / (fp64_fast["ms_per_step"] / 1e3) / 1e9,
+                                    note="FP64 with 1/r^2 from the hardware reciprocal and the Sec. III.C "
+                                         "correction of r^-8 and r^-14")
     if not args.no_cpu:
         print("bench: CPU oracle sample ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)

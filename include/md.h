@@ -78,6 +78,9 @@ typedef enum {
                                       LDS-staged partner tiles (it falls back per block / wavefront
                                       where a tile does not apply); default: chosen from the geometry */
 #define MD_F_TILE_OFF 8u           /* never use the staged-tile force pass (testing, tuning) */
+#define MD_F_FAST_RCP 16u          /* FP64 path: 1/r^2 from the hardware reciprocal, with the
+                                      correction of Sec. III.C applied to r^-6, r^-8, r^-12 and
+                                      r^-14 (r^-2n ~ xt^n ((n + 1) - n xt r^2)) instead of a division */
 
 typedef struct {
     int64_t n;            /* particles in the box, >= 2 */

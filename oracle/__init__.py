@@ -47,7 +47,7 @@ P_I64 = C.POINTER(C.c_int64)
 
 class OrcParams(C.Structure):
     _fields_ = [("rc", C.c_double), ("skin", C.c_double), ("dt", C.c_double), ("mass", C.c_double),
-                ("cutoff", C.c_int32), ("rebuild", C.c_int32), ("verify", C.c_int32), ("pad", C.c_int32)]
+                ("cutoff", C.c_int32), ("rebuild", C.c_int32), ("verify", C.c_int32), ("rcp", C.c_int32)]
 
 
 class OrcStats(C.Structure):
@@ -77,6 +77,13 @@ def lib():
         L.orc_forces_list.argtypes = [C.c_int64, P_D, P_D, C.c_double, C.c_double, C.c_double,
                                       P_I64, P_I32, P_D, P_D, P_D]
         L.orc_forces_list.restype = C.c_double
+        L.orc_forces_list_rcp.argtypes = [C.c_int64, P_D, P_D, C.c_double, C.c_double, C.c_double,
+                                          P_I64, P_I32, P_D, P_D, P_D, C.c_int]
+        L.orc_forces_list_rcp.restype = C.c_double
+        L.orc_rcp_approx.argtypes = [C.c_double]
+        L.orc_rcp_approx.restype = C.c_double
+        L.orc_rpow_approx.argtypes = [C.c_double, C.c_double, C.c_int, C.c_int]
+        L.orc_rpow_approx.restype = C.c_double
         L.orc_forces_brute.argtypes = [C.c_int64, P_D, P_D, C.c_double, C.c_double, C.c_double, P_D, P_D]
         L.orc_forces_brute.restype = C.c_double
         L.orc_forces_sample.argtypes = [C.c_int64, P_D, P_D, C.c_double, C.c_double, C.c_double,
@@ -168,7 +175,22 @@ def neighbors(q, L, r_list, half=False, brute=False):
     return kp, pl[:tot]
 
 
-def forces_list(q, L, rc, kp, pl, c2, c0, per_particle_pe=False):
+# reciprocal modes of the force evaluation (Sec. III.C): IEEE division, the
+# paper's approximate reciprocal (relative error < 1/256) without and with its
+# correction, and an exact reciprocal through the corrected formulas
+RCP_DIV, RCP_APPROX, RCP_APPROX_CORR, RCP_EXACT_CORR = 0, 1, 2, 3
+
+
+def rcp_approx(x):
+    return lib().orc_rcp_approx(float(x))
+
+
+def rpow_approx(r2, xt, n, corr):
+    """xt^n, times the correction (n + 1) - n xt r^2 when corr."""
+    return lib().orc_rpow_approx(float(r2), float(xt), int(n), int(bool(corr)))
+
+
+def forces_list(q, L, rc, kp, pl, c2, c0, per_particle_pe=False, rcp=RCP_DIV):
     q = _q(q)
     Lb = _box(L)
     n = q.shape[0]
@@ -177,18 +199,18 @@ def forces_list(q, L, rc, kp, pl, c2, c0, per_particle_pe=False):
     pe_i = np.zeros(n) if per_particle_pe else None
     kp = np.ascontiguousarray(kp, dtype=np.int64)
     pl = np.ascontiguousarray(pl, dtype=np.int32)
-    pe = lib().orc_forces_list(n, _pd(q), _pd(Lb), rc, c2, c0, kp.ctypes.data_as(P_I64),
-                               pl.ctypes.data_as(P_I32), _pd(F), _pd(A),
-                               _pd(pe_i) if pe_i is not None else None)
+    pe = lib().orc_forces_list_rcp(n, _pd(q), _pd(Lb), rc, c2, c0, kp.ctypes.data_as(P_I64),
+                                   pl.ctypes.data_as(P_I32), _pd(F), _pd(A),
+                                   _pd(pe_i) if pe_i is not None else None, int(rcp))
     return (F, pe, A, pe_i) if per_particle_pe else (F, pe, A)
 
 
-def forces(q, L, rc, skin=0.0, mode=CUT_EQ1):
+def forces(q, L, rc, skin=0.0, mode=CUT_EQ1, rcp=RCP_DIV):
     """F, PE and the absolute pair-force sum A at positions q (list at rc + skin)."""
     c2, c0 = coeffs(rc, mode)
     qw, _, _ = cells(q, L, rc + skin)
     kp, pl = neighbors(qw, L, rc + skin)
-    return forces_list(qw, L, rc, kp, pl, c2, c0)
+    return forces_list(qw, L, rc, kp, pl, c2, c0, rcp=rcp)
 
 
 def forces_brute(q, L, rc, mode=CUT_EQ1):
@@ -254,14 +276,14 @@ class RunResult:
 
 
 def run(q, v, L, nsteps, rc=2.5, skin=0.3, dt=0.005, mass=1.0, mode=CUT_EQ1,
-        rebuild=REBUILD_DUTC, energy_every=0, verify=False) -> RunResult:
+        rebuild=REBUILD_DUTC, energy_every=0, verify=False, rcp=RCP_DIV) -> RunResult:
     """Velocity-Verlet NVE run from (q, v) with a fresh initial list and forces."""
     q = _q(q)
     v = np.ascontiguousarray(v, dtype=np.float64).copy()
     Lb = _box(L)
     n = q.shape[0]
     F = np.zeros((n, 3))
-    p = OrcParams(rc, skin, dt, mass, mode, rebuild, int(verify), 0)
+    p = OrcParams(rc, skin, dt, mass, mode, rebuild, int(verify), int(rcp))
     st = OrcStats(0, 0, 0, 0.0)
     ns = nsteps // energy_every if energy_every > 0 else 0
     ke = np.zeros(max(ns, 1))

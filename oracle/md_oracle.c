@@ -18,7 +18,10 @@
  *     benchmark integrator of Sec. III.B;
  *   - the list-validity check of Sec. II.A (dynamic upper time cutoff): the
  *     accumulated bound D += dt * max|v| after each drift, rebuild when
- *     2D > skin.
+ *     2D > skin;
+ *   - the approximate reciprocal of Sec. III.C and its correction of r^-8 and
+ *     r^-14 (a model instruction with relative error below 1/256), as an
+ *     alternative force evaluation for the energy-conservation comparison.
  *
  * Readings where the paper is silent are listed in the repository's design
  * notes; the ones that shape arithmetic here are: strict "<" at rc and at the
@@ -87,6 +90,52 @@ double orc_pair_f(double r2, double c2) {
     double s = 1.0 / r2;
     double s3 = s * s * s;
     return (24.0 * s3 - 48.0 * s3 * s3) * s + 8.0 * c2;
+}
+
+/* ------------------------------------------------- approximate reciprocal (Sec. III.C)
+ * The paper's SIMD kernel replaces the divide by a reciprocal approximation with
+ * relative error below 1/256 and corrects the powers of it that the force needs:
+ * with xt the approximation of 1/r^2 and xt r^2 = 1 + e,
+ *   r^-2n = xt^n (1 + e)^-n = xt^n (1 - n e + O(e^2)) = xt^n ((n + 1) - n xt r^2) + O(e^2).
+ * orc_rcp_approx models such an instruction: 1/x with its mantissa cut to 8 bits
+ * after the leading one (relative error below 2^-8). */
+double orc_rcp_approx(double x) {
+    int e;
+    double m = frexp(1.0 / x, &e); /* 1/x = m 2^e, m in [0.5, 1) */
+    return ldexp(floor(m * 512.0) / 512.0, e);
+}
+
+/* xt^n, times the correction factor (n + 1) - n xt r^2 when corr != 0. */
+double orc_rpow_approx(double r2, double xt, int n, int corr) {
+    double p = 1.0;
+    for (int k = 0; k < n; ++k) p *= xt;
+    return corr ? p * ((double)(n + 1) - (double)n * xt * r2) : p;
+}
+
+/* f(r) and V(r) of Eq. (1) from an approximate reciprocal xt of r^2:
+ * f = 24 r^-8 - 48 r^-14 + 8 c2, V = 4 (r^-12 - r^-6 + c2 r^2 + c0). */
+double orc_pair_f_rcp(double r2, double c2, double xt, int corr) {
+    return 24.0 * orc_rpow_approx(r2, xt, 4, corr) - 48.0 * orc_rpow_approx(r2, xt, 7, corr) + 8.0 * c2;
+}
+double orc_pair_v_rcp(double r2, double c2, double c0, double xt, int corr) {
+    return 4.0 * (orc_rpow_approx(r2, xt, 6, corr) - orc_rpow_approx(r2, xt, 3, corr) + c2 * r2 + c0);
+}
+
+/* Reciprocal modes of the force evaluation:
+ *   0 IEEE division (the plain definition),
+ *   1 approximate reciprocal (orc_rcp_approx) without correction,
+ *   2 approximate reciprocal with the correction,
+ *   3 exact reciprocal through the corrected formulas (the correction then vanishes). */
+static void pair_fv(double r2, double c2, double c0, int rcp, double *f, double *v) {
+    if (rcp == 0) {
+        *f = orc_pair_f(r2, c2);
+        *v = orc_pair_v(r2, c2, c0);
+        return;
+    }
+    double xt = rcp == 3 ? 1.0 / r2 : orc_rcp_approx(r2);
+    int corr = rcp != 1;
+    *f = orc_pair_f_rcp(r2, c2, xt, corr);
+    *v = orc_pair_v_rcp(r2, c2, c0, xt, corr);
 }
 
 /* ---------------------------------------------------------------- geometry */
@@ -257,9 +306,9 @@ int64_t orc_neighbors_brute(int64_t n, const double *q, const double *L, double 
  *   PE  = sum over pairs i < j with r_ij < rc of V(r_ij)
  *   A_i = sum_{j} |f(r_ij) d_ij|   (normalisation for force-error metrics)
  * pe_i (nullable) receives 1/2 sum_j V(r_ij) per particle.  Returns PE. */
-double orc_forces_list(int64_t n, const double *q, const double *L, double rc, double c2, double c0,
-                       const int64_t *key_ptr, const int32_t *partners,
-                       double *F, double *A, double *pe_i) {
+double orc_forces_list_rcp(int64_t n, const double *q, const double *L, double rc, double c2, double c0,
+                           const int64_t *key_ptr, const int32_t *partners,
+                           double *F, double *A, double *pe_i, int rcp) {
     double rc2 = rc * rc, pe = 0.0;
 #pragma omp parallel for schedule(dynamic, 256) reduction(+ : pe)
     for (int64_t i = 0; i < n; ++i) {
@@ -269,10 +318,10 @@ double orc_forces_list(int64_t n, const double *q, const double *L, double rc, d
             double d[3];
             double r2 = dist2(q, i, j, L, d);
             if (r2 < rc2) {
-                double f = orc_pair_f(r2, c2);
+                double f, v;
+                pair_fv(r2, c2, c0, rcp, &f, &v);
                 fx += f * d[0]; fy += f * d[1]; fz += f * d[2];
                 a += sqrt((f * d[0]) * (f * d[0]) + (f * d[1]) * (f * d[1]) + (f * d[2]) * (f * d[2]));
-                double v = orc_pair_v(r2, c2, c0);
                 e += 0.5 * v;
                 if (j > i) pe += v;
             }
@@ -282,6 +331,12 @@ double orc_forces_list(int64_t n, const double *q, const double *L, double rc, d
         if (pe_i) pe_i[i] = e;
     }
     return pe;
+}
+
+double orc_forces_list(int64_t n, const double *q, const double *L, double rc, double c2, double c0,
+                       const int64_t *key_ptr, const int32_t *partners,
+                       double *F, double *A, double *pe_i) {
+    return orc_forces_list_rcp(n, q, L, rc, c2, c0, key_ptr, partners, F, A, pe_i, 0);
 }
 
 /* Forces and PE by brute force over all pairs (no list, no cells). */
@@ -378,7 +433,7 @@ typedef struct {
     int32_t cutoff;   /* ORC_CUT_* */
     int32_t rebuild;  /* ORC_REBUILD_* */
     int32_t verify;   /* nonzero: count pairs within rc missing from the list, every step */
-    int32_t pad;
+    int32_t rcp;      /* reciprocal mode of the force evaluation (see pair_fv) */
 } orc_params;
 
 typedef struct {
@@ -459,7 +514,7 @@ int orc_run(int64_t n, double *q, double *v, double *F, const double *L, const o
     int rcode = sys_build(&s, p);
     if (rcode != 0) goto done;
     if (!F_valid) {
-        orc_forces_list(n, q, s.L, p->rc, s.c2, s.c0, s.kp, s.pl, F, NULL, NULL);
+        orc_forces_list_rcp(n, q, s.L, p->rc, s.c2, s.c0, s.kp, s.pl, F, NULL, NULL, p->rcp);
         stats->D = 0.0;
         stats->rebuilds += 1;
     }
@@ -500,7 +555,7 @@ int orc_run(int64_t n, double *q, double *v, double *F, const double *L, const o
             stats->rebuilds += 1;
         }
         if (p->verify) stats->missed_pairs += sys_missed(&s, p);
-        double pe = orc_forces_list(n, q, s.L, p->rc, s.c2, s.c0, s.kp, s.pl, F, NULL, NULL);
+        double pe = orc_forces_list_rcp(n, q, s.L, p->rc, s.c2, s.c0, s.kp, s.pl, F, NULL, NULL, p->rcp);
         for (int64_t i = 0; i < 3 * n; ++i) v[i] = v[i] + h * F[i];
         stats->steps += 1;
         if (energy_every > 0 && step % energy_every == 0) {

@@ -141,8 +141,10 @@ md_status validate(const md_params* b, int32_t nbox, std::string& why) {
         if (p.precision != MD_PREC_FP64 && p.precision != MD_PREC_FP32_MIXED) return bad("unknown precision");
         if (p.cutoff < MD_CUT_EQ1 || p.cutoff > MD_CUT_RAW) return bad("unknown cutoff scheme");
         if (p.rebuild < MD_REBUILD_DUTC || p.rebuild > MD_REBUILD_NEVER) return bad("unknown rebuild policy");
-        if (p.flags & ~(uint32_t)(MD_F_VERIFY_LIST | MD_F_GRAPH | MD_F_TILE_ON | MD_F_TILE_OFF))
+        if (p.flags & ~(uint32_t)(MD_F_VERIFY_LIST | MD_F_GRAPH | MD_F_TILE_ON | MD_F_TILE_OFF | MD_F_FAST_RCP))
             return bad("unknown flag bits");
+        if ((p.flags & MD_F_FAST_RCP) && p.precision != MD_PREC_FP64)
+            return bad("MD_F_FAST_RCP applies to the FP64 path only");
         if ((p.flags & MD_F_TILE_ON) && (p.flags & MD_F_TILE_OFF)) return bad("MD_F_TILE_ON with MD_F_TILE_OFF");
         if (!(p.threads_per_key == 0 || p.threads_per_key == 1 || p.threads_per_key == 2 ||
               p.threads_per_key == 4 || p.threads_per_key == 8))
@@ -344,6 +346,7 @@ void params_refresh(md_ctx* c) {
     if (p.flags & MD_F_TILE_ON) tile = p.precision == MD_PREC_FP32_MIXED;
     if (p.flags & MD_F_TILE_OFF) tile = false;
     P.tile = tile ? 1 : 0;
+    P.fastrcp = (p.flags & MD_F_FAST_RCP) ? 1 : 0;
 }
 
 void free_all(md_ctx* c) {

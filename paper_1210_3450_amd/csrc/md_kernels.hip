@@ -1029,6 +1029,7 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Params p) {
         if constexpr (!MIX) {
             const Pos* __restrict__ q = d.q[sq];
             const double rc2 = p.rc2, c2x8 = 8.0 * p.c2;
+            const bool fast = p.fastrcp != 0;  // uniform
             // CHK: the lane's last chunk, entries from `valid` on are padding
             auto chunk = [&](int c, auto chk_c, int valid) {
                 constexpr bool CHK = decltype(chk_c)::value;
@@ -1056,13 +1057,26 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Params p) {
                     const double dz = (qj[k].z - qi.z) - sh.z;
                     const double r2 = dx * dx + dy * dy + dz * dz;
                     const bool in = (!CHK || k < valid) && r2 < rc2;
-                    const double inv = 1.0 / r2;
-                    const double inv3 = inv * inv * inv;
-                    const double f = in ? (24.0 * inv3 - 48.0 * inv3 * inv3) * inv + c2x8 : 0.0;
+                    double f, e = 0.0;
+                    if (fast) {
+                        // Sec. III.C: with xt ~ 1/r^2 and t = xt r^2 = 1 + eps,
+                        // r^-2n = xt^n ((n + 1) - n t) + O(eps^2)
+                        const double xt = __builtin_amdgcn_rcp(r2);
+                        const double t = xt * r2;
+                        const double x2 = xt * xt, x3 = x2 * xt, x4 = x2 * x2;
+                        const double r8 = x4 * (5.0 - 4.0 * t), r14 = x4 * x3 * (8.0 - 7.0 * t);
+                        f = in ? 24.0 * r8 - 48.0 * r14 + c2x8 : 0.0;
+                        if (ENERGY) e = x3 * x3 * (7.0 - 6.0 * t) - x3 * (4.0 - 3.0 * t);
+                    } else {
+                        const double inv = 1.0 / r2;
+                        const double inv3 = inv * inv * inv;
+                        f = in ? (24.0 * inv3 - 48.0 * inv3 * inv3) * inv + c2x8 : 0.0;
+                        if (ENERGY) e = inv3 * inv3 - inv3;
+                    }
                     Fx += f * dx;
                     Fy += f * dy;
                     Fz += f * dz;
-                    if (ENERGY) pe += in ? 2.0 * (inv3 * inv3 - inv3 + p.c2 * r2 + p.c0) : 0.0;
+                    if (ENERGY) pe += in ? 2.0 * (e + p.c2 * r2 + p.c0) : 0.0;
                 }
             };
             for (int c = 0; c < nfull; ++c) chunk(c, std::false_type{}, U);

@@ -61,6 +61,7 @@ BAD = [
     dict(rebuild=5),
     dict(flags=1 << 7),
     dict(flags=4 | 8),                    # tile on and off together
+    dict(flags=16, precision=1),          # fast reciprocal on the mixed path
     dict(threads_per_key=3),
     dict(list_cap=-1),
     dict(box=(3000.0, 20.0, 20.0)),       # > 1023 cells on one axis

@@ -164,6 +164,24 @@ def test_forces_mixed(name, tpk):
     assert pe == pytest.approx(per, rel=1e-6, abs=1e-9)
 
 
+@pytest.mark.parametrize("name", ["fcc4000", "jitter_ragged", "clustered", "edges"])
+def test_forces_fp64_fast_reciprocal(name):
+    """FP64 with the hardware reciprocal and the Sec. III.C correction of r^-8 and
+    r^-14: the error against the oracle's division is second order in the
+    reciprocal's error, which leaves the FP64 bar (1e-12 normalised) in reach
+    (measured: below 4e-14)."""
+    b = B()
+    q, v, L = case(name)
+    with make_ctx(q, v, L, flags=b.MD_F_FAST_RCP) as c:
+        F = c.compute_forces().cpu().numpy()
+        _, pe = c.energy()
+    Fr, per, A = oracle.forces(q, L, 2.5, 0.3)
+    err = norm_err(F, Fr, A)
+    print("fast reciprocal, %s: normalised force error %.3e, PE rel %.3e" % (name, err, abs(pe - per) / abs(per)))
+    assert err <= 1e-12
+    assert pe == pytest.approx(per, rel=1e-12)
+
+
 def tile_case(name):
     """Boxes for the FP32-mixed force pass with LDS-staged partner tiles: wide
     rows (26-30 cells) so that a block's keys span one or two rows, with x-wrap

@@ -56,6 +56,23 @@ def test_small_nve_energy_drift_matches_oracle():
         assert dev[k] < 3.0 * dev["oracle"] + 1e-5
 
 
+def test_small_nve_drift_fast_reciprocal():
+    """The energy-conservation comparison of Sec. III.C on the GPU: 2000 steps at
+    N = 4000 with the hardware reciprocal and the correction keep the energy at
+    the level of exact division."""
+    b = B()
+    w = inputs.small_nve()
+    dev = {}
+    for name, flags in (("division", b.MD_F_GRAPH), ("fast_rcp", b.MD_F_GRAPH | b.MD_F_FAST_RCP)):
+        with b.Context(b.make_params(w.n, w.box, precision=0, flags=flags)) as c:
+            c.set_state(w.pos, w.vel)
+            c.step(2000, 10)
+            ke, pe = c.energy_series()
+        dev[name] = _maxdev(ke[:, 0], pe[:, 0])
+    print("max |E(t)-E(0)|/|E(0)| over 2000 steps:", dev)
+    assert dev["fast_rcp"] < 1.5 * dev["division"] + 1e-5
+
+
 def test_cavitation_protocol_reduced_size():
     """24^3 simple-cubic sites at density 0.7 (13,824 particles, rc = 3.0):
     equilibrate at T = 0.9 by rescaling, expand every length by 1.1, run NVE.

@@ -337,3 +337,58 @@ def _list_args(q, L):
     kp, pl = oracle.neighbors(qw, L, 2.8)
     c2, c0 = oracle.coeffs(2.5)
     return qw, L, 2.5, kp, pl, c2, c0
+
+
+# ---------------------------------------------------------------- approximate reciprocal (Sec. III.C)
+
+def test_rcp_approx_model_error_below_1_over_256():
+    """The model instruction: relative error below 1/256, and not exact in general."""
+    r2 = np.linspace(0.6, 9.0, 2001)
+    xt = np.array([oracle.rcp_approx(x) for x in r2])
+    rel = np.abs(xt * r2 - 1.0)
+    assert rel.max() < 1.0 / 256.0
+    assert rel.max() > 1.0 / 2048.0
+
+
+@pytest.mark.parametrize("n,second", [(4, 10.0), (7, 28.0)])
+def test_rcp_correction_is_second_order(n, second):
+    """With xt r^2 = 1 + e: xt^n ((n+1) - n xt r^2) = r^-2n (1 - n(n+1)/2 e^2 + O(e^3)),
+    against (1 + n e) without the correction: the factors 10 and 28 for r^-8 and
+    r^-14, and 4 and 7 uncorrected."""
+    for r in (0.9, 1.12, 1.7, 2.5):
+        r2 = r * r
+        for e in (1.0 / 256, -1.0 / 256, 1.0 / 4096):
+            xt = (1.0 + e) / r2
+            exact = r2 ** (-n)
+            corr = oracle.rpow_approx(r2, xt, n, True) / exact - 1.0
+            plain = oracle.rpow_approx(r2, xt, n, False) / exact - 1.0
+            assert corr == pytest.approx(-second * e * e, rel=0.05)
+            assert plain == pytest.approx(n * e, rel=0.03)
+
+
+def test_exact_reciprocal_through_corrected_formulas_is_exact():
+    """Feeding the exact reciprocal to the corrected formulas reproduces the plain
+    forces and energy (the correction factor is then 1)."""
+    w = inputs.small_nve()
+    qw, _, _ = oracle.cells(w.pos, w.box, 2.8)
+    kp, pl = oracle.neighbors(qw, w.box, 2.8)
+    c2, c0 = oracle.coeffs(2.5)
+    F0, pe0, A = oracle.forces_list(qw, w.box, 2.5, kp, pl, c2, c0)
+    F3, pe3, _ = oracle.forces_list(qw, w.box, 2.5, kp, pl, c2, c0, rcp=oracle.RCP_EXACT_CORR)
+    assert (np.linalg.norm(F3 - F0, axis=1) / A).max() < 1e-13
+    assert pe3 == pytest.approx(pe0, rel=1e-13)
+
+
+@pytest.mark.slow
+def test_reciprocal_correction_restores_energy_conservation():
+    """The energy-conservation comparison of Sec. III.C at 4000 particles: with
+    the 1/256 reciprocal the total energy drifts away; with the correction it
+    stays at the level of exact division."""
+    w = inputs.small_nve()
+    dev = {}
+    for mode in (oracle.RCP_DIV, oracle.RCP_APPROX, oracle.RCP_APPROX_CORR):
+        r = oracle.run(w.pos, w.vel, w.box, 1000, energy_every=10, rcp=mode)
+        E = r.ke + r.pe
+        dev[mode] = float(np.abs(E - E[0]).max() / abs(E[0]))
+    assert dev[oracle.RCP_APPROX] > 3.0 * dev[oracle.RCP_APPROX_CORR]
+    assert dev[oracle.RCP_APPROX_CORR] < 1.5 * dev[oracle.RCP_DIV] + 1e-5
