@@ -201,6 +201,29 @@ md_status md_batch_energy(md_ctx *ctx, double *ke, double *pe);
  * samples available (at most the internal capacity of 4096).  Synchronizing. */
 md_status md_energy_series(md_ctx *ctx, double *ke, double *pe, int32_t max, int32_t *count);
 
+/* Pair virial and thermostat share at the same samples as md_energy_series:
+ * host arrays [max][nbox]: vir = sum over pairs i < j within rc of f(r) r^2
+ * (f = V'(r)/r, the Algorithm 1 scalar), so that the pressure of box b at a
+ * sample is P = (2 KE - vir) / (3 V); thermostat = Q xi^2 / 2 + g T eta (zero
+ * without a thermostat), so that KE + PE + thermostat is conserved.
+ * Synchronizing; either pointer may be NULL. */
+md_status md_observable_series(md_ctx *ctx, double *vir, double *thermostat, int32_t max, int32_t *count);
+
+/* Virial pressure of every box at the current state, P = (2 KE - vir) / (3 V)
+ * (host double [nbox]).  Evaluates forces and energies (like md_energy);
+ * synchronizing. */
+md_status md_pressure(md_ctx *ctx, double *pressure);
+
+/* Nose-Hoover thermostat for the equilibration of the cavitation runs (Sec. IV.A):
+ * dv/dt = F/m - xi v, dxi/dt = (2 KE - g T) / Q, deta/dt = xi, with g = 3N - 3 and
+ * Q = g T tau^2, integrated as thermostat(dt/2), velocity Verlet, thermostat(dt/2)
+ * per step (KE + PE + Q xi^2 / 2 + g T eta is conserved).  T: host double [nbox]
+ * (> 0), tau: relaxation time; tau <= 0 switches the thermostat off (NVE, T may
+ * be NULL).  Resets xi = eta = 0; the setting survives md_set_state.  While a
+ * thermostat is on, md_step runs every step unfused (no graph replay). */
+md_status md_set_thermostat(md_ctx *ctx, const double *T, double tau);
+md_status md_get_thermostat(md_ctx *ctx, double *xi, double *eta);  /* host [nbox], nullable */
+
 /* ---- diagnostics and parity (synchronizing) ----------------------------- */
 
 /* Cell of every particle at the last binning, box-local linear id

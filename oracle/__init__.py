@@ -50,6 +50,10 @@ class OrcParams(C.Structure):
                 ("cutoff", C.c_int32), ("rebuild", C.c_int32), ("verify", C.c_int32), ("rcp", C.c_int32)]
 
 
+class OrcThermo(C.Structure):
+    _fields_ = [("T", C.c_double), ("tau", C.c_double), ("xi", C.c_double), ("eta", C.c_double)]
+
+
 class OrcStats(C.Structure):
     _fields_ = [("steps", C.c_int64), ("rebuilds", C.c_int64), ("missed_pairs", C.c_int64),
                 ("D", C.c_double)]
@@ -84,6 +88,11 @@ def lib():
         L.orc_rcp_approx.restype = C.c_double
         L.orc_rpow_approx.argtypes = [C.c_double, C.c_double, C.c_int, C.c_int]
         L.orc_rpow_approx.restype = C.c_double
+        L.orc_virial_list.argtypes = [C.c_int64, P_D, P_D, C.c_double, C.c_double, P_I64, P_I32]
+        L.orc_virial_list.restype = C.c_double
+        L.orc_run_obs.argtypes = [C.c_int64, P_D, P_D, P_D, P_D, C.POINTER(OrcParams), C.POINTER(OrcThermo),
+                                  C.c_int64, C.c_int64, P_D, P_D, P_D, P_D, C.POINTER(OrcStats), C.c_int32]
+        L.orc_run_obs.restype = C.c_int
         L.orc_forces_brute.argtypes = [C.c_int64, P_D, P_D, C.c_double, C.c_double, C.c_double, P_D, P_D]
         L.orc_forces_brute.restype = C.c_double
         L.orc_forces_sample.argtypes = [C.c_int64, P_D, P_D, C.c_double, C.c_double, C.c_double,
@@ -293,6 +302,56 @@ def run(q, v, L, nsteps, rc=2.5, skin=0.3, dt=0.005, mass=1.0, mode=CUT_EQ1,
     if rcode != 0:
         raise ValueError("orc_run failed with code %d" % rcode)
     return RunResult(q, v, F, ke[:ns], pe[:ns], st.steps, st.rebuilds, st.missed_pairs, st.D)
+
+
+def virial(q, L, rc, skin=0.3, mode=CUT_EQ1):
+    """Pair virial sum_{i<j, r<rc} f(r) r^2 at positions q (f = V'(r)/r)."""
+    c2, _ = coeffs(rc, mode)
+    qw, _, _ = cells(q, L, rc + skin)
+    kp, pl = neighbors(qw, L, rc + skin)
+    return lib().orc_virial_list(qw.shape[0], _pd(qw), _pd(_box(L)), rc, c2, kp.ctypes.data_as(P_I64),
+                                 pl.ctypes.data_as(P_I32))
+
+
+def pressure(ke, vir, volume):
+    """Virial pressure P = (2 KE - sum_{i<j} f r^2) / (3 V)."""
+    return (2.0 * ke - vir) / (3.0 * volume)
+
+
+@dataclass
+class ObsResult:
+    q: np.ndarray
+    v: np.ndarray
+    F: np.ndarray
+    ke: np.ndarray
+    pe: np.ndarray
+    vir: np.ndarray
+    thermo: np.ndarray   # thermostat share Q xi^2 / 2 + g T eta of the conserved quantity
+    xi: float
+    eta: float
+    steps: int
+    rebuilds: int
+
+
+def run_obs(q, v, L, nsteps, rc=2.5, skin=0.3, dt=0.005, mass=1.0, mode=CUT_EQ1, energy_every=10,
+            T=None, tau=0.0, xi=0.0, eta=0.0, rcp=RCP_DIV) -> ObsResult:
+    """Velocity-Verlet run with energies, pair virial and, when tau > 0, a
+    Nose-Hoover thermostat at temperature T (relaxation time tau)."""
+    q = _q(q)
+    v = np.ascontiguousarray(v, dtype=np.float64).copy()
+    Lb = _box(L)
+    n = q.shape[0]
+    F = np.zeros((n, 3))
+    p = OrcParams(rc, skin, dt, mass, mode, REBUILD_DUTC, 0, int(rcp))
+    th = OrcThermo(float(T) if T is not None else 0.0, float(tau), float(xi), float(eta))
+    st = OrcStats(0, 0, 0, 0.0)
+    ns = nsteps // energy_every if energy_every > 0 else 0
+    ke, pe, vir, tho = (np.zeros(max(ns, 1)) for _ in range(4))
+    rcode = lib().orc_run_obs(n, _pd(q), _pd(v), _pd(F), _pd(Lb), C.byref(p), C.byref(th), nsteps,
+                              energy_every, _pd(ke), _pd(pe), _pd(vir), _pd(tho), C.byref(st), 0)
+    if rcode != 0:
+        raise ValueError("orc_run_obs failed with code %d" % rcode)
+    return ObsResult(q, v, F, ke[:ns], pe[:ns], vir[:ns], tho[:ns], th.xi, th.eta, st.steps, st.rebuilds)
 
 
 def initial_forces(q, L, rc=2.5, skin=0.3, mode=CUT_EQ1):

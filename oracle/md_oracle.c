@@ -19,6 +19,8 @@
  *   - the list-validity check of Sec. II.A (dynamic upper time cutoff): the
  *     accumulated bound D += dt * max|v| after each drift, rebuild when
  *     2D > skin;
+ *   - the pair virial and a Nose-Hoover thermostat (the equilibration of the
+ *     cavitation runs, Sec. IV.A), with the conserved extended energy;
  *   - the approximate reciprocal of Sec. III.C and its correction of r^-8 and
  *     r^-14 (a model instruction with relative error below 1/256), as an
  *     alternative force evaluation for the energy-conservation comparison.
@@ -339,6 +341,25 @@ double orc_forces_list(int64_t n, const double *q, const double *L, double rc, d
     return orc_forces_list_rcp(n, q, L, rc, c2, c0, key_ptr, partners, F, A, pe_i, 0);
 }
 
+/* Pair virial sum over a full list: sum_{i<j, r<rc} f(r) r^2, where f = V'(r)/r.
+ * The pair contribution to the pressure is W = -sum_{i<j} f r^2 (the force on i
+ * from j is f (q_j - q_i), against q_i - q_j), so P = (2 KE + W) / (3 V). */
+double orc_virial_list(int64_t n, const double *q, const double *L, double rc, double c2,
+                       const int64_t *key_ptr, const int32_t *partners) {
+    double rc2 = rc * rc, w = 0.0;
+#pragma omp parallel for schedule(dynamic, 256) reduction(+ : w)
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t k = key_ptr[i]; k < key_ptr[i + 1]; ++k) {
+            int64_t j = partners[k];
+            if (j <= i) continue;
+            double d[3];
+            double r2 = dist2(q, i, j, L, d);
+            if (r2 < rc2) w += orc_pair_f(r2, c2) * r2;
+        }
+    }
+    return w;
+}
+
 /* Forces and PE by brute force over all pairs (no list, no cells). */
 double orc_forces_brute(int64_t n, const double *q, const double *L, double rc, double c2, double c0,
                         double *F, double *A) {
@@ -491,17 +512,52 @@ static int64_t sys_missed(const orc_sys *s, const orc_params *p) {
     return missed;
 }
 
+/* Nose-Hoover thermostat state of a run (used when tau > 0).  The equations
+ * dv/dt = F/m - xi v, dxi/dt = (2 KE - g T) / Q, deta/dt = xi, with g = 3N - 3
+ * degrees of freedom and Q = g T tau^2, conserve H = KE + PE + Q xi^2 / 2 + g T eta.
+ * A step is the symmetric splitting
+ *   thermostat(dt/2); velocity Verlet (kick, drift, forces, kick); thermostat(dt/2),
+ * where thermostat(h) is: xi += (h/2) G; v *= exp(-xi h); eta += xi h; xi += (h/2) G
+ * with G = (2 KE - g T) / Q evaluated from the current velocities. */
+typedef struct {
+    double T, tau;   /* target temperature and relaxation time; tau <= 0: NVE */
+    double xi, eta;  /* thermostat variable and its time integral (in and out) */
+} orc_thermo;
+
+static double kin(int64_t n, const double *v, double mass) { return orc_kinetic(n, v, mass); }
+
+static void thermo_half(int64_t n, double *v, double mass, orc_thermo *th, double h) {
+    double g = 3.0 * (double)n - 3.0;
+    double Q = g * th->T * th->tau * th->tau;
+    double G = (2.0 * kin(n, v, mass) - g * th->T) / Q;
+    th->xi = th->xi + 0.5 * h * G;
+    double sc = exp(-th->xi * h);
+    for (int64_t i = 0; i < 3 * n; ++i) v[i] = v[i] * sc;
+    th->eta = th->eta + th->xi * h;
+    G = (2.0 * kin(n, v, mass) - g * th->T) / Q;
+    th->xi = th->xi + 0.5 * h * G;
+}
+
+/* Thermostat's share of the conserved quantity: Q xi^2 / 2 + g T eta. */
+static double thermo_energy(int64_t n, const orc_thermo *th) {
+    double g = 3.0 * (double)n - 3.0;
+    double Q = g * th->T * th->tau * th->tau;
+    return 0.5 * Q * th->xi * th->xi + g * th->T * th->eta;
+}
+
 /* Advance (q, v) by nsteps velocity-Verlet steps.
  *   On entry: q, v at time t (caller order).  If F_valid == 0 the initial list
  *   and forces are built first; otherwise F holds F(q) and D is taken from stats.
  *   Per step: v += (dt/2m) F; q += dt v; DUTC update; rebuild if required;
- *   F = F(q); v += (dt/2m) F.
+ *   F = F(q); v += (dt/2m) F  (wrapped in thermostat half steps when th->tau > 0).
  *   energy_every > 0: after every energy_every-th step, KE and PE go to
- *   ke_out[k], pe_out[k] (k counts samples).
+ *   ke_out[k], pe_out[k] (k counts samples); vir_out[k] (nullable) receives the
+ *   pair virial sum_{i<j} f r^2 and th_out[k] (nullable) the thermostat's share
+ *   of the conserved quantity.
  * Returns 0 or a negative code.  stats accumulate. */
-int orc_run(int64_t n, double *q, double *v, double *F, const double *L, const orc_params *p,
-            int64_t nsteps, int64_t energy_every, double *ke_out, double *pe_out,
-            orc_stats *stats, int32_t F_valid) {
+int orc_run_obs(int64_t n, double *q, double *v, double *F, const double *L, const orc_params *p,
+                orc_thermo *th, int64_t nsteps, int64_t energy_every, double *ke_out, double *pe_out,
+                double *vir_out, double *th_out, orc_stats *stats, int32_t F_valid) {
     orc_sys s;
     memset(&s, 0, sizeof(s));
     s.n = n; s.q = q; s.v = v; s.F = F;
@@ -511,6 +567,7 @@ int orc_run(int64_t n, double *q, double *v, double *F, const double *L, const o
     s.kp = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1));
     s.cap = 64 * n + 64;
     s.pl = (int32_t *)malloc(sizeof(int32_t) * (size_t)s.cap);
+    int thermo = th && th->tau > 0.0;
     int rcode = sys_build(&s, p);
     if (rcode != 0) goto done;
     if (!F_valid) {
@@ -526,6 +583,7 @@ int orc_run(int64_t n, double *q, double *v, double *F, const double *L, const o
     int64_t k = 0;
     for (int64_t step = 1; step <= nsteps; ++step) {
         double vmax2 = 0.0;
+        if (thermo) thermo_half(n, v, p->mass, th, 0.5 * p->dt);
         for (int64_t i = 0; i < 3 * n; ++i) v[i] = v[i] + h * F[i];
         for (int64_t i = 0; i < 3 * n; ++i) q[i] = q[i] + p->dt * v[i];
         for (int64_t i = 0; i < n; ++i) {
@@ -557,16 +615,25 @@ int orc_run(int64_t n, double *q, double *v, double *F, const double *L, const o
         if (p->verify) stats->missed_pairs += sys_missed(&s, p);
         double pe = orc_forces_list_rcp(n, q, s.L, p->rc, s.c2, s.c0, s.kp, s.pl, F, NULL, NULL, p->rcp);
         for (int64_t i = 0; i < 3 * n; ++i) v[i] = v[i] + h * F[i];
+        if (thermo) thermo_half(n, v, p->mass, th, 0.5 * p->dt);
         stats->steps += 1;
         if (energy_every > 0 && step % energy_every == 0) {
             ke_out[k] = orc_kinetic(n, v, p->mass);
             pe_out[k] = pe;
+            if (vir_out) vir_out[k] = orc_virial_list(n, q, s.L, p->rc, s.c2, s.kp, s.pl);
+            if (th_out) th_out[k] = thermo ? thermo_energy(n, th) : 0.0;
             ++k;
         }
     }
 done:
     free(s.qb); free(s.kp); free(s.pl);
     return rcode;
+}
+
+int orc_run(int64_t n, double *q, double *v, double *F, const double *L, const orc_params *p,
+            int64_t nsteps, int64_t energy_every, double *ke_out, double *pe_out,
+            orc_stats *stats, int32_t F_valid) {
+    return orc_run_obs(n, q, v, F, L, p, NULL, nsteps, energy_every, ke_out, pe_out, NULL, NULL, stats, F_valid);
 }
 
 /* Initial list and forces only (no step): wraps q, builds, fills F, returns PE. */

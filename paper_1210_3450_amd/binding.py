@@ -73,6 +73,10 @@ _SIGS = {
     "md_energy": (_S, [_P, _PD, _PD]),
     "md_batch_energy": (_S, [_P, _PD, _PD]),
     "md_energy_series": (_S, [_P, _PD, _PD, C.c_int32, _PI32]),
+    "md_observable_series": (_S, [_P, _PD, _PD, C.c_int32, _PI32]),
+    "md_pressure": (_S, [_P, _PD]),
+    "md_set_thermostat": (_S, [_P, _PD, C.c_double]),
+    "md_get_thermostat": (_S, [_P, _PD, _PD]),
     "md_get_cells": (_S, [_P, _P, _PI32]),
     "md_get_neighbors": (_S, [_P, _P, _P, C.c_int64, _PI64]),
     "md_get_stats": (_S, [_P, C.POINTER(md_stats)]),
@@ -229,6 +233,34 @@ class Context:
                                    C.byref(cnt)), "md_energy_series")
         k = min(cnt.value, max_samples)
         return ke[:k], pe[:k]
+
+    def observable_series(self, max_samples=4096):
+        """(vir, thermostat) per sample: pair virial sum_{i<j} f r^2 and Q xi^2/2 + g T eta."""
+        vir = np.zeros((max_samples, self.nbox))
+        th = np.zeros((max_samples, self.nbox))
+        cnt = C.c_int32()
+        self._chk(md_observable_series(self.ctx, vir.ctypes.data_as(_PD), th.ctypes.data_as(_PD), max_samples,
+                                       C.byref(cnt)), "md_observable_series")
+        k = min(cnt.value, max_samples)
+        return vir[:k], th[:k]
+
+    def pressure(self):
+        P = np.zeros(self.nbox)
+        self._chk(md_pressure(self.ctx, P.ctypes.data_as(_PD)), "md_pressure")
+        return P
+
+    def set_thermostat(self, T, tau):
+        """Nose-Hoover at temperature T (scalar or per box) with relaxation time tau (<= 0: off)."""
+        Tb = np.ascontiguousarray(np.broadcast_to(np.asarray(T if T is not None else 0.0, dtype=np.float64),
+                                                  (self.nbox,)))
+        self._chk(md_set_thermostat(self.ctx, Tb.ctypes.data_as(_PD), float(tau)), "md_set_thermostat")
+
+    def get_thermostat(self):
+        xi = np.zeros(self.nbox)
+        eta = np.zeros(self.nbox)
+        self._chk(md_get_thermostat(self.ctx, xi.ctypes.data_as(_PD), eta.ctypes.data_as(_PD)),
+                  "md_get_thermostat")
+        return xi, eta
 
     # ---- diagnostics
     def get_cells(self):

@@ -383,9 +383,12 @@ void free_all(md_ctx* c) {
     dfree(D.disp_s);
     dfree(D.ke_part);
     dfree(D.pe_part);
+    dfree(D.vir_part);
     dfree(D.dshift);
     dfree(D.series_ke);
     dfree(D.series_pe);
+    dfree(D.series_vir);
+    dfree(D.series_th);
     dfree(c->bk_pos);
     dfree(c->bk_vel);
     dfree(c->dscratch);
@@ -429,9 +432,12 @@ md_status alloc_all(md_ctx* c) {
     A(D.disp_s, (size_t)c->nbox * kStripes * kStripeStride);
     A(D.ke_part, (size_t)c->nwave * 8);
     A(D.pe_part, (size_t)c->nwave * 8);
+    A(D.vir_part, (size_t)c->nwave * 8);
     A(D.dshift, (size_t)27 * c->nbox);
     A(D.series_ke, (size_t)kMaxSeries * c->nbox);
     A(D.series_pe, (size_t)kMaxSeries * c->nbox);
+    A(D.series_vir, (size_t)kMaxSeries * c->nbox);
+    A(D.series_th, (size_t)kMaxSeries * c->nbox);
     A(c->bk_pos, (size_t)c->ntotal * 3);
     A(c->bk_vel, (size_t)c->ntotal * 3);
     A(c->dscratch, (size_t)c->nbox);
@@ -442,6 +448,7 @@ md_status alloc_all(md_ctx* c) {
     HIPCHK(c, hipMemsetAsync(D.disp_s, 0, sizeof(unsigned long long) * c->nbox * kStripes * kStripeStride, c->stream));
     HIPCHK(c, hipHostMalloc((void**)&c->st_h, sizeof(BoxState) * c->nbox, hipHostMallocDefault));
     std::memset(c->st_h, 0, sizeof(BoxState) * c->nbox);
+    for (int b = 0; b < c->nbox; ++b) c->st_h[b].vscale = 1.0;
     return MD_OK;
 }
 
@@ -614,9 +621,13 @@ md_status reset_states_for_new_state(md_ctx* c, bool keep_series) {
         BoxState& st = c->st_h[b];
         const int32_t ns = st.nseries, built = st.built;
         const unsigned long long missed = st.missed;
+        const double thT = st.thT, thQ = st.thQ;  // the thermostat setting survives a new state
         std::memset(&st, 0, sizeof(BoxState));
         st.built = built;
         st.missed = missed;
+        st.vscale = 1.0;
+        st.thT = thT;
+        st.thQ = thQ;
         if (keep_series) st.nseries = ns;
     }
     return push_states(c);
@@ -815,13 +826,39 @@ md_status md_step(md_ctx* c, int32_t nsteps, int32_t energy_every) {
     if ((s = ensure_list_and_forces(c)) != MD_OK) return s;
     if (nsteps == 0) return MD_OK;
     if ((s = sync_states(c)) != MD_OK) return s;
+    bool thermo = false;
+    for (int b = 0; b < c->nbox; ++b) thermo = thermo || c->st_h[b].thQ > 0.0;
     int32_t done = 0;
     while (done < nsteps) {
         const int32_t chunk = std::min(kChunk, nsteps - done);
         // checkpoint for a replay if the list overflows inside the chunk
         std::vector<BoxState> before(c->st_h, c->st_h + c->nbox);
         launch_get_state(c->D, c->P, c->bk_pos, c->bk_vel, c->nwave, c->stream);
-        for (int32_t k = 1; k <= chunk; ++k) {
+        for (int32_t k = 1; k <= chunk && thermo; ++k) {
+            // Nose-Hoover: every step is kick/drift, forces with the closing kick and the
+            // energy partials, then the thermostat half steps (end of this step and start
+            // of the next) folded into the next kick; the run ends with the velocities
+            // scaled by the closing half step's factor
+            const int32_t gk = done + k;
+            if (k == 1) {
+                launch_ke_partial(c->D, c->P, c->stream);
+                launch_energy_reduce(c->D, c->P, false, 2, c->stream);
+                launch_kick_drift(c->D, c->P, c->stream);
+                launch_dutc(c->D, c->P, c->stream);
+            }
+            const bool energy = energy_every > 0 && gk % energy_every == 0;
+            const bool last = k == chunk;
+            if ((s = enqueue_rebuild(c, true)) != MD_OK) return s;
+            if ((s = enqueue_force(c, kForceEnd, true)) != MD_OK) return s;
+            launch_energy_reduce(c->D, c->P, energy, last ? 1 : 3, c->stream);
+            if (last) {
+                launch_vscale(c->D, c->P, c->stream);
+            } else {
+                launch_kick_drift(c->D, c->P, c->stream);
+                launch_dutc(c->D, c->P, c->stream);
+            }
+        }
+        for (int32_t k = 1; k <= chunk && !thermo; ++k) {
             const int32_t gk = done + k;
             if (k == 1) {
                 launch_kick_drift(c->D, c->P, c->stream);
@@ -832,7 +869,7 @@ md_status md_step(md_ctx* c, int32_t nsteps, int32_t energy_every) {
             if (energy || last) {
                 if ((s = enqueue_rebuild(c, true)) != MD_OK) return s;
                 if ((s = enqueue_force(c, kForceEnd, energy)) != MD_OK) return s;
-                if (energy) launch_energy_reduce(c->D, c->P, true, c->stream);
+                if (energy) launch_energy_reduce(c->D, c->P, true, 0, c->stream);
                 if (!last) {
                     launch_kick_drift(c->D, c->P, c->stream);
                     launch_dutc(c->D, c->P, c->stream);
@@ -848,6 +885,10 @@ md_status md_step(md_ctx* c, int32_t nsteps, int32_t energy_every) {
         LAUNCHCHK(c);
         if ((s = sync_states(c)) != MD_OK) return s;
         if ((s = status_from_states(c)) != MD_OK) return s;
+        if (thermo) {  // k_vscale applied the pending factor: the next kick starts from 1
+            for (int b = 0; b < c->nbox; ++b) c->st_h[b].vscale = 1.0;
+            if ((s = push_states(c)) != MD_OK) return s;
+        }
         const int32_t need = max_need(c);
         if (need > c->P.cap) {
             // overflowed: restore the chunk's starting state, grow, rebuild, replay
@@ -886,7 +927,7 @@ static md_status energies(md_ctx* c) {
     if (!c->have_list && (s = build_list(c)) != MD_OK) return s;
     if ((s = enqueue_force(c, kForceOnly, true)) != MD_OK) return s;
     c->have_F = true;
-    launch_energy_reduce(c->D, c->P, false, c->stream);
+    launch_energy_reduce(c->D, c->P, false, 0, c->stream);
     LAUNCHCHK(c);
     return sync_states(c);
 }
@@ -925,6 +966,64 @@ md_status md_energy_series(md_ctx* c, double* ke, double* pe, int32_t max, int32
         HIPCHK(c, hipMemcpy(ke, c->D.series_ke, sizeof(double) * n * c->nbox, hipMemcpyDeviceToHost));
     if (n > 0 && pe)
         HIPCHK(c, hipMemcpy(pe, c->D.series_pe, sizeof(double) * n * c->nbox, hipMemcpyDeviceToHost));
+    return MD_OK;
+}
+
+md_status md_observable_series(md_ctx* c, double* vir, double* thermostat, int32_t max, int32_t* count) {
+    md_status s;
+    if ((s = check_ctx(c)) != MD_OK) return s;
+    if ((s = sync_states(c)) != MD_OK) return s;
+    int32_t n = c->st_h[0].nseries;
+    if (count) *count = n;
+    n = std::min(n, std::max(max, 0));
+    if (n > 0 && vir)
+        HIPCHK(c, hipMemcpy(vir, c->D.series_vir, sizeof(double) * n * c->nbox, hipMemcpyDeviceToHost));
+    if (n > 0 && thermostat)
+        HIPCHK(c, hipMemcpy(thermostat, c->D.series_th, sizeof(double) * n * c->nbox, hipMemcpyDeviceToHost));
+    return MD_OK;
+}
+
+md_status md_pressure(md_ctx* c, double* pressure) {
+    md_status s;
+    if ((s = check_ctx(c)) != MD_OK) return s;
+    if (!pressure) return fail(c, MD_EINVAL, "pressure must not be NULL");
+    if ((s = energies(c)) != MD_OK) return s;
+    for (int b = 0; b < c->nbox; ++b) {
+        const double V = c->boxes[b].box[0] * c->boxes[b].box[1] * c->boxes[b].box[2];
+        pressure[b] = (2.0 * c->st_h[b].ke - c->st_h[b].vir) / (3.0 * V);
+    }
+    return MD_OK;
+}
+
+md_status md_set_thermostat(md_ctx* c, const double* T, double tau) {
+    md_status s;
+    if ((s = check_ctx(c)) != MD_OK) return s;
+    if (!std::isfinite(tau)) return fail(c, MD_EINVAL, "tau must be finite");
+    if (tau > 0.0) {
+        if (!T) return fail(c, MD_EINVAL, "T must not be NULL when tau > 0");
+        for (int b = 0; b < c->nbox; ++b)
+            if (!(T[b] > 0.0) || !std::isfinite(T[b])) return fail(c, MD_EINVAL, "T[%d] must be > 0", b);
+    }
+    if ((s = sync_states(c)) != MD_OK) return s;
+    for (int b = 0; b < c->nbox; ++b) {
+        BoxState& st = c->st_h[b];
+        const double g = 3.0 * (double)c->boxes[b].n - 3.0;
+        st.thT = tau > 0.0 ? T[b] : 0.0;
+        st.thQ = tau > 0.0 ? g * T[b] * tau * tau : 0.0;
+        st.xi = st.eta = 0.0;
+        st.vscale = 1.0;
+    }
+    return push_states(c);
+}
+
+md_status md_get_thermostat(md_ctx* c, double* xi, double* eta) {
+    md_status s;
+    if ((s = check_ctx(c)) != MD_OK) return s;
+    if ((s = sync_states(c)) != MD_OK) return s;
+    for (int b = 0; b < c->nbox; ++b) {
+        if (xi) xi[b] = c->st_h[b].xi;
+        if (eta) eta[b] = c->st_h[b].eta;
+    }
     return MD_OK;
 }
 

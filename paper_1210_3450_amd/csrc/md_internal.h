@@ -91,6 +91,10 @@ struct BoxState {
     double ke, pe;             // last reduced energies
     int32_t nseries;           // energy samples recorded
     int32_t pad;
+    double vir;                // last reduced pair virial sum_{i<j} f r^2
+    double xi, eta;            // Nose-Hoover thermostat variable and its time integral
+    double vscale;             // velocity factor the next kick applies (thermostat; 1 otherwise)
+    double thT, thQ;           // thermostat temperature and mass (thQ = 0: no thermostat)
 };
 
 struct Params {
@@ -140,9 +144,12 @@ struct Dev {
     unsigned long long* disp_s;  // [nbox][kStripes] striped max |q - q_build|^2 (bits)
     double* ke_part;     // per list wave
     double* pe_part;
+    double* vir_part;
     double4* dshift;     // [nbox][27] FP64 image shift s * L
     double* series_ke;   // [kMaxSeries][nbox]
     double* series_pe;
+    double* series_vir;  // pair virial sum_{i<j} f r^2 at each sample
+    double* series_th;   // thermostat share Q xi^2 / 2 + g T eta at each sample
 };
 
 // Kernel modes of the force pass.
@@ -168,7 +175,12 @@ void launch_rebuild_chain(const Dev& d, const Params& p, bool with_list, hipStre
 void launch_force(const Dev& d, const Params& p, int mode, bool energy, hipStream_t s);
 void launch_kick_drift(const Dev& d, const Params& p, hipStream_t s);
 void launch_dutc(const Dev& d, const Params& p, hipStream_t s);
-void launch_energy_reduce(const Dev& d, const Params& p, bool record, hipStream_t s);
+// thermo: bit 0 applies the thermostat half step that ends a step (after the
+// closing kick), bit 1 the one that starts the next step; the velocity factor
+// goes to BoxState::vscale for the next kick (or k_vscale).
+void launch_energy_reduce(const Dev& d, const Params& p, bool record, int thermo, hipStream_t s);
+void launch_ke_partial(const Dev& d, const Params& p, hipStream_t s);
+void launch_vscale(const Dev& d, const Params& p, hipStream_t s);
 void launch_verify(const Dev& d, const Params& p, hipStream_t s);
 void launch_scale(const Dev& d, const Params& p, const double* alpha_q, const double* scale_v,
                   hipStream_t s);

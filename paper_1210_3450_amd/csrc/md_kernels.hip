@@ -825,6 +825,10 @@ __device__ __forceinline__ double kick(double v, double h, double f) {
 #pragma clang fp contract(off)
     return v + h * f;
 }
+__device__ __forceinline__ double scale(double v, double s) {
+#pragma clang fp contract(off)
+    return v * s;
+}
 __device__ __forceinline__ double drift(double x, double dt, double v) {
 #pragma clang fp contract(off)
     return x + dt * v;
@@ -848,7 +852,7 @@ __device__ __forceinline__ void stripe_put(unsigned long long* base, int b, int 
 template <int PREC, int MODE, int TPK, bool ENERGY>
 __device__ __forceinline__ void force_finish(const Dev& d, const Params& p, const BoxGeom& g, int b, int lw, int key,
                                              bool owner, const Pos& qi, uint32_t cc, int sq, int sp, double Fx,
-                                             double Fy, double Fz, double pe) {
+                                             double Fy, double Fz, double pe, double vir) {
     const int l = lane_id();
     if (TPK > 1) {
 #pragma unroll
@@ -856,7 +860,10 @@ __device__ __forceinline__ void force_finish(const Dev& d, const Params& p, cons
             Fx += __shfl_xor(Fx, o);
             Fy += __shfl_xor(Fy, o);
             Fz += __shfl_xor(Fz, o);
-            if (ENERGY) pe += __shfl_xor(pe, o);
+            if (ENERGY) {
+                pe += __shfl_xor(pe, o);
+                vir += __shfl_xor(vir, o);
+            }
         }
     }
     double ke = 0.0, w2 = 0.0, m2 = 0.0;
@@ -910,9 +917,11 @@ __device__ __forceinline__ void force_finish(const Dev& d, const Params& p, cons
     if (ENERGY) {
         const double ks = wave_sum(ke);
         const double ps = wave_sum(owner ? pe : 0.0);
+        const double vs = wave_sum(owner ? vir : 0.0);
         if (l == 0) {
             d.ke_part[lw] = ks;
             d.pe_part[lw] = ps;
+            d.vir_part[lw] = vs;
         }
     }
 }
@@ -1000,7 +1009,7 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Params p) {
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 
-    double Fx = 0.0, Fy = 0.0, Fz = 0.0, pe = 0.0;
+    double Fx = 0.0, Fy = 0.0, Fz = 0.0, pe = 0.0, vir = 0.0;  // vir: sum_j f r^2 (energy passes)
     // The pair loop, instantiated twice so the choice between the LDS table and
     // direct lookups is made once per wavefront, outside the loop.
     auto pair_loop = [&](auto tabled_c) {
@@ -1076,7 +1085,10 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Params p) {
                     Fx += f * dx;
                     Fy += f * dy;
                     Fz += f * dz;
-                    if (ENERGY) pe += in ? 2.0 * (e + p.c2 * r2 + p.c0) : 0.0;
+                    if (ENERGY) {
+                        pe += in ? 2.0 * (e + p.c2 * r2 + p.c0) : 0.0;
+                        vir += in ? f * r2 : 0.0;
+                    }
                 }
             };
             for (int c = 0; c < nfull; ++c) chunk(c, std::false_type{}, U);
@@ -1087,7 +1099,7 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Params p) {
             const int nux = -ui.x, nuy = -ui.y, nuz = -ui.z;
             // lengths stay in fixed-point units: r^2 in units^2, 1/r^2 rescaled once
             const float rc2u = g.rc2u, lam2inv = g.lam2inv, lam2 = g.lam * g.lam, c2x8 = 8.0f * p.c2f;
-            float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f, pes = 0.f;
+            float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f, pes = 0.f, virs = 0.f;
             auto chunk = [&](int c, auto chk_c, int valid) {
                 constexpr bool CHK = decltype(chk_c)::value;
                 const uint4 raw = raw_next;
@@ -1121,7 +1133,10 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Params p) {
                     bx += f * dx;
                     by += f * dy;
                     bz += f * dz;
-                    if (ENERGY) pes += in ? 2.0f * (inv3 * inv3 - inv3 + p.c2f * (r2 * lam2) + p.c0f) : 0.0f;
+                    if (ENERGY) {
+                        pes += in ? 2.0f * (inv3 * inv3 - inv3 + p.c2f * (r2 * lam2) + p.c0f) : 0.0f;
+                        virs += in ? f * r2 : 0.0f;  // units^2: times lam^2 below
+                    }
                 }
                 kahan_add(sx, cx, bx);  // compensated across batches
                 kahan_add(sy, cy, by);
@@ -1134,6 +1149,7 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Params p) {
             Fy = ((double)sy - (double)cy) * lam;
             Fz = ((double)sz - (double)cz) * lam;
             pe = (double)pes;
+            vir = (double)virs * lam * lam;
         }
     };
     if (active) {
@@ -1142,7 +1158,8 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Params p) {
         else
             pair_loop(std::false_type{});
     }
-    force_finish<PREC, MODE, TPK, ENERGY>(d, p, g, b, lw, key, active && sub == 0, qi, cc, sq, sp, Fx, Fy, Fz, pe);
+    force_finish<PREC, MODE, TPK, ENERGY>(d, p, g, b, lw, key, active && sub == 0, qi, cc, sq, sp, Fx, Fy, Fz, pe,
+                                          vir);
 }
 
 // FP32-mixed force pass with LDS-staged partner tiles (one lane per key).  The
@@ -1324,7 +1341,7 @@ __global__ __launch_bounds__(kBlock) void k_force_tile(Dev d, Params p) {
     __syncthreads();
     if (!wave_ok) return;
     const int sp = d.st[b].sp;
-    double Fx = 0.0, Fy = 0.0, Fz = 0.0, pe = 0.0;
+    double Fx = 0.0, Fy = 0.0, Fz = 0.0, pe = 0.0, vir = 0.0;
     if (active) {
         const int nl = qi.cnt;
         const int nfull = nl >> 3, ntail = nl & 7;
@@ -1339,7 +1356,7 @@ __global__ __launch_bounds__(kBlock) void k_force_tile(Dev d, Params p) {
         };
         const int4 ui = units3(qi, cc, g);
         const float rc2u = g.rc2u, lam2inv = g.lam2inv, lam2 = g.lam * g.lam, c2x8 = 8.0f * p.c2f;
-        float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f, pes = 0.f;
+        float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f, pes = 0.f, virs = 0.f;
         uint4 raw_next = nl > 0 ? l4[0] : make_uint4(0u, 0u, 0u, 0u);
         // one chunk of 8 entries: fetch the 8 partners, then the pair math on exact
         // integer separations (one rounding to FP32 each)
@@ -1401,7 +1418,10 @@ __global__ __launch_bounds__(kBlock) void k_force_tile(Dev d, Params p) {
                     bx += f * dx;
                     by += f * dy;
                     bz += f * dz;
-                    if (ENERGY) pes += in ? 2.0f * (inv3 * inv3 - inv3 + p.c2f * (r2 * lam2) + p.c0f) : 0.0f;
+                    if (ENERGY) {
+                        pes += in ? 2.0f * (inv3 * inv3 - inv3 + p.c2f * (r2 * lam2) + p.c0f) : 0.0f;
+                        virs += in ? f * r2 : 0.0f;  // units^2: times lam^2 below
+                    }
                 }
                 kahan_add(sx, cx, bx);  // compensated across batches
                 kahan_add(sy, cy, by);
@@ -1419,8 +1439,10 @@ __global__ __launch_bounds__(kBlock) void k_force_tile(Dev d, Params p) {
         Fy = ((double)sy - (double)cy) * lam;
         Fz = ((double)sz - (double)cz) * lam;
         pe = (double)pes;
+        vir = (double)virs * lam * lam;
     }
-    force_finish<MD_PREC_FP32_MIXED, MODE, 1, ENERGY>(d, p, g, b, lw, key, active, qi, cc, sq, sp, Fx, Fy, Fz, pe);
+    force_finish<MD_PREC_FP32_MIXED, MODE, 1, ENERGY>(d, p, g, b, lw, key, active, qi, cc, sq, sp, Fx, Fy, Fz, pe,
+                                                      vir);
 }
 
 // First half kick and drift from stored forces (start of a chunk of steps).
@@ -1433,9 +1455,10 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(Dev d, Params p) {
         const int sq = d.st[b].sq, sp = d.st[b].sp;
         double w2 = 0.0, m2 = 0.0;
         if (s - g.slot_off < g.npart) {
-            const double vx = kick(d.vx[sp][s], p.h, d.fx[s]);
-            const double vy = kick(d.vy[sp][s], p.h, d.fy[s]);
-            const double vz = kick(d.vz[sp][s], p.h, d.fz[s]);
+            const double vs = d.st[b].vscale;  // thermostat factor; 1 (exact) otherwise
+            const double vx = kick(scale(d.vx[sp][s], vs), p.h, d.fx[s]);
+            const double vy = kick(scale(d.vy[sp][s], vs), p.h, d.fy[s]);
+            const double vz = kick(scale(d.vz[sp][s], vs), p.h, d.fz[s]);
             d.vx[sp][s] = vx;
             d.vy[sp][s] = vy;
             d.vz[sp][s] = vz;
@@ -1459,38 +1482,105 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(Dev d, Params p) {
 }
 
 // Per-box energies from per-wave partials, in a fixed order (deterministic).
-__global__ __launch_bounds__(kBlock) void k_energy_reduce(Dev d, Params p, int record) {
-    __shared__ double ks[kBlock], ps[kBlock];
+// Per box: KE, PE and pair virial from the per-wave partials in a fixed order;
+// optionally the Nose-Hoover half steps around the step boundary (one thread per
+// box, the velocity factor left in BoxState::vscale) and a sample of the series.
+// Thermostat half step of length h: xi += (h/2) G; factor exp(-xi h) (KE scales by
+// its square); eta += xi h; xi += (h/2) G, with G = (2 KE - g T) / Q, g = 3N - 3.
+__global__ __launch_bounds__(kBlock) void k_energy_reduce(Dev d, Params p, int record, int thermo) {
+    __shared__ double ks[kBlock], ps[kBlock], vs[kBlock];
     for (int b = blockIdx.x; b < p.nbox; b += gridDim.x) {
         const BoxGeom& g = d.geom[b];
         const int K = kWave / p.tpk;
         const int w0 = g.slot_off / K, w1 = (g.slot_off + g.nslot) / K;
-        double k = 0.0, e = 0.0;
+        double k = 0.0, e = 0.0, v = 0.0;
         for (int w = w0 + threadIdx.x; w < w1; w += kBlock) {
             k += d.ke_part[w];
             e += d.pe_part[w];
+            v += d.vir_part[w];
         }
         ks[threadIdx.x] = k;
         ps[threadIdx.x] = e;
+        vs[threadIdx.x] = v;
         __syncthreads();
         for (int o = kBlock / 2; o > 0; o >>= 1) {
             if (threadIdx.x < o) {
                 ks[threadIdx.x] += ks[threadIdx.x + o];
                 ps[threadIdx.x] += ps[threadIdx.x + o];
+                vs[threadIdx.x] += vs[threadIdx.x + o];
             }
             __syncthreads();
         }
         if (threadIdx.x == 0) {
             BoxState& st = d.st[b];
-            st.ke = ks[0];
+            double ke = ks[0], ke_s = ks[0], th = 0.0;  // ke_s, th: values at the sample time
+            if (thermo && st.thQ > 0.0) {
+                const double gT = (3.0 * g.npart - 3.0) * st.thT, Q = st.thQ, h = 0.5 * p.dt;
+                double xi = st.xi, eta = st.eta, f = 1.0;
+                for (int half = 0; half < 2; ++half) {  // 0: ends this step, 1: starts the next
+                    if (!(thermo & (1 << half))) continue;
+                    xi = xi + 0.5 * h * ((2.0 * ke - gT) / Q);
+                    const double sc = exp(-xi * h);
+                    f = f * sc;
+                    ke = ke * (sc * sc);
+                    eta = eta + xi * h;
+                    xi = xi + 0.5 * h * ((2.0 * ke - gT) / Q);
+                    if (half == 0) {
+                        ke_s = ke;
+                        th = 0.5 * Q * xi * xi + gT * eta;
+                    }
+                }
+                st.xi = xi;
+                st.eta = eta;
+                st.vscale = f;
+            }
+            st.ke = ke_s;
             st.pe = ps[0];
+            st.vir = 0.5 * vs[0];  // every pair appears in both keys' lists
             if (record && st.nseries < kMaxSeries) {
-                d.series_ke[(size_t)st.nseries * p.nbox + b] = ks[0];
-                d.series_pe[(size_t)st.nseries * p.nbox + b] = ps[0];
+                const size_t at = (size_t)st.nseries * p.nbox + b;
+                d.series_ke[at] = ke_s;
+                d.series_pe[at] = ps[0];
+                d.series_vir[at] = 0.5 * vs[0];
+                d.series_th[at] = th;
                 st.nseries += 1;
             }
         }
         __syncthreads();
+    }
+}
+
+// KE partials of the current velocities, in the per-list-wave layout the
+// reduction reads (a slot wave's sum in its first list wave, zeros in the others).
+__global__ __launch_bounds__(kBlock) void k_ke_partial(Dev d, Params p) {
+    const int l = lane_id();
+    for (int w = blockIdx.x * 4 + (threadIdx.x >> 6); w < p.nwave; w += gridDim.x * 4) {
+        const int b = d.wave_box[w];
+        const BoxGeom& g = d.geom[b];
+        const int s = w * kWave + l, sp = d.st[b].sp;
+        const double k = s - g.slot_off < g.npart ? 0.5 * p.mass * norm2(d.vx[sp][s], d.vy[sp][s], d.vz[sp][s])
+                                                  : 0.0;
+        const double ks = wave_sum(k);
+        if (l < p.tpk) {
+            d.ke_part[w * p.tpk + l] = l == 0 ? ks : 0.0;
+            d.pe_part[w * p.tpk + l] = 0.0;
+            d.vir_part[w * p.tpk + l] = 0.0;
+        }
+    }
+}
+
+// Apply the pending thermostat factor to the velocities (end of a run of steps).
+__global__ __launch_bounds__(kBlock) void k_vscale(Dev d, Params p) {
+    const int l = lane_id();
+    for (int w = blockIdx.x * 4 + (threadIdx.x >> 6); w < p.nwave; w += gridDim.x * 4) {
+        const int b = d.wave_box[w];
+        const BoxGeom& g = d.geom[b];
+        const int s = w * kWave + l, sp = d.st[b].sp;
+        if (s - g.slot_off >= g.npart) continue;
+        const double f = d.st[b].vscale;
+        d.vx[sp][s] = scale(d.vx[sp][s], f);
+        d.vy[sp][s] = scale(d.vy[sp][s], f);
+        d.vz[sp][s] = scale(d.vz[sp][s], f);
     }
 }
 
@@ -1676,8 +1766,14 @@ void launch_kick_drift(const Dev& d, const Params& p, hipStream_t s) {
 void launch_dutc(const Dev& d, const Params& p, hipStream_t s) {
     k_dutc<<<p.nbox < 1024 ? p.nbox : 1024, kBlock, 0, s>>>(d, p);
 }
-void launch_energy_reduce(const Dev& d, const Params& p, bool record, hipStream_t s) {
-    k_energy_reduce<<<p.nbox < 1024 ? p.nbox : 1024, kBlock, 0, s>>>(d, p, record ? 1 : 0);
+void launch_energy_reduce(const Dev& d, const Params& p, bool record, int thermo, hipStream_t s) {
+    k_energy_reduce<<<p.nbox < 1024 ? p.nbox : 1024, kBlock, 0, s>>>(d, p, record ? 1 : 0, thermo);
+}
+void launch_ke_partial(const Dev& d, const Params& p, hipStream_t s) {
+    k_ke_partial<<<grid_for_waves(p.nwave), kBlock, 0, s>>>(d, p);
+}
+void launch_vscale(const Dev& d, const Params& p, hipStream_t s) {
+    k_vscale<<<grid_for_waves(p.nwave), kBlock, 0, s>>>(d, p);
 }
 void launch_verify(const Dev& d, const Params& p, hipStream_t s) {
     k_verify<<<grid_for_waves(p.nwave), kBlock, 0, s>>>(d, p);

@@ -528,3 +528,90 @@ def test_batch_trajectory_matches_per_box_runs():
         reb += r.rebuilds
         off += n
     assert st["rebuilds"] == reb
+
+
+# ------------------------------------------------------------------ pressure and thermostat
+
+@pytest.mark.parametrize("name", ["fcc4000", "jitter_ragged", "clustered"])
+@pytest.mark.parametrize("precision,tol", [(0, 1e-12), (1, 1e-5)])
+def test_pressure_matches_oracle(name, precision, tol):
+    """Virial pressure P = (2 KE - sum_{i<j} f r^2) / (3 V) against the oracle."""
+    q, v, L = case(name)
+    with make_ctx(q, v, L, precision=precision) as c:
+        P = c.pressure()[0]
+    Lv = np.broadcast_to(np.asarray(L, dtype=np.float64), (3,))
+    Pr = oracle.pressure(oracle.kinetic(v), oracle.virial(q, L, 2.5), float(np.prod(Lv)))
+    assert P == pytest.approx(Pr, rel=tol, abs=tol * 1e-3)
+
+
+def test_virial_series_matches_oracle_at_the_final_state():
+    w = inputs.small_nve()
+    with make_ctx(w.pos, w.vel, w.box[0]) as c:
+        c.step(40, 10)
+        vir, th = c.observable_series()
+        q, _ = c.get_state()
+    assert vir.shape[0] == 4 and (th == 0).all()
+    assert vir[-1, 0] == pytest.approx(oracle.virial(q.cpu().numpy(), w.box, 2.5), rel=1e-12)
+
+
+def test_thermostat_trajectory_matches_oracle():
+    """Nose-Hoover at T = 1.5, tau = 0.1 (FP64), 100 steps: positions within 1e-9
+    of the oracle's, energies, thermostat share and xi alike."""
+    w = inputs.small_nve()
+    r = oracle.run_obs(w.pos, w.vel, w.box, 100, energy_every=10, T=1.5, tau=0.1)
+    with make_ctx(w.pos, w.vel, w.box[0]) as c:
+        c.set_thermostat(1.5, 0.1)
+        c.step(60, 10)
+        c.step(40, 10)  # two calls: the half steps across a call boundary
+        q, v = c.get_state()
+        ke, pe = c.energy_series()
+        vir, th = c.observable_series()
+        xi, eta = c.get_thermostat()
+    d = _wrapdiff(q.cpu().numpy(), r.q, w.box)
+    assert np.abs(d).max() < 1e-9
+    np.testing.assert_allclose(ke[:, 0], r.ke, rtol=1e-9)
+    np.testing.assert_allclose(pe[:, 0], r.pe, rtol=1e-9)
+    np.testing.assert_allclose(vir[:, 0], r.vir, rtol=1e-9)
+    np.testing.assert_allclose(th[:, 0], r.thermo, rtol=1e-8, atol=1e-8)
+    assert xi[0] == pytest.approx(r.xi, rel=1e-8, abs=1e-10)
+
+
+def test_thermostat_with_infinite_mass_equals_nve_bitwise():
+    """With Q ~ 1e304 the friction stays ~1e-303 and every factor exp(-xi dt/2)
+    rounds to 1: the run equals plain NVE bit for bit.  Energies are sampled
+    every step so that both runs evaluate forces with the same kernel variant."""
+    w = inputs.small_nve()
+    out = []
+    for tau in (0.0, 1e150):
+        with make_ctx(w.pos, w.vel, w.box[0]) as c:
+            c.set_thermostat(2.0, tau)
+            c.step(50, 1)
+            q, v = c.get_state()
+            out.append((q.cpu().numpy(), v.cpu().numpy(), c.energy_series()[0]))
+    np.testing.assert_array_equal(out[0][0], out[1][0])
+    np.testing.assert_array_equal(out[0][1], out[1][1])
+    np.testing.assert_array_equal(out[0][2], out[1][2])
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_thermostat_ensemble_reaches_each_box_temperature(precision):
+    """Three boxes with targets 0.8, 1.2, 1.6: each box's temperature over the last
+    half of 1000 steps averages to its own target; the extended energy holds."""
+    b = B()
+    spec = inputs.batch_spec(3, seed=41, nmin=3000, nmax=5000)
+    boxes = [inputs.batch_box(spec, k) for k in range(3)]
+    pos = np.concatenate([p for p, _, _ in boxes])
+    vel = np.concatenate([v for _, v, _ in boxes])
+    params = [b.make_params(p.shape[0], L, precision=precision) for p, _, L in boxes]
+    T0 = np.array([0.8, 1.2, 1.6])
+    with b.Context(params) as c:
+        c.set_state(pos, vel)
+        c.set_thermostat(T0, 0.1)
+        c.step(1000, 10)
+        ke, pe = c.energy_series()
+        _, th = c.observable_series()
+    n = np.array([p.shape[0] for p, _, _ in boxes])
+    T = 2 * ke / (3 * n - 3)
+    np.testing.assert_allclose(T[T.shape[0] // 2:].mean(axis=0), T0, rtol=0.06)
+    H = ke + pe + th
+    assert (np.abs(H - H[0]).max(axis=0) / ke[0]).max() < 5e-3

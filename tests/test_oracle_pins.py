@@ -392,3 +392,61 @@ def test_reciprocal_correction_restores_energy_conservation():
         dev[mode] = float(np.abs(E - E[0]).max() / abs(E[0]))
     assert dev[oracle.RCP_APPROX] > 3.0 * dev[oracle.RCP_APPROX_CORR]
     assert dev[oracle.RCP_APPROX_CORR] < 1.5 * dev[oracle.RCP_DIV] + 1e-5
+
+
+# ---------------------------------------------------------------- virial and thermostat
+
+def test_virial_is_the_scaling_derivative_of_the_energy():
+    """sum_{i<j} f r^2 = sum_{i<j} V'(r) r = d PE(lambda q, lambda L) / d lambda at 1,
+    by central differences of the oracle's energy (V and V' vanish at rc, so the
+    derivative is smooth)."""
+    q = inputs.random_box(500, (10.5, 11.0, 12.0), 21, min_sep=0.85)
+    L = np.array([10.5, 11.0, 12.0])
+    w = oracle.virial(q, L, 2.5)
+    h = 1e-6
+    _, pp, _ = oracle.forces(q * (1 + h), L * (1 + h), 2.5, 0.3)
+    _, pm, _ = oracle.forces(q * (1 - h), L * (1 - h), 2.5, 0.3)
+    assert w == pytest.approx((pp - pm) / (2 * h), rel=1e-7)
+
+
+def test_fcc_lattice_virial_from_shells():
+    """At rest on the rho = 0.5 FCC lattice (rc = 2.5): sum_{i<j} f r^2 per site is
+    1/2 sum over the shells inside rc of n_k f(r_k) r_k^2, with f from the
+    coefficients of the independent linear solve."""
+    c2, _ = pb.lj_coeffs(2.5)
+
+    def f(r2):
+        return 24.0 * r2 ** -4 - 48.0 * r2 ** -7 + 8.0 * c2
+
+    per_site = 0.5 * sum(cnt * f(s2 * 1.0) * s2 for s2, cnt in _fcc_shells() if s2 < 6.25)
+    q = inputs.fcc_positions(5, 2.0)
+    assert oracle.virial(q, 10.0, 2.5) / 500 == pytest.approx(per_site, rel=1e-13)
+    assert oracle.pressure(0.0, oracle.virial(q, 10.0, 2.5), 1000.0) == pytest.approx(-per_site * 500 / 3000.0,
+                                                                                       rel=1e-13)
+
+
+def test_thermostat_with_infinite_mass_is_nve():
+    """A Nose-Hoover thermostat whose mass is effectively infinite leaves the
+    velocity-Verlet trajectory unchanged bit for bit."""
+    w = inputs.small_nve()
+    a = oracle.run(w.pos, w.vel, w.box, 60, energy_every=10)
+    b = oracle.run_obs(w.pos, w.vel, w.box, 60, energy_every=10, T=2.0, tau=1e150)
+    np.testing.assert_array_equal(a.q, b.q)
+    np.testing.assert_array_equal(a.v, b.v)
+    np.testing.assert_array_equal(a.ke, b.ke)
+
+
+@pytest.mark.slow
+def test_thermostat_conserves_extended_energy_and_reaches_temperature():
+    """Heating from T = 1.0 to T = 1.5 with tau = 0.1: KE + PE changes by far more
+    than its NVE fluctuation while KE + PE + Q xi^2 / 2 + g T eta stays conserved
+    to the NVE level, and the temperature of the second half averages to 1.5."""
+    w = inputs.small_nve()
+    r = oracle.run_obs(w.pos, w.vel, w.box, 2000, energy_every=10, T=1.5, tau=0.1)
+    E = r.ke + r.pe
+    H = E + r.thermo
+    g = 3 * w.n - 3
+    T = 2 * r.ke / g
+    assert abs(E[-1] - E[0]) / abs(E[0]) > 0.2
+    assert np.abs(H - H[0]).max() / abs(H[0]) < 2e-3
+    assert T[T.size // 2:].mean() == pytest.approx(1.5, rel=0.05)
