@@ -108,6 +108,9 @@ def lib():
         L.orc_run.restype = C.c_int
         L.orc_initial_forces.argtypes = [C.c_int64, P_D, P_D, C.POINTER(OrcParams), P_D]
         L.orc_initial_forces.restype = C.c_double
+        L.orc_bubbles.argtypes = [C.c_int64, P_D, P_D, C.c_double, C.c_double, C.POINTER(C.c_uint8), P_I32]
+        L.orc_bubbles.restype = C.c_int64
+        L.orc_subcell_grid.argtypes = [P_D, C.c_double, P_I32, P_D, P_D, C.c_double]
         _lib = L
     return _lib
 
@@ -366,3 +369,37 @@ def initial_forces(q, L, rc=2.5, skin=0.3, mode=CUT_EQ1):
 def csr_sets(kp, pl):
     """Per-key partner arrays of a CSR list."""
     return [pl[kp[i]:kp[i + 1]] for i in range(len(kp) - 1)]
+
+
+@dataclass
+class BubbleResult:
+    nsub: tuple          # subcells per axis (nx, ny, nz)
+    threshold: float     # gas iff count < threshold
+    counts: np.ndarray   # uint8 [nz * ny * nx], linear index (cz*ny + cy)*nx + cx
+    labels: np.ndarray   # int32, smallest linear index of the subcell's bubble; -1 liquid
+    roots: np.ndarray    # int64 bubble labels, ascending
+    sizes: np.ndarray    # int64 subcells per bubble, in the order of roots
+
+
+def bubbles(q, L, side=3.0, rho_gas=0.2) -> BubbleResult:
+    """Bubble identification of Sec. IV.B: byte counts per subcell of edge
+    >= side, gas iff count < rho_gas * subcell volume, face-adjacent gas
+    subcells (periodic) form one bubble."""
+    q = _q(q)
+    Lb = _box(L)
+    ns = np.zeros(3, dtype=np.int32)
+    inv = np.zeros(3)
+    thr = C.c_double()
+    lib().orc_subcell_grid(_pd(Lb), side, ns.ctypes.data_as(P_I32), _pd(inv), C.byref(thr), rho_gas)
+    nsub = int(np.prod(ns.astype(np.int64)))
+    counts = np.zeros(nsub, dtype=np.uint8)
+    labels = np.zeros(nsub, dtype=np.int32)
+    nb = lib().orc_bubbles(q.shape[0], _pd(q), _pd(Lb), side, rho_gas,
+                           counts.ctypes.data_as(C.POINTER(C.c_uint8)), labels.ctypes.data_as(P_I32))
+    if nb < 0:
+        raise ValueError("orc_bubbles failed (%d)" % nb)
+    gas = labels[labels >= 0]
+    roots, sizes = np.unique(gas, return_counts=True)
+    assert roots.shape[0] == nb
+    return BubbleResult(tuple(int(x) for x in ns), thr.value, counts, labels, roots.astype(np.int64),
+                        sizes.astype(np.int64))

@@ -182,3 +182,34 @@ def random_box(n: int, L, seed: int, min_sep: float = 0.0) -> np.ndarray:
     idx = np.indices((m, m, m)).reshape(3, -1).T[:, ::-1][:n].astype(np.float64)
     q = (idx + 0.5) * s + rng.uniform(-amp, amp, size=(n, 3))
     return np.ascontiguousarray(np.mod(q, Lv))
+
+
+def subcell_field_positions(counts: np.ndarray, L, seed: int, margin: float = 0.01) -> np.ndarray:
+    """Positions that realise a given count field: counts[z, y, x] particles drawn
+    uniformly inside subcell (x, y, z) of a regular nx*ny*nz grid over the box,
+    keeping a relative margin from the subcell faces so that no particle sits
+    on a boundary.  Returned in subcell order."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    counts = np.asarray(counts, dtype=np.int64)
+    nz, ny, nx = counts.shape
+    Lv = np.broadcast_to(np.asarray(L, dtype=np.float64), (3,))
+    e = Lv / np.array([nx, ny, nz])
+    z, y, x = np.nonzero(counts)
+    k = counts[z, y, x]
+    lo = np.repeat(np.stack([x, y, z], axis=1) * e, k, axis=0)
+    t = rng.uniform(margin, 1.0 - margin, size=(int(k.sum()), 3))
+    return lo + t * e
+
+
+def bubble_field(shape, p_gas: float, seed: int, liquid: int = 8, gas_max: int = 5, border: bool = False):
+    """A random gas/liquid pattern on a subcell grid (shape = (nz, ny, nx)) and a
+    count field for it: liquid subcells hold `liquid` particles, gas subcells
+    0..gas_max.  With border=True the outermost layer is liquid."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    gas = rng.uniform(size=shape) < p_gas
+    if border:
+        gas[0, :, :] = gas[-1, :, :] = False
+        gas[:, 0, :] = gas[:, -1, :] = False
+        gas[:, :, 0] = gas[:, :, -1] = False
+    counts = np.where(gas, rng.integers(0, gas_max + 1, size=shape), liquid)
+    return gas, counts

@@ -450,3 +450,130 @@ def test_thermostat_conserves_extended_energy_and_reaches_temperature():
     assert abs(E[-1] - E[0]) / abs(E[0]) > 0.2
     assert np.abs(H - H[0]).max() / abs(H[0]) < 2e-3
     assert T[T.size // 2:].mean() == pytest.approx(1.5, rel=0.05)
+
+
+# ------------------------------------------------------------------ bubble identification
+
+def _union_find_components(gas, periodic):
+    """Reference clustering: scipy's face-connected labelling, then, on a torus,
+    labels on opposite faces merged when both subcells are gas."""
+    from scipy import ndimage
+    lab, nl = ndimage.label(gas)
+    parent = list(range(nl + 1))
+
+    def find(a):
+        while parent[a] != a:
+            a = parent[a]
+        return a
+
+    if periodic:
+        for ax in range(3):
+            a = np.take(lab, 0, axis=ax)
+            b = np.take(lab, -1, axis=ax)
+            for u, v in zip(a[(a > 0) & (b > 0)], b[(a > 0) & (b > 0)]):
+                ru, rv = find(int(u)), int(find(int(v)))
+                if ru != rv:
+                    parent[max(ru, rv)] = min(ru, rv)
+    comp = np.array([find(k) for k in range(nl + 1)])[lab]
+    flat = comp.reshape(-1)
+    out = np.full(flat.shape, -1, dtype=np.int64)
+    idx = np.arange(flat.size)
+    for c in np.unique(flat[flat > 0]):
+        members = idx[flat == c]
+        out[members] = members.min()
+    return out
+
+
+def test_bubble_counts_match_histogram():
+    """Byte counts per subcell equal numpy's histogram over the same edges
+    (positions off the faces, some one box length outside [0, L))."""
+    L = (13.1, 9.7, 16.4)
+    rng = np.random.Generator(np.random.PCG64(3))
+    q = rng.uniform(0.0, 1.0, size=(2000, 3)) * np.array(L)
+    q[:200, 0] -= L[0]
+    q[200:400, 2] += L[2]
+    r = oracle.bubbles(q, L, 3.0, 0.2)
+    assert r.nsub == (4, 3, 5)
+    edges = [np.linspace(0.0, L[a], r.nsub[a] + 1) for a in range(3)]
+    H, _ = np.histogramdd(np.mod(q, np.array(L)), bins=edges)
+    np.testing.assert_array_equal(r.counts.reshape(5, 3, 4).transpose(2, 1, 0), H.astype(np.uint8))
+    assert r.threshold == pytest.approx(0.2 * (13.1 / 4) * (9.7 / 3) * (16.4 / 5), rel=1e-15)
+
+
+def test_bubble_threshold_and_saturation():
+    """Edge 3, volume 27: 5 particles (density 0.185) is gas and 6 (0.222) is
+    liquid at rho_gas = 0.2; 300 particles in one subcell saturate the byte."""
+    counts = np.full((4, 4, 4), 8)
+    counts[0, 0, 0] = 5
+    counts[1, 1, 1] = 6
+    counts[2, 2, 2] = 300
+    q = inputs.subcell_field_positions(counts, 12.0, 1)
+    r = oracle.bubbles(q, 12.0)
+    assert r.threshold == pytest.approx(5.4)
+    assert r.counts[0] == 5 and r.labels[0] == 0
+    assert r.counts[(1 * 4 + 1) * 4 + 1] == 6 and r.labels[(1 * 4 + 1) * 4 + 1] == -1
+    assert r.counts[(2 * 4 + 2) * 4 + 2] == 255
+    assert list(r.roots) == [0] and list(r.sizes) == [1]
+
+
+@pytest.mark.parametrize("seed,p", [(1, 0.2), (2, 0.3), (3, 0.45)])
+def test_bubble_labels_match_scipy_interior(seed, p):
+    """Gas patterns kept off the box faces: clusters equal scipy's face-connected
+    labelling, each labelled by its smallest linear subcell index."""
+    shape = (8, 9, 10)
+    L = (30.0, 27.0, 24.0)
+    gas, counts = inputs.bubble_field(shape, p, seed, border=True)
+    q = inputs.subcell_field_positions(counts, L, seed)
+    r = oracle.bubbles(q, L)
+    assert r.nsub == (10, 9, 8)
+    np.testing.assert_array_equal(r.labels, _union_find_components(gas, periodic=False))
+
+
+@pytest.mark.parametrize("seed,p", [(4, 0.25), (5, 0.32), (6, 0.5)])
+def test_bubble_labels_match_scipy_periodic(seed, p):
+    """Gas patterns touching the faces: clusters equal scipy's labelling merged
+    across the periodic boundaries."""
+    shape = (7, 6, 9)
+    L = (27.0, 18.0, 21.0)
+    gas, counts = inputs.bubble_field(shape, p, seed)
+    q = inputs.subcell_field_positions(counts, L, seed + 10)
+    r = oracle.bubbles(q, L)
+    ref = _union_find_components(gas, periodic=True)
+    np.testing.assert_array_equal(r.labels, ref)
+    assert r.sizes.sum() == gas.sum()
+
+
+def test_bubble_special_shapes():
+    """A tube through the periodic x faces is one bubble; subcells touching only
+    along an edge are two; all gas is one bubble; all liquid is none."""
+    n = 6
+    L = 18.0
+
+    def run(gas):
+        counts = np.where(gas, 0, 9)
+        return oracle.bubbles(inputs.subcell_field_positions(counts, L, 7), L)
+
+    g = np.zeros((n, n, n), bool)
+    g[2, 3, :] = True
+    r = run(g)
+    assert list(r.sizes) == [n] and list(r.roots) == [(2 * n + 3) * n]
+    g = np.zeros((n, n, n), bool)
+    g[1, 1, 0] = g[1, 1, n - 1] = True         # neighbours across the x face
+    g[4, 4, 4] = g[4, 3, 3] = True             # edge contact only
+    r = run(g)
+    assert sorted(r.sizes.tolist()) == [1, 1, 2]
+    assert r.labels[(1 * n + 1) * n + n - 1] == (1 * n + 1) * n
+    r = run(np.ones((n, n, n), bool))
+    assert list(r.sizes) == [n ** 3] and list(r.roots) == [0]
+    r = run(np.zeros((n, n, n), bool))
+    assert r.roots.size == 0 and (r.labels == -1).all()
+
+
+def test_bubble_single_subcell_axis():
+    """An axis with one subcell is its own periodic neighbour."""
+    counts = np.zeros((1, 2, 3), dtype=np.int64)
+    counts[0, 1, :] = 30
+    q = inputs.subcell_field_positions(counts, (15.0, 10.0, 5.0), 2)
+    r = oracle.bubbles(q, (15.0, 10.0, 5.0), side=5.0, rho_gas=0.2)
+    assert r.nsub == (3, 2, 1)
+    assert list(r.roots) == [0] and list(r.sizes) == [3]
