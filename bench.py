@@ -211,46 +211,90 @@ def workload_medium(B, torch, args):
             "config": {"workload": "fcc1M_rho0.5_rc2.5_skin0.3_dt0.005", "graphs": True}, "paths": out}
 
 
+def bubble_summary(ctx, torch):
+    """md_bubbles at the current state (edge 3, gas below density 0.2), timed."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = ctx.bubbles(fields=False)
+    dt = time.perf_counter() - t0
+    sizes = r["sizes"]
+    hist = np.bincount(np.minimum(np.ceil(np.log2(np.maximum(sizes, 1))).astype(int), 20)).tolist() \
+        if sizes.size else []
+    return {"nbubbles": int(r["nbubbles"]), "gas_subcells": int(r["ngas"]), "largest": int(r["largest"]),
+            "subcells": int(np.prod(r["nsub"])), "size_hist_log2": hist, "wall_ms": dt * 1e3}
+
+
+def pressure_series(ke, vir, V, every, marks):
+    """Virial pressure P = (2 KE - W) / (3 V) at the recorded samples."""
+    P = (2.0 * ke - vir) / (3.0 * V)
+    out = {"every": every, "min": float(P.min()), "step_of_min": int((np.argmin(P) + 1) * every),
+           "last": float(P[-1])}
+    out["at_step"] = {str(m): float(P[m // every - 1]) for m in marks if 0 < m // every <= P.shape[0]}
+    return out
+
+
 def workload_cavitation(B, torch, args):
-    """Cavitation-style box: 128^3 simple-cubic sites at density 0.7 (2,097,152
-    particles, rc = 3.0, seed 4); equilibrated at T = 0.9 by velocity rescaling every
-    10 steps; all lengths expanded by 1.1 (density 0.526); 5000 NVE steps."""
+    """Cavitation protocol of Sec. IV: 128^3 simple-cubic sites at density 0.7
+    (2,097,152 particles, rc = 3.0, seed 4) held at T = 0.9 by a Nose-Hoover
+    thermostat (tau = 0.5); all lengths expanded by 1.1 (density 0.526), the
+    thermostat switched off, 5000 NVE steps.  Reports the virial pressure before
+    and after the expansion and along the NVE run, bubbles (edge-3 subcells,
+    gas below density 0.2) at NVE steps 0, 1000 and 5000, list-length
+    histograms, drift and throughput of both precisions."""
     from paper_1210_3450_amd import inputs
     w = inputs.cavitation_liquid(n_side=args.cav_side)
     res = {}
     stream = torch.cuda.Stream()
+    alpha = 1.1
     with torch.cuda.stream(stream):
         ctx = B.Context(B.make_params(w.n, w.box, rc=w.rc, skin=w.skin, dt=w.dt,
                                       precision=B.MD_PREC_FP32_MIXED, flags=B.MD_F_GRAPH), stream=stream)
         ctx.set_state(w.pos, w.vel)
         t0 = time.time()
-        for _ in range(args.cav_equil // 10):
-            ctx.step(10)
-            ke, _ = ctx.energy()
-            T = 2.0 * ke / (3 * w.n - 3)
-            ctx.scale_velocities(math.sqrt(w.T / T))
-        ke, pe = ctx.energy()
-        res["equilibration"] = {"steps": args.cav_equil, "T_end": 2.0 * ke / (3 * w.n - 3),
-                                "pe_per_particle": pe / w.n, "wall_s": time.time() - t0}
-        ctx.rescale_box(1.1)
+        ctx.set_thermostat(w.T, 0.5)
+        every = max(1, args.cav_equil // 50)
+        ctx.step(args.cav_equil, every)
+        ke_s, pe_s = ctx.energy_series()
+        vir_s, th_s = ctx.observable_series()
+        V0 = w.box[0] ** 3
+        H = ke_s[:, 0] + pe_s[:, 0] + th_s[:, 0]
+        T_s = 2.0 * ke_s[:, 0] / (3 * w.n - 3)
+        half = T_s.shape[0] // 2
+        res["equilibration"] = {
+            "steps": args.cav_equil, "thermostat": "Nose-Hoover T=%.2f tau=0.5" % w.T,
+            "T_mean_second_half": float(T_s[half:].mean()), "T_end": float(T_s[-1]),
+            "pressure": pressure_series(ke_s[:, 0], vir_s[:, 0], V0, every, [every, args.cav_equil]),
+            "extended_energy_rel_dev": float(np.abs(H - H[0]).max() / abs(H[0])),
+            "pe_per_particle_end": float(pe_s[-1, 0] / w.n), "wall_s": time.time() - t0}
+        P_liq = float(ctx.pressure()[0])
+        ke, _ = ctx.energy()
+        ctx.set_thermostat(None, 0.0)
+        ctx.rescale_box(alpha)
         ke1, pe1 = ctx.energy()
-        res["after_expansion"] = {"box": w.box[0] * 1.1, "density": w.n / (w.box[0] * 1.1) ** 3,
+        P_exp = float(ctx.pressure()[0])
+        res["after_expansion"] = {"box": w.box[0] * alpha, "density": w.n / (w.box[0] * alpha) ** 3,
                                   "T": 2.0 * ke1 / (3 * w.n - 3), "pe_per_particle": pe1 / w.n,
-                                  "ke_unchanged": bool(abs(ke1 - ke) <= 1e-9 * abs(ke))}
+                                  "ke_unchanged": bool(abs(ke1 - ke) <= 1e-9 * abs(ke)),
+                                  "pressure_before": P_liq, "pressure_after": P_exp}
         p0, v0 = ctx.get_state()
         hist = {"0": list_histogram(ctx)}
+        bubbles = {"0": bubble_summary(ctx, torch)}
+        V1 = (w.box[0] * alpha) ** 3
         for name, prec in (("fp32_mixed", B.MD_PREC_FP32_MIXED), ("fp64", B.MD_PREC_FP64)):
-            c2 = B.Context(B.make_params(w.n, (w.box[0] * 1.1,) * 3, rc=w.rc, skin=w.skin, dt=w.dt,
+            c2 = B.Context(B.make_params(w.n, (w.box[0] * alpha,) * 3, rc=w.rc, skin=w.skin, dt=w.dt,
                                          precision=prec, flags=B.MD_F_GRAPH), stream=stream)
             c2.set_state(p0, v0)
             st0 = c2.stats()
             ms1 = timed_steps(c2, torch, stream, 1000, 10)
             if name == "fp32_mixed":
                 hist["1000"] = list_histogram(c2)
+                bubbles["1000"] = bubble_summary(c2, torch)
             ms2 = timed_steps(c2, torch, stream, args.cav_steps - 1000, 10)
             if name == "fp32_mixed":
                 hist[str(args.cav_steps)] = list_histogram(c2)
+                bubbles[str(args.cav_steps)] = bubble_summary(c2, torch)
             ke, pe = c2.energy_series()
+            vir, _ = c2.observable_series()
             st = c2.stats()
             ke_end, pe_end = c2.energy()
             c2.close()
@@ -258,9 +302,12 @@ def workload_cavitation(B, torch, args):
                          "particle_steps_per_s": w.n * args.cav_steps / ((ms1 + ms2) / 1e3),
                          "rebuilds": st["rebuilds"] - st0["rebuilds"], "list_regrows": st["list_regrows"],
                          "drift_%d_steps" % args.cav_steps: drift_stats(ke[:, 0], pe[:, 0], w.n, w.dt, 10),
+                         "pressure_nve": pressure_series(ke[:, 0], vir[:, 0], V1, 10,
+                                                         [10, 100, 200, 500, 1000, 2000, 3000, 5000]),
                          "T_end": 2.0 * ke_end / (3 * w.n - 3), "pe_per_particle_end": pe_end / w.n}
         ctx.close()
     res["list_length_histograms_nve_step"] = hist
+    res["bubbles_nve_step"] = bubbles
     return {"metric": "particle-steps/s, cavitation box (uneven lists), FP32-mixed on 1 MI355X",
             "value": res["fp32_mixed"]["particle_steps_per_s"], "unit": "particle-steps/s", "n_gpus": 1,
             "steps": args.cav_steps, "higher_is_better": True, "dtype": "f32 pair forces / f64 state",

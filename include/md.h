@@ -224,6 +224,42 @@ md_status md_pressure(md_ctx *ctx, double *pressure);
 md_status md_set_thermostat(md_ctx *ctx, const double *T, double tau);
 md_status md_get_thermostat(md_ctx *ctx, double *xi, double *eta);  /* host [nbox], nullable */
 
+/* ---- bubble identification (Sec. IV.B) ---------------------------------- */
+
+typedef struct {
+    int32_t nsub[3];   /* subcells per axis, floor(L / side) */
+    int32_t pad;
+    double side[3];    /* subcell edges L / nsub */
+    double threshold;  /* a subcell is gas iff its count < rho_gas * volume of a subcell */
+    int64_t ngas;      /* gas subcells */
+    int64_t nbubbles;  /* bubbles: clusters of face-adjacent gas subcells, periodic */
+    int64_t largest;   /* subcells in the largest bubble, 0 without bubbles */
+} md_bubble_info;
+
+/* Bubbles of box `box` at the current positions, as in the analysis of Sec. IV.B.
+ * The box is cut into nsub = floor(L / side) subcells per axis (edge L / nsub,
+ * so at least `side`); every particle is wrapped into [0, L) and binned with
+ * min((int)(x * nsub / L), nsub - 1).  A subcell's particle count is held in
+ * one unsigned byte (saturating at 255); the subcell is gas when that count is
+ * below rho_gas * (L0/n0) * (L1/n1) * (L2/n2) (FP64, evaluated left to right).
+ * Gas subcells sharing a face, across periodic faces too, form one bubble
+ * (site percolation on the simple cubic lattice); each bubble is labelled by
+ * its smallest linear subcell index (cz * ny + cy) * nx + cx.
+ *   counts  device uint8 [nsub total] or NULL: the byte counts;
+ *   labels  device int32 [nsub total] or NULL: bubble label, -1 for liquid;
+ *   roots, sizes  host int64 [cap] or NULL (cap = 0): the first min(cap,
+ *           nbubbles) bubbles in ascending label order and their sizes in
+ *           subcells;
+ *   info    host, required.
+ * MD_EINVAL: bad box index, side not finite or <= 0, rho_gas not finite or
+ * < 0, fewer than 1 or more than 1024 subcells on an axis, info NULL.
+ * MD_ESTATE without a state; MD_ENUMERIC for a position outside [-L, 2L).
+ * Work buffers (about 17 bytes per subcell) are allocated on the first call and
+ * grown when needed.  Synchronizing. */
+md_status md_bubbles(md_ctx *ctx, int32_t box, double side, double rho_gas, uint8_t *counts,
+                     int32_t *labels, int64_t *roots, int64_t *sizes, int64_t cap,
+                     md_bubble_info *info);
+
 /* ---- diagnostics and parity (synchronizing) ----------------------------- */
 
 /* Cell of every particle at the last binning, box-local linear id

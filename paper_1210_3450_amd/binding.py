@@ -52,6 +52,11 @@ class md_stats(C.Structure):
                 ("rebuild_ms", C.c_double), ("rebuild_launches", C.c_int64)]
 
 
+class md_bubble_info(C.Structure):
+    _fields_ = [("nsub", C.c_int32 * 3), ("pad", C.c_int32), ("side", C.c_double * 3), ("threshold", C.c_double),
+                ("ngas", C.c_int64), ("nbubbles", C.c_int64), ("largest", C.c_int64)]
+
+
 _P = C.c_void_p
 _PD = C.POINTER(C.c_double)
 _PI32 = C.POINTER(C.c_int32)
@@ -77,6 +82,8 @@ _SIGS = {
     "md_pressure": (_S, [_P, _PD]),
     "md_set_thermostat": (_S, [_P, _PD, C.c_double]),
     "md_get_thermostat": (_S, [_P, _PD, _PD]),
+    "md_bubbles": (_S, [_P, C.c_int32, C.c_double, C.c_double, _P, _P, _PI64, _PI64, C.c_int64,
+                        C.POINTER(md_bubble_info)]),
     "md_get_cells": (_S, [_P, _P, _PI32]),
     "md_get_neighbors": (_S, [_P, _P, _P, C.c_int64, _PI64]),
     "md_get_stats": (_S, [_P, C.POINTER(md_stats)]),
@@ -261,6 +268,39 @@ class Context:
         self._chk(md_get_thermostat(self.ctx, xi.ctypes.data_as(_PD), eta.ctypes.data_as(_PD)),
                   "md_get_thermostat")
         return xi, eta
+
+    # ---- bubble analysis
+    def bubbles(self, box=0, side=3.0, rho_gas=0.2, fields=True, cap=None):
+        """Bubbles of one box (md_bubbles).  Returns a dict: nsub (nx, ny, nz), side,
+        threshold, ngas, nbubbles, largest, roots and sizes (numpy int64, ascending
+        roots; all bubbles unless cap is given) and, with fields=True, the byte
+        counts and labels per subcell as device tensors (uint8, int32)."""
+        import torch
+        info = md_bubble_info()
+        counts = labels = None
+        torch.cuda.synchronize(self.device)
+        if fields:
+            self._chk(md_bubbles(self.ctx, int(box), float(side), float(rho_gas), None, None, None, None, 0,
+                                 C.byref(info)), "md_bubbles")
+            nsub = int(info.nsub[0]) * int(info.nsub[1]) * int(info.nsub[2])
+            counts = torch.empty(nsub, dtype=torch.uint8, device=self.device)
+            labels = torch.empty(nsub, dtype=torch.int32, device=self.device)
+        k = int(cap) if cap is not None else None
+        if k is None:
+            if not fields:
+                self._chk(md_bubbles(self.ctx, int(box), float(side), float(rho_gas), None, None, None, None, 0,
+                                     C.byref(info)), "md_bubbles")
+            k = int(info.nbubbles)
+        roots = np.zeros(max(k, 1), dtype=np.int64)
+        sizes = np.zeros(max(k, 1), dtype=np.int64)
+        self._chk(md_bubbles(self.ctx, int(box), float(side), float(rho_gas),
+                             _ptr(counts) if fields else None, _ptr(labels) if fields else None,
+                             roots.ctypes.data_as(_PI64), sizes.ctypes.data_as(_PI64), k, C.byref(info)),
+                  "md_bubbles")
+        m = min(k, int(info.nbubbles))
+        return {"nsub": tuple(info.nsub), "side": tuple(info.side), "threshold": info.threshold,
+                "ngas": info.ngas, "nbubbles": info.nbubbles, "largest": info.largest,
+                "roots": roots[:m], "sizes": sizes[:m], "counts": counts, "labels": labels}
 
     # ---- diagnostics
     def get_cells(self):

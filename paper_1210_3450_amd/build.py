@@ -10,7 +10,7 @@ import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
-SOURCES = [os.path.join(PKG, "csrc", f) for f in ("md_api.hip", "md_kernels.hip")]
+SOURCES = [os.path.join(PKG, "csrc", f) for f in ("md_api.hip", "md_kernels.hip", "md_bubbles.hip")]
 HEADERS = [os.path.join(PKG, "csrc", "md_internal.h"), os.path.join(ROOT, "include", "md.h")]
 LIB = os.path.join(PKG, "libmdgpu.so")
 

@@ -62,6 +62,9 @@ struct md_ctx {
     hipGraphExec_t graph_many = nullptr, graph_one = nullptr;
     double force_ms = 0.0, rebuild_ms = 0.0;
     int64_t force_n = 0, rebuild_n = 0;
+    // bubble analysis work buffers (md_bubbles), bw_alloc subcells each
+    BubbleWork bw{};
+    int64_t bw_alloc = 0;
 };
 
 namespace {
@@ -392,6 +395,13 @@ void free_all(md_ctx* c) {
     dfree(c->bk_pos);
     dfree(c->bk_vel);
     dfree(c->dscratch);
+    dfree(c->bw.cnt);
+    dfree(c->bw.par);
+    dfree(c->bw.lab);
+    dfree(c->bw.size);
+    dfree(c->bw.roots);
+    dfree(c->bw.flag);
+    c->bw_alloc = 0;
     if (c->st_h) (void)hipHostFree(c->st_h);
     c->st_h = nullptr;
     for (hipEvent_t e : c->ev_force) (void)hipEventDestroy(e);
@@ -1014,6 +1024,80 @@ md_status md_set_thermostat(md_ctx* c, const double* T, double tau) {
         st.vscale = 1.0;
     }
     return push_states(c);
+}
+
+md_status md_bubbles(md_ctx* c, int32_t box, double side, double rho_gas, uint8_t* counts, int32_t* labels,
+                     int64_t* roots, int64_t* sizes, int64_t cap, md_bubble_info* info) {
+    md_status s;
+    if ((s = check_ctx(c)) != MD_OK) return s;
+    if (!info) return fail(c, MD_EINVAL, "info must not be NULL");
+    if (box < 0 || box >= c->nbox) return fail(c, MD_EINVAL, "box %d out of range [0, %d)", box, c->nbox);
+    if (!finite_pos(side)) return fail(c, MD_EINVAL, "side must be finite and > 0");
+    if (!(rho_gas >= 0.0) || !std::isfinite(rho_gas)) return fail(c, MD_EINVAL, "rho_gas must be finite and >= 0");
+    if (cap < 0 || (cap > 0 && (!roots || !sizes))) return fail(c, MD_EINVAL, "roots and sizes need cap entries");
+    if (!c->have_state) return fail(c, MD_ESTATE, "no state: call md_set_state first");
+    SubGrid sg{};
+    const double* L = c->boxes[box].box;
+    for (int a = 0; a < 3; ++a) {
+        const double n = std::floor(L[a] / side);
+        if (n < 1.0 || n > 1024.0)
+            return fail(c, MD_EINVAL, "floor(L / side) = %.0f on axis %d: need 1..1024 subcells", n, a);
+        sg.L[a] = L[a];
+        sg.n[a] = (int32_t)n;
+        sg.inv[a] = (double)sg.n[a] / L[a];
+    }
+    const double vol = (L[0] / sg.n[0]) * (L[1] / sg.n[1]) * (L[2] / sg.n[2]);
+    sg.thr = rho_gas * vol;
+    const int64_t nsub = (int64_t)sg.n[0] * sg.n[1] * sg.n[2];
+    sg.nsub = (int32_t)nsub;
+    if (nsub > c->bw_alloc) {
+        dfree(c->bw.cnt);
+        dfree(c->bw.par);
+        dfree(c->bw.lab);
+        dfree(c->bw.size);
+        dfree(c->bw.roots);
+        dfree(c->bw.flag);
+        c->bw_alloc = 0;
+        if ((s = dalloc(c, &c->bw.cnt, nsub)) != MD_OK || (s = dalloc(c, &c->bw.par, nsub)) != MD_OK ||
+            (s = dalloc(c, &c->bw.lab, nsub)) != MD_OK || (s = dalloc(c, &c->bw.size, nsub)) != MD_OK ||
+            (s = dalloc(c, &c->bw.roots, nsub)) != MD_OK || (s = dalloc(c, &c->bw.flag, 2)) != MD_OK)
+            return s;
+        c->bw_alloc = nsub;
+    }
+    HIPCHK(c, hipMemsetAsync(c->bw.cnt, 0, sizeof(uint32_t) * nsub, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->bw.flag, 0, sizeof(int32_t) * 2, c->stream));
+    launch_bubbles(c->D, box, c->geom[box].npart, sg, c->bw, counts, c->stream);
+    LAUNCHCHK(c);
+    if (labels)
+        HIPCHK(c, hipMemcpyAsync(labels, c->bw.lab, sizeof(int32_t) * nsub, hipMemcpyDeviceToDevice, c->stream));
+    int32_t flag[2] = {0, 0};
+    HIPCHK(c, hipMemcpyAsync(flag, c->bw.flag, sizeof flag, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (flag[0]) return fail(c, MD_ENUMERIC, "box %d: a position is not finite or lies outside [-L, 2L)", box);
+    std::vector<int2> rs((size_t)flag[1]);
+    if (flag[1] > 0) {
+        HIPCHK(c, hipMemcpy(rs.data(), c->bw.roots, sizeof(int2) * rs.size(), hipMemcpyDeviceToHost));
+        std::sort(rs.begin(), rs.end(), [](const int2& a, const int2& b) { return a.x < b.x; });
+    }
+    int64_t ngas = 0, largest = 0;
+    for (const int2& r : rs) {
+        ngas += r.y;
+        largest = std::max<int64_t>(largest, r.y);
+    }
+    for (int64_t k = 0; k < cap && k < (int64_t)rs.size(); ++k) {
+        roots[k] = rs[k].x;
+        sizes[k] = rs[k].y;
+    }
+    *info = md_bubble_info{};
+    for (int a = 0; a < 3; ++a) {
+        info->nsub[a] = sg.n[a];
+        info->side[a] = L[a] / sg.n[a];
+    }
+    info->threshold = sg.thr;
+    info->ngas = ngas;
+    info->nbubbles = (int64_t)rs.size();
+    info->largest = largest;
+    return MD_OK;
 }
 
 md_status md_get_thermostat(md_ctx* c, double* xi, double* eta) {

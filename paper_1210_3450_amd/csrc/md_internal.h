@@ -152,12 +152,52 @@ struct Dev {
     double* series_th;   // thermostat share Q xi^2 / 2 + g T eta at each sample
 };
 
+// Wrap one coordinate into [0, L) and return its cell index, exactly as the
+// plain definition: "if (x < 0) x += L; if (x >= L) x -= L;" then
+// min((int)(x * n/L), n - 1).  One IEEE operation per line, no contraction.
+__device__ __forceinline__ int bin_axis(double& x, double L, double inv, int n, bool& bad) {
+#pragma clang fp contract(off)
+    if (!(x >= -L && x < 2.0 * L)) {  // also catches NaN
+        bad = true;
+        return 0;
+    }
+    if (x < 0.0) x += L;
+    if (x >= L) x -= L;
+    const double t = x * inv;
+    const int k = (int)t;
+    return k > n - 1 ? n - 1 : k;
+}
+
 // Kernel modes of the force pass.
 enum ForceMode : int {
     kForceOnly = 0,  // F -> fx/fy/fz
     kForceEnd = 1,   // v += h F (closing half kick), F stored
     kForceMid = 2    // v += h F twice (close step n, open step n+1), drift q, DUTC max
 };
+
+// Subcell grid of the bubble analysis (md_bubbles.hip): n = floor(L / side)
+// per axis, inv = n / L rounded once on the host, thr = rho_gas * subcell volume.
+struct SubGrid {
+    double L[3];
+    double inv[3];
+    double thr;
+    int32_t n[3];
+    int32_t nsub;
+};
+
+// Device work buffers of the bubble analysis, nsub entries each (flag: 2 ints,
+// [0] bad position, [1] root count; cleared by the caller).
+struct BubbleWork {
+    uint32_t* cnt;   // particles per subcell (cleared by the caller)
+    int32_t* par;    // union-find parent, -1 for liquid
+    int32_t* lab;    // bubble label (smallest subcell index), -1 for liquid
+    int32_t* size;   // subcells per bubble, at its root
+    int2* roots;     // (root, size) of each bubble, unordered
+    int32_t* flag;
+};
+
+void launch_bubbles(const Dev& d, int32_t b, int32_t npart, const SubGrid& sg, const BubbleWork& w, uint8_t* bytes,
+                    hipStream_t s);
 
 // Host-side launchers (md_kernels.hip).  All take the stream to launch on.
 void launch_set_state(const Dev& d, const Params& p, const double* pos, const double* vel,

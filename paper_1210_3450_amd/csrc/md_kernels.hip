@@ -99,22 +99,6 @@ __device__ __forceinline__ int4 units3(const Pos& x, uint32_t cc, const BoxGeom&
 
 }
 
-// Wrap one coordinate into [0, L) and return its cell index, exactly as the
-// plain definition: "if (x < 0) x += L; if (x >= L) x -= L;" then
-// min((int)(x * n/L), n - 1).  One IEEE operation per line, no contraction.
-__device__ __forceinline__ int bin_axis(double& x, double L, double inv, int n, bool& bad) {
-#pragma clang fp contract(off)
-    if (!(x >= -L && x < 2.0 * L)) {  // also catches NaN
-        bad = true;
-        return 0;
-    }
-    if (x < 0.0) x += L;
-    if (x >= L) x -= L;
-    const double t = x * inv;
-    const int k = (int)t;
-    return k > n - 1 ? n - 1 : k;
-}
-
 // ---------------------------------------------------------------- state I/O
 
 __global__ __launch_bounds__(kBlock) void k_set_state(Dev d, Params p, const double* __restrict__ pos,

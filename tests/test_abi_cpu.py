@@ -30,6 +30,8 @@ def test_struct_sizes_match_header_layout():
     # md_params: int64 + 3 doubles + 4 doubles + 6 int32 + 6 uint64
     assert C.sizeof(B.md_params) == 8 + 24 + 32 + 24 + 48
     assert C.sizeof(B.md_stats) == 5 * 8 + 4 * 4 + 8 + 8 + 8 + 8 + 8
+    # md_bubble_info: 4 int32 + 3 doubles + 1 double + 3 int64
+    assert C.sizeof(B.md_bubble_info) == 16 + 24 + 8 + 24
 
 
 def test_status_strings():
@@ -44,6 +46,8 @@ def test_null_safety():
     assert B.md_step(None, 1, 0) == B.MD_EINVAL
     assert B.md_set_state(None, None, None) == B.MD_EINVAL
     assert B.md_energy(None, None, None) == B.MD_EINVAL
+    info = B.md_bubble_info()
+    assert B.md_bubbles(None, 0, 3.0, 0.2, None, None, None, None, 0, C.byref(info)) == B.MD_EINVAL
     assert B.md_last_error(None) is not None
 
 

@@ -2,7 +2,6 @@
 NVE run, the cavitation protocol (uneven lists after expansion) at reduced size,
 and the 1M-particle force error at checkpoints of each path's own trajectory.
 Measured figures are printed (pytest -s) for the design notes."""
-import math
 
 import numpy as np
 import pytest
@@ -74,23 +73,29 @@ def test_small_nve_drift_fast_reciprocal():
 
 
 def test_cavitation_protocol_reduced_size():
-    """24^3 simple-cubic sites at density 0.7 (13,824 particles, rc = 3.0):
-    equilibrate at T = 0.9 by rescaling, expand every length by 1.1, run NVE.
-    Neighbour sets stay bit-exact and FP32-mixed forces within 1e-5 on the
-    expanded, uneven state; energy stays bounded."""
+    """24^3 simple-cubic sites at density 0.7 (13,824 particles, rc = 3.0): hold
+    at T = 0.9 with the Nose-Hoover thermostat, expand every length by 1.1
+    (thermostat off), run NVE.  The liquid's virial pressure is positive and
+    turns negative on expansion (Sec. IV.C); neighbour sets stay bit-exact and
+    FP32-mixed forces within 1e-5 on the expanded, uneven state; energy stays
+    bounded."""
     b = B()
     w = inputs.cavitation_liquid(n_side=24)
     p = b.make_params(w.n, w.box, rc=3.0, precision=b.MD_PREC_FP32_MIXED, flags=b.MD_F_GRAPH)
     with b.Context(p) as c:
         c.set_state(w.pos, w.vel)
-        for _ in range(30):
-            c.step(10)
-            ke, _ = c.energy()
-            c.scale_velocities(math.sqrt(0.9 / (2.0 * ke / (3 * w.n - 3))))
+        c.set_thermostat(0.9, 0.5)
+        c.step(300)
+        P_liq = c.pressure()[0]
         ke0, _ = c.energy()
+        c.set_thermostat(None, 0.0)
         c.rescale_box(1.1)
         ke1, _ = c.energy()
+        P_exp = c.pressure()[0]
         assert ke1 == pytest.approx(ke0, rel=1e-12)  # expansion keeps the momenta
+        print("virial pressure: liquid %.4f, after expansion %.4f, T %.4f" % (P_liq, P_exp,
+                                                                              2 * ke0 / (3 * w.n - 3)))
+        assert P_liq > 0.0 > P_exp
         c.step(400, 10)
         kes, pes = c.energy_series()
         q, _ = c.get_state()
