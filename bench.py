@@ -371,6 +371,10 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-fast-rcp", action="store_true",
                     help="skip the FP64 run with the hardware reciprocal and its correction")
+    ap.add_argument("--no-half", action="store_true",
+                    help="skip the half-list (Newton's third law) runs of both precisions")
+    ap.add_argument("--half-steps", type=int, default=100,
+                    help="timed steps of each half-list run (about 48 ms per step at 32M)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--workload", default="fcc32m",
@@ -429,6 +433,15 @@ def main():
         print("bench: FP64 with the corrected hardware reciprocal %.3f ms/step" % fp64_fast["ms_per_step"],
               file=sys.stderr, flush=True)
 
+    half = {}
+    if not args.no_half:
+        for name, prec in (("fp32_mixed", B.MD_PREC_FP32_MIXED), ("fp64", B.MD_PREC_FP64)):
+            if prec == B.MD_PREC_FP64 and args.no_fp64:
+                continue
+            half[name] = run_gpu(B, torch, w, prec, args.half_steps, args.warmup, 0, B.MD_F_HALF_LIST)
+            print("bench: half list, %s %.3f ms/step" % (name, half[name]["ms_per_step"]), file=sys.stderr,
+                  flush=True)
+
     rho = 0.5
     rl = w.rc + w.skin
     bpp = algorithmic_bytes_per_particle_step(rho, rl)
@@ -476,6 +489,11 @@ def main():
         out["fp64_fast_rcp"] = dict(fp64_fast, gflops=FLOP_PER_PAIR * pairs / (fp64_fast["ms_per_step"] / 1e3) / 1e9,
                                     note="FP64 with 1/r^2 from the hardware reciprocal and the Sec. III.C "
                                          "correction of r^-8 and r^-14")
+    if half:
+        out["half_list"] = dict(half, note="MD_F_HALF_LIST: each pair once (home cell after the key, 13 forward "
+                                           "stencil cells), reactions added to partners atomically, integration "
+                                           "as a separate pass; force_ms_avg covers clearing F, the force pass "
+                                           "and the integration pass")
     if not args.no_cpu:
         print("bench: CPU oracle sample ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)

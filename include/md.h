@@ -81,6 +81,14 @@ typedef enum {
 #define MD_F_FAST_RCP 16u          /* FP64 path: 1/r^2 from the hardware reciprocal, with the
                                       correction of Sec. III.C applied to r^-6, r^-8, r^-12 and
                                       r^-14 (r^-2n ~ xt^n ((n + 1) - n xt r^2)) instead of a division */
+#define MD_F_HALF_LIST 32u         /* half list with Newton's third law (Sec. II.A, Fig. 1 holds each
+                                      pair once): a key lists its partners in the home cell after
+                                      itself and in the 13 forward stencil cells; the force pass adds
+                                      each pair's reaction to the partner atomically, then a separate
+                                      pass integrates.  One lane per key (threads_per_key 0 or 1); not
+                                      with MD_F_VERIFY_LIST or MD_F_TILE_ON.  Forces agree with the
+                                      full list within the precision's tolerance but are not bitwise
+                                      reproducible (the order of the atomic additions varies). */
 
 typedef struct {
     int64_t n;            /* particles in the box, >= 2 */
@@ -270,6 +278,8 @@ md_status md_get_cells(md_ctx *ctx, int32_t *cell_of_particle, int32_t *ncell);
 /* The current pair list as the full sorted list of Fig. 1 in caller ids:
  * key_ptr device int64 [n + 1], partners device int32 [cap], partners of
  * each key ascending (box-local caller ids for ensembles are global ids).
+ * With MD_F_HALF_LIST each pair appears once, under the key whose forward
+ * stencil (or later rank in the same cell) holds the partner.
  * *total (host) receives the entry count; if it exceeds cap nothing is
  * written to partners and MD_EINVAL is returned.  MD_ESTATE without a list. */
 md_status md_get_neighbors(md_ctx *ctx, int64_t *key_ptr, int32_t *partners, int64_t cap,
@@ -286,7 +296,8 @@ md_status md_set_timing(md_ctx *ctx, int32_t on);
  * each candidate (1, 2, 4, 8) and keeps the fastest; rebuilds the list in the
  * chosen layout.  cache_path (nullable): a text file of
  * "precision density_bucket n_bucket threads_per_key" lines consulted first
- * and appended to.  Synchronizing. */
+ * and appended to.  With MD_F_HALF_LIST there is one layout and nothing is
+ * timed.  Synchronizing. */
 md_status md_autotune(md_ctx *ctx, const char *cache_path);
 
 /* ---- errors ------------------------------------------------------------ */

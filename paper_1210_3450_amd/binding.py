@@ -34,7 +34,7 @@ MD_OK, MD_EINVAL, MD_ENOMEM, MD_EHIP, MD_ENUMERIC, MD_ESTATE, MD_ELIST = 0, -1, 
 MD_PREC_FP64, MD_PREC_FP32_MIXED = 0, 1
 MD_CUT_EQ1, MD_CUT_SHIFT, MD_CUT_RAW = 0, 1, 2
 MD_REBUILD_DUTC, MD_REBUILD_DISPLACEMENT, MD_REBUILD_EVERY_STEP, MD_REBUILD_NEVER = 0, 1, 2, 3
-MD_F_VERIFY_LIST, MD_F_GRAPH, MD_F_TILE_ON, MD_F_TILE_OFF, MD_F_FAST_RCP = 1, 2, 4, 8, 16
+MD_F_VERIFY_LIST, MD_F_GRAPH, MD_F_TILE_ON, MD_F_TILE_OFF, MD_F_FAST_RCP, MD_F_HALF_LIST = 1, 2, 4, 8, 16, 32
 
 
 class md_params(C.Structure):

@@ -144,8 +144,13 @@ md_status validate(const md_params* b, int32_t nbox, std::string& why) {
         if (p.precision != MD_PREC_FP64 && p.precision != MD_PREC_FP32_MIXED) return bad("unknown precision");
         if (p.cutoff < MD_CUT_EQ1 || p.cutoff > MD_CUT_RAW) return bad("unknown cutoff scheme");
         if (p.rebuild < MD_REBUILD_DUTC || p.rebuild > MD_REBUILD_NEVER) return bad("unknown rebuild policy");
-        if (p.flags & ~(uint32_t)(MD_F_VERIFY_LIST | MD_F_GRAPH | MD_F_TILE_ON | MD_F_TILE_OFF | MD_F_FAST_RCP))
+        if (p.flags &
+            ~(uint32_t)(MD_F_VERIFY_LIST | MD_F_GRAPH | MD_F_TILE_ON | MD_F_TILE_OFF | MD_F_FAST_RCP | MD_F_HALF_LIST))
             return bad("unknown flag bits");
+        if ((p.flags & MD_F_HALF_LIST) && (p.flags & (MD_F_VERIFY_LIST | MD_F_TILE_ON)))
+            return bad("MD_F_HALF_LIST does not combine with MD_F_VERIFY_LIST or MD_F_TILE_ON");
+        if ((p.flags & MD_F_HALF_LIST) && p.threads_per_key > 1)
+            return bad("MD_F_HALF_LIST takes one lane per key (threads_per_key 0 or 1)");
         if ((p.flags & MD_F_FAST_RCP) && p.precision != MD_PREC_FP64)
             return bad("MD_F_FAST_RCP applies to the FP64 path only");
         if ((p.flags & MD_F_TILE_ON) && (p.flags & MD_F_TILE_OFF)) return bad("MD_F_TILE_ON with MD_F_TILE_OFF");
@@ -243,6 +248,9 @@ int32_t estimate_cap(const md_ctx* c) {
         const double rho = (double)p.n / (p.box[0] * p.box[1] * p.box[2]);
         mean = std::max(mean, rho * 4.0 / 3.0 * M_PI * rl * rl * rl);
     }
+    // a half list holds half the partners on average, but its lengths spread more
+    // (a cell's first particle lists its whole cell, the last none of it)
+    if (c->prm.flags & MD_F_HALF_LIST) return (int32_t)std::ceil(0.75 * mean) + 24;
     return (int32_t)std::ceil(1.5 * mean) + 16;
 }
 
@@ -348,7 +356,8 @@ void params_refresh(md_ctx* c) {
     }
     if (p.flags & MD_F_TILE_ON) tile = p.precision == MD_PREC_FP32_MIXED;
     if (p.flags & MD_F_TILE_OFF) tile = false;
-    P.tile = tile ? 1 : 0;
+    P.half = (p.flags & MD_F_HALF_LIST) ? 1 : 0;
+    P.tile = tile && !P.half ? 1 : 0;
     P.fastrcp = (p.flags & MD_F_FAST_RCP) ? 1 : 0;
 }
 
@@ -678,6 +687,7 @@ md_status create_impl(const md_params* boxes, int32_t nbox, void* stream, md_ctx
     // per key to fill the chip; large ones are bound by partner gathers, where the
     // FP64 path's 32-byte records gain from two lanes reading adjacent entries
     if (tpk == 0) tpk = c->ntotal < 262144 ? 4 : (c->prm.precision == MD_PREC_FP64 ? 2 : 1);
+    if (c->prm.flags & MD_F_HALF_LIST) tpk = 1;
     c->P.tpk = tpk;
     params_refresh(c);
     if ((s = alloc_all(c)) != MD_OK || (s = upload_geometry(c)) != MD_OK ||
@@ -1199,6 +1209,7 @@ md_status md_autotune(md_ctx* c, const char* cache_path) {
     md_status s;
     if ((s = check_ctx(c)) != MD_OK) return s;
     if ((s = ensure_list_and_forces(c)) != MD_OK) return s;
+    if (c->P.half) return MD_OK;  // a half list has one layout: one lane per key
     // cache key: precision, density (1/20 steps), particles per box (log2), ensemble or not
     double rho = 0.0, nmean = 0.0;
     for (int b = 0; b < c->nbox; ++b) {

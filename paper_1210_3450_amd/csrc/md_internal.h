@@ -111,7 +111,7 @@ struct Params {
     int32_t record;     // energy reduction appends to the series
     int32_t tile;       // FP32-mixed forces from LDS-staged partner tiles (one lane per key)
     int32_t fastrcp;    // FP64 forces from the hardware reciprocal with the correction of r^-8, r^-14
-    int32_t pad2;
+    int32_t half;       // half list (each pair once, forward stencil cells), partner forces by atomics
 };
 
 struct Dev {

@@ -600,7 +600,7 @@ typedef const __attribute__((address_space(4))) double const_double;
 // stored to the list directly.
 constexpr int kStage = 4096;  // LDS list entries per wavefront
 
-template <int TPK, bool WRAP, bool STAGED>
+template <int TPK, bool WRAP, bool STAGED, bool HALF>
 __device__ __forceinline__ void list_pass(const Dev& d, const Params& p, const Pos* __restrict__ q,
                                           const const_double* qc, int cs0, int kb, int mb, int c0, int total,
                                           int start, int pre, double shx, double shy, double shz, int pre13,
@@ -665,8 +665,12 @@ __device__ __forceinline__ void list_pass(const Dev& d, const Params& p, const P
             if (k < nch) {
                 const double r2 = WRAP ? dist2_exact(qi, make_double3(cx[k], cy[k], cz[k]), sx[k], sy[k], sz[k])
                                        : dist2_exact0(qi, make_double3(cx[k], cy[k], cz[k]));
-                // lanes within the list radius, minus the key itself
-                const unsigned long long mask = __builtin_amdgcn_ballot_w64(r2 < rl2) & ~(k == sk ? sb : 0ull);
+                // lanes within the list radius, minus the key itself; the half list
+                // keeps only candidates after the key (the home cell comes first and
+                // the backward stencil cells hold no candidates)
+                const unsigned long long mask =
+                    HALF ? __builtin_amdgcn_ballot_w64(r2 < rl2 && k * kWave + l > self)
+                         : __builtin_amdgcn_ballot_w64(r2 < rl2) & ~(k == sk ? sb : 0ull);
                 const uint32_t pos = __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
                                                                __builtin_amdgcn_mbcnt_lo((unsigned)mask, (unsigned)cnt));
                 unsigned long long sm = mask;
@@ -684,7 +688,7 @@ __device__ __forceinline__ void list_pass(const Dev& d, const Params& p, const P
     }
 }
 
-template <int TPK>
+template <int TPK, bool HALF>
 __global__ __launch_bounds__(kBlock) void k_list(Dev d, Params p) {
     if (!*d.any) return;  // no box rebuilds this step
     __shared__ __align__(16) uint16_t stage_all[kBlock / kWave][kStage];
@@ -722,6 +726,9 @@ __global__ __launch_bounds__(kBlock) void k_list(Dev d, Params p) {
             start = d.cell_start[nc];
             cnt = d.cell_cnt[nc];
             if (cnt > kMaxCellCount) atomicOr(&d.st[b].err, 2);  // ranks would not fit 11 bits
+            // half list: only the home cell (s = 13) and the forward cells s > 13, whose
+            // offsets are lexicographically positive, so each pair of cells meets once
+            if (HALF && l < 13) cnt = 0;
         }
         const bool wrap = __ballot(img) != 0ull;  // uniform: this cell touches the box boundary
         const int incl = wave_incl_scan(cnt);
@@ -737,12 +744,12 @@ __global__ __launch_bounds__(kBlock) void k_list(Dev d, Params p) {
             if (staged) {
                 if (wrap) {
                     for (int c0 = 0; c0 < total; c0 += 3 * kWave)
-                        list_pass<TPK, true, true>(d, p, q, qc, cs0, kb, mb, c0, total, start, pre, shx, shy, shz,
-                                                   pre13, n_own, stage);
+                        list_pass<TPK, true, true, HALF>(d, p, q, qc, cs0, kb, mb, c0, total, start, pre, shx, shy,
+                                                         shz, pre13, n_own, stage);
                 } else {
                     for (int c0 = 0; c0 < total; c0 += 6 * kWave)
-                        list_pass<TPK, false, true>(d, p, q, qc, cs0, kb, mb, c0, total, start, pre, shx, shy, shz,
-                                                    pre13, n_own, stage);
+                        list_pass<TPK, false, true, HALF>(d, p, q, qc, cs0, kb, mb, c0, total, start, pre, shx, shy,
+                                                          shz, pre13, n_own, stage);
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
@@ -767,12 +774,12 @@ __global__ __launch_bounds__(kBlock) void k_list(Dev d, Params p) {
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             } else if (wrap) {
                 for (int c0 = 0; c0 < total; c0 += 3 * kWave)
-                    list_pass<TPK, true, false>(d, p, q, qc, cs0, kb, mb, c0, total, start, pre, shx, shy, shz,
-                                                pre13, n_own, stage);
+                    list_pass<TPK, true, false, HALF>(d, p, q, qc, cs0, kb, mb, c0, total, start, pre, shx, shy, shz,
+                                                      pre13, n_own, stage);
             } else {
                 for (int c0 = 0; c0 < total; c0 += 6 * kWave)
-                    list_pass<TPK, false, false>(d, p, q, qc, cs0, kb, mb, c0, total, start, pre, shx, shy, shz,
-                                                 pre13, n_own, stage);
+                    list_pass<TPK, false, false, HALF>(d, p, q, qc, cs0, kb, mb, c0, total, start, pre, shx, shy,
+                                                       shz, pre13, n_own, stage);
             }
             if (l < mb) {
                 const int nk = n_own < cap ? n_own : cap;
@@ -833,7 +840,7 @@ __device__ __forceinline__ void stripe_put(unsigned long long* base, int b, int 
 // The end of a force pass for one key: reduce the lanes of a key, then store F,
 // or kick (closing half kick; mid-step: closing and opening kicks, drift and the
 // fixed-point re-encoding), DUTC maximum and energy partials per wavefront.
-template <int PREC, int MODE, int TPK, bool ENERGY>
+template <int PREC, int MODE, int TPK, bool ENERGY, bool HALF>
 __device__ __forceinline__ void force_finish(const Dev& d, const Params& p, const BoxGeom& g, int b, int lw, int key,
                                              bool owner, const Pos& qi, uint32_t cc, int sq, int sp, double Fx,
                                              double Fy, double Fz, double pe, double vir) {
@@ -850,12 +857,22 @@ __device__ __forceinline__ void force_finish(const Dev& d, const Params& p, cons
             }
         }
     }
+    if (HALF) {  // each pair once: its energy and virial count twice against the full list's halves
+        pe *= 2.0;
+        vir *= 2.0;
+    }
     double ke = 0.0, w2 = 0.0, m2 = 0.0;
     if (MODE == kForceOnly) {
-        if (owner) {
+        if (owner && HALF) {  // other keys add their reactions to this particle concurrently
+            unsafeAtomicAdd(d.fx + key, Fx);
+            unsafeAtomicAdd(d.fy + key, Fy);
+            unsafeAtomicAdd(d.fz + key, Fz);
+        } else if (owner) {
             d.fx[key] = Fx;
             d.fy[key] = Fy;
             d.fz[key] = Fz;
+        }
+        if (owner) {
             if (ENERGY) ke = 0.5 * p.mass * norm2(d.vx[sp][key], d.vy[sp][key], d.vz[sp][key]);
         }
     } else if (MODE == kForceEnd) {
@@ -945,8 +962,12 @@ __device__ __forceinline__ typename ForceTab<PREC>::Rec force_rec(const Dev& d, 
     }
 }
 
-template <int PREC, int MODE, int TPK, bool ENERGY>
+// HALF (half list, kForceOnly, one lane per key): the reaction -f d of every pair
+// goes to the partner by an atomic add, and the key's own sum is added likewise;
+// F must be zero before the pass.
+template <int PREC, int MODE, int TPK, bool ENERGY, bool HALF = false>
 __global__ __launch_bounds__(kBlock) void k_force(Dev d, Params p) {
+    static_assert(!HALF || (MODE == kForceOnly && TPK == 1), "half lists: forces only, one lane per key");
     constexpr int K = kWave / TPK;
     constexpr int U = 8;  // entries per iteration (one 16-byte chunk)
     constexpr bool MIX = PREC == MD_PREC_FP32_MIXED;
@@ -1069,6 +1090,11 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Params p) {
                     Fx += f * dx;
                     Fy += f * dy;
                     Fz += f * dz;
+                    if (HALF && in) {  // Newton's third law: the reaction on the partner
+                        unsafeAtomicAdd(d.fx + js[k], -(f * dx));
+                        unsafeAtomicAdd(d.fy + js[k], -(f * dy));
+                        unsafeAtomicAdd(d.fz + js[k], -(f * dz));
+                    }
                     if (ENERGY) {
                         pe += in ? 2.0 * (e + p.c2 * r2 + p.c0) : 0.0;
                         vir += in ? f * r2 : 0.0;
@@ -1083,6 +1109,7 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Params p) {
             const int nux = -ui.x, nuy = -ui.y, nuz = -ui.z;
             // lengths stay in fixed-point units: r^2 in units^2, 1/r^2 rescaled once
             const float rc2u = g.rc2u, lam2inv = g.lam2inv, lam2 = g.lam * g.lam, c2x8 = 8.0f * p.c2f;
+            const double lamd = (double)g.lam;
             float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f, pes = 0.f, virs = 0.f;
             auto chunk = [&](int c, auto chk_c, int valid) {
                 constexpr bool CHK = decltype(chk_c)::value;
@@ -1114,9 +1141,15 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Params p) {
                     const float inv = __builtin_amdgcn_rcpf(r2) * lam2inv;  // 1/r^2 in length units
                     const float inv3 = inv * inv * inv;
                     const float f = in ? (inv3 * inv) * (24.0f - 48.0f * inv3) + c2x8 : 0.0f;
-                    bx += f * dx;
-                    by += f * dy;
-                    bz += f * dz;
+                    const float fdx = f * dx, fdy = f * dy, fdz = f * dz;
+                    bx += fdx;
+                    by += fdy;
+                    bz += fdz;
+                    if (HALF && in) {  // Newton's third law: the reaction on the partner, in lengths
+                        unsafeAtomicAdd(d.fx + js[k], -(double)fdx * lamd);
+                        unsafeAtomicAdd(d.fy + js[k], -(double)fdy * lamd);
+                        unsafeAtomicAdd(d.fz + js[k], -(double)fdz * lamd);
+                    }
                     if (ENERGY) {
                         pes += in ? 2.0f * (inv3 * inv3 - inv3 + p.c2f * (r2 * lam2) + p.c0f) : 0.0f;
                         virs += in ? f * r2 : 0.0f;  // units^2: times lam^2 below
@@ -1142,8 +1175,8 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Params p) {
         else
             pair_loop(std::false_type{});
     }
-    force_finish<PREC, MODE, TPK, ENERGY>(d, p, g, b, lw, key, active && sub == 0, qi, cc, sq, sp, Fx, Fy, Fz, pe,
-                                          vir);
+    force_finish<PREC, MODE, TPK, ENERGY, HALF>(d, p, g, b, lw, key, active && sub == 0, qi, cc, sq, sp, Fx, Fy, Fz,
+                                                pe, vir);
 }
 
 // FP32-mixed force pass with LDS-staged partner tiles (one lane per key).  The
@@ -1425,11 +1458,52 @@ __global__ __launch_bounds__(kBlock) void k_force_tile(Dev d, Params p) {
         pe = (double)pes;
         vir = (double)virs * lam * lam;
     }
-    force_finish<MD_PREC_FP32_MIXED, MODE, 1, ENERGY>(d, p, g, b, lw, key, active, qi, cc, sq, sp, Fx, Fy, Fz, pe,
+    force_finish<MD_PREC_FP32_MIXED, MODE, 1, ENERGY, false>(d, p, g, b, lw, key, active, qi, cc, sq, sp, Fx, Fy, Fz, pe,
                                                       vir);
 }
 
+// Half-list steps: F is accumulated by atomics, so the integrator runs as its own
+// pass after the force pass.  k_zero_f clears F before the force pass.
+__global__ __launch_bounds__(kBlock) void k_zero_f(Dev d, Params p) {
+    const int n = p.nwave * kWave;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        d.fx[i] = 0.0;
+        d.fy[i] = 0.0;
+        d.fz[i] = 0.0;
+    }
+}
+
+// Closing half kick from stored forces; ENERGY: per-wave kinetic energy partials
+// of the kicked velocities (one lane per key, so list waves are slot waves).
+template <bool ENERGY>
+__global__ __launch_bounds__(kBlock) void k_kick_close(Dev d, Params p) {
+    const int l = lane_id();
+    for (int w = blockIdx.x * 4 + (threadIdx.x >> 6); w < p.nwave; w += gridDim.x * 4) {
+        const int b = d.wave_box[w];
+        const BoxGeom& g = d.geom[b];
+        const int s = w * kWave + l;
+        const int sp = d.st[b].sp;
+        double ke = 0.0;
+        if (s - g.slot_off < g.npart) {
+            const double vx = kick(d.vx[sp][s], p.h, d.fx[s]);
+            const double vy = kick(d.vy[sp][s], p.h, d.fy[s]);
+            const double vz = kick(d.vz[sp][s], p.h, d.fz[s]);
+            d.vx[sp][s] = vx;
+            d.vy[sp][s] = vy;
+            d.vz[sp][s] = vz;
+            if (ENERGY) ke = 0.5 * p.mass * norm2(vx, vy, vz);
+        }
+        if (ENERGY) {
+            const double ks = wave_sum(ke);
+            if (l == 0) d.ke_part[w] = ks;
+        }
+    }
+}
+
 // First half kick and drift from stored forces (start of a chunk of steps).
+// CLOSE (half-list continuing steps): the closing half kick of the previous step
+// first, with the same forces, as the fused full-list pass does.
+template <bool CLOSE>
 __global__ __launch_bounds__(kBlock) void k_kick_drift(Dev d, Params p) {
     const int l = lane_id();
     for (int w = blockIdx.x * 4 + (threadIdx.x >> 6); w < p.nwave; w += gridDim.x * 4) {
@@ -1440,9 +1514,13 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(Dev d, Params p) {
         double w2 = 0.0, m2 = 0.0;
         if (s - g.slot_off < g.npart) {
             const double vs = d.st[b].vscale;  // thermostat factor; 1 (exact) otherwise
-            const double vx = kick(scale(d.vx[sp][s], vs), p.h, d.fx[s]);
-            const double vy = kick(scale(d.vy[sp][s], vs), p.h, d.fy[s]);
-            const double vz = kick(scale(d.vz[sp][s], vs), p.h, d.fz[s]);
+            const double fx = d.fx[s], fy = d.fy[s], fz = d.fz[s];
+            const double ux = CLOSE ? kick(d.vx[sp][s], p.h, fx) : d.vx[sp][s];
+            const double uy = CLOSE ? kick(d.vy[sp][s], p.h, fy) : d.vy[sp][s];
+            const double uz = CLOSE ? kick(d.vz[sp][s], p.h, fz) : d.vz[sp][s];
+            const double vx = kick(scale(ux, vs), p.h, fx);
+            const double vy = kick(scale(uy, vs), p.h, fy);
+            const double vz = kick(scale(uz, vs), p.h, fz);
             d.vx[sp][s] = vx;
             d.vy[sp][s] = vy;
             d.vz[sp][s] = vz;
@@ -1665,7 +1743,10 @@ void launch_mark_rebuild(const Dev& d, const Params& p, hipStream_t s) {
 
 template <int TPK>
 static void launch_list_t(const Dev& d, const Params& p, hipStream_t s) {
-    k_list<TPK><<<grid_for_waves(p.ntile * kTile, 8192), kBlock, 0, s>>>(d, p);
+    if (TPK == 1 && p.half)
+        k_list<1, true><<<grid_for_waves(p.ntile * kTile, 8192), kBlock, 0, s>>>(d, p);
+    else
+        k_list<TPK, false><<<grid_for_waves(p.ntile * kTile, 8192), kBlock, 0, s>>>(d, p);
 }
 
 void launch_rebuild_chain(const Dev& d, const Params& p, bool with_list, hipStream_t s) {
@@ -1737,7 +1818,33 @@ static void launch_force_p(const Dev& d, const Params& p, int mode, bool energy,
     }
 }
 
+// Half list: clear F, accumulate it with the reactions, then integrate from it.
+template <int PREC>
+static void launch_force_half(const Dev& d, const Params& p, int mode, bool energy, hipStream_t s) {
+    const int nb = (p.nwave + 3) / 4;
+    k_zero_f<<<grid_for_waves(p.nwave), kBlock, 0, s>>>(d, p);
+    if (energy)
+        k_force<PREC, kForceOnly, 1, true, true><<<nb, kBlock, 0, s>>>(d, p);
+    else
+        k_force<PREC, kForceOnly, 1, false, true><<<nb, kBlock, 0, s>>>(d, p);
+    if (mode == kForceEnd) {
+        if (energy)
+            k_kick_close<true><<<nb, kBlock, 0, s>>>(d, p);
+        else
+            k_kick_close<false><<<nb, kBlock, 0, s>>>(d, p);
+    } else if (mode == kForceMid) {
+        k_kick_drift<true><<<nb, kBlock, 0, s>>>(d, p);
+    }
+}
+
 void launch_force(const Dev& d, const Params& p, int mode, bool energy, hipStream_t s) {
+    if (p.half) {
+        if (p.precision == MD_PREC_FP64)
+            launch_force_half<MD_PREC_FP64>(d, p, mode, energy, s);
+        else
+            launch_force_half<MD_PREC_FP32_MIXED>(d, p, mode, energy, s);
+        return;
+    }
     if (p.precision == MD_PREC_FP64)
         launch_force_p<MD_PREC_FP64>(d, p, mode, energy, s);
     else
@@ -1745,7 +1852,7 @@ void launch_force(const Dev& d, const Params& p, int mode, bool energy, hipStrea
 }
 
 void launch_kick_drift(const Dev& d, const Params& p, hipStream_t s) {
-    k_kick_drift<<<(p.nwave + 3) / 4, kBlock, 0, s>>>(d, p);
+    k_kick_drift<false><<<(p.nwave + 3) / 4, kBlock, 0, s>>>(d, p);
 }
 void launch_dutc(const Dev& d, const Params& p, hipStream_t s) {
     k_dutc<<<p.nbox < 1024 ? p.nbox : 1024, kBlock, 0, s>>>(d, p);

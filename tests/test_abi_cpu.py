@@ -66,6 +66,10 @@ BAD = [
     dict(flags=1 << 7),
     dict(flags=4 | 8),                    # tile on and off together
     dict(flags=16, precision=1),          # fast reciprocal on the mixed path
+    dict(flags=32 | 1),                   # half list with the verifier
+    dict(flags=32 | 4, precision=1),      # half list with staged tiles
+    dict(flags=32, threads_per_key=2),    # half list takes one lane per key
+    dict(flags=1 << 6),
     dict(threads_per_key=3),
     dict(list_cap=-1),
     dict(box=(3000.0, 20.0, 20.0)),       # > 1023 cells on one axis
