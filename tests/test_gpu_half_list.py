@@ -172,3 +172,44 @@ def test_half_list_full_size_1m_forces():
             _, pe = c.energy()
         assert norm_err(F, Fr, A) <= tol
         assert pe == pytest.approx(per, rel=1e-11 if precision == 0 else 1e-6)
+
+
+@pytest.mark.parametrize("policy", [1, 2])
+def test_half_list_other_rebuild_policies_match_oracle(policy):
+    """Displacement and every-step rebuilds with the half list (the integration
+    pass carries the displacement maximum)."""
+    w = inputs.small_nve()
+    r = oracle.run(w.pos, w.vel, w.box, 60, rebuild=policy)
+    with half_ctx(w.pos, w.vel, w.box[0], rebuild=policy) as c:
+        c.step(60)
+        pos, _ = c.get_state()
+        st = c.stats()
+    assert np.abs(_wrapdiff(pos.cpu().numpy(), r.q, w.box)).max() < 1e-9
+    assert st["rebuilds"] == r.rebuilds
+
+
+def test_half_list_overflow_regrows_at_build_and_during_steps():
+    q, v, L = case("clustered")
+    with half_ctx(q, v, L, list_cap=8) as c:
+        c.build_neighbors()
+        kp, pl = c.get_neighbors()
+        assert c.stats()["list_regrows"] >= 1
+    i, j = pairs_of(kp.cpu().numpy(), pl.cpu().numpy())
+    n = q.shape[0]
+    kpr, plr = oracle.neighbors(q, L, 2.8, half=True)
+    ir, jr = pairs_of(kpr, plr)
+    np.testing.assert_array_equal(np.sort(np.minimum(i, j).astype(np.int64) * n + np.maximum(i, j)),
+                                  np.sort(ir.astype(np.int64) * n + jr))
+    # a lattice heated to T = 3: the longest half list grows past the capacity of the first build
+    rng = np.random.Generator(np.random.PCG64(11))
+    q0, v0 = inputs.fcc_positions(5, 2.0), inputs.maxwell_boltzmann(500, 3.0, 1.0, rng)
+    with half_ctx(q0, v0, 10.0) as c:
+        c.build_neighbors()
+        cap0 = (c.stats()["max_list_len"] + 7) // 8 * 8
+    r = oracle.run(q0, v0, 10.0, 120)
+    with half_ctx(q0, v0, 10.0, list_cap=cap0) as c:
+        c.step(120)
+        pos, _ = c.get_state()
+        st = c.stats()
+    assert st["list_regrows"] >= 1
+    assert np.abs(_wrapdiff(pos.cpu().numpy(), r.q, 10.0)).max() < 1e-9
