@@ -433,7 +433,7 @@ md_status alloc_all(md_ctx* c) {
     A(D.wave_box, c->nwave);
     for (int k = 0; k < 2; ++k) {
         A(D.q[k], ns);
-        if (c->prm.precision == MD_PREC_FP32_MIXED) A(D.u[k], ns);
+        if (c->prm.precision == MD_PREC_FP32_MIXED) A(D.u[k], 3 * ns);
         A(D.vx[k], ns);
         A(D.vy[k], ns);
         A(D.vz[k], ns);

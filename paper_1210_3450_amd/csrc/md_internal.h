@@ -8,7 +8,8 @@
 //   q[2]      Pos records (x, y, z in FP64, the packed cell coordinates of the last
 //             build, the list length), 32 bytes, ping-pong: the force kernel gathers
 //             partners from q[sq] and writes drifted positions to q[1-sq].
-//   u[2]      int4 cell-relative positions in fixed point (FP32-mixed path),
+//   u[2]      cell-relative positions in fixed point, 3 int32 per slot (12 bytes,
+//             no padding, so a partner gather touches fewer cache lines; FP32-mixed path),
 //             ping-pong with q: u = rint((x - (c + 1/2) cs) * ucs) per axis,
 //             c = the particle's cell at the last build, ucs a power of two
 //             (units per length, the same on every axis).  A pair's separation
@@ -121,7 +122,7 @@ struct Dev {
     int32_t* wave_box;   // box of each 64-slot wavefront
     int32_t* tile_box;   // box of each cell tile
     Pos* q[2];
-    int4* u[2];
+    int32_t* u[2];       // fixed-point positions, 3 ints per slot (U3 records)
     double* vx[2];
     double* vy[2];
     double* vz[2];

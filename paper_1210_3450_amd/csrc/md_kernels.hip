@@ -99,6 +99,18 @@ __device__ __forceinline__ int4 units3(const Pos& x, uint32_t cc, const BoxGeom&
 
 }
 
+
+// Fixed-point position record of the FP32-mixed path: 12 bytes, 4-byte aligned,
+// so records pack densely and a gather of one record is one dwordx3 load.
+struct __attribute__((packed, aligned(4))) U3 {
+    int x, y, z;
+};
+__device__ __forceinline__ void put_u(int32_t* u, int s, int4 v) { *reinterpret_cast<U3*>(u + 3 * s) = U3{v.x, v.y, v.z}; }
+__device__ __forceinline__ int4 get_u(const int32_t* u, int s) {
+    const U3 t = *reinterpret_cast<const U3*>(u + 3 * s);
+    return make_int4(t.x, t.y, t.z, 0);
+}
+
 // ---------------------------------------------------------------- state I/O
 
 __global__ __launch_bounds__(kBlock) void k_set_state(Dev d, Params p, const double* __restrict__ pos,
@@ -523,7 +535,7 @@ __global__ __launch_bounds__(kBlock) void k_permute(Dev d, Params p) {
         x.cc = cc;
         x.cnt = 0;
         d.q[nq][s] = x;
-        if (p.precision == MD_PREC_FP32_MIXED) d.u[nq][s] = units3(x, cc, g);
+        if (p.precision == MD_PREC_FP32_MIXED) put_u(d.u[nq], s, units3(x, cc, g));
         if (d.qb) d.qb[s] = make_double4(x.x, x.y, x.z, 0.0);
     }
 }
@@ -903,7 +915,7 @@ __device__ __forceinline__ void force_finish(const Dev& d, const Params& p, cons
             const Pos xn = make_pos(drift(qi.x, p.dt, vx), drift(qi.y, p.dt, vy), drift(qi.z, p.dt, vz), qi.cc,
                                     qi.cnt);
             d.q[sq ^ 1][key] = xn;
-            if (PREC == MD_PREC_FP32_MIXED) d.u[sq ^ 1][key] = units3(xn, cc, g);
+            if (PREC == MD_PREC_FP32_MIXED) put_u(d.u[sq ^ 1], key, units3(xn, cc, g));
             w2 = norm2(vx, vy, vz);
             if (d.qb) {
                 const double4 xb = d.qb[key];
@@ -1108,7 +1120,7 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Params p) {
             for (int c = 0; c < nfull; ++c) chunk(c, std::false_type{}, U);
             if (ntail) chunk(nfull, std::true_type{}, ntail);
         } else {
-            const int4* __restrict__ u = d.u[sq];
+            const int32_t* __restrict__ u = d.u[sq];
             const int4 ui = units3(qi, cc, g);  // own coordinate from the record: no extra load
             const int nux = -ui.x, nuy = -ui.y, nuz = -ui.z;
             // lengths stay in fixed-point units: r^2 in units^2, 1/r^2 rescaled once
@@ -1128,7 +1140,10 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Params p) {
                 int4 uj[U];
 #pragma unroll
                 for (int k = 0; k < U; ++k)  // 32-bit byte offsets: slots < 2^27
-                    uj[k] = *reinterpret_cast<const int4*>(reinterpret_cast<const char*>(u) + (js[k] << 4));
+                {  // 32-bit byte offsets from a uniform base: slots < 2^27, 12 bytes each
+                    const U3 t = *reinterpret_cast<const U3*>(reinterpret_cast<const char*>(u) + js[k] * 12u);
+                    uj[k] = make_int4(t.x, t.y, t.z, 0);
+                }
                 if (!CHK && (c + 1 < nfull || ntail)) raw_next = l4[(size_t)(c + 1) * kWave];
                 // the stencil offsets are read again below rather than held across the gathers
                 __builtin_amdgcn_sched_barrier(0);
@@ -1319,7 +1334,7 @@ __global__ __launch_bounds__(kBlock) void k_force_tile(Dev d, Params p) {
     if (tiled) {
         // ---- copy the pieces: chunk c (64 records of one piece) goes to wavefront c % 4
         const int NC = blk[1];
-        const int4* __restrict__ u = d.u[sq];
+        const int32_t* __restrict__ u = d.u[sq];
         const uint32_t uox = (uint32_t)g.uoff[0];
         for (int c0 = wib; c0 < NC; c0 += 4 * 8) {
             int4 v[8];
@@ -1332,7 +1347,8 @@ __global__ __launch_bounds__(kBlock) void k_force_tile(Dev d, Params p) {
                     const int pc = ch_part[c], i = ch_off[c] + l;
                     pcs[k] = pc;
                     if (i < pt_len[pc]) {
-                        v[k] = u[pt_s0[pc] + i];
+                        v[k] = get_u(u, pt_s0[pc] + i);
+                        v[k].w = (int)(d.q[sq][pt_s0[pc] + i].cc & 1023u);  // its cell's x index
                         li[k] = pt_base[pc] + i;
                     }
                 }
@@ -1387,7 +1403,7 @@ __global__ __launch_bounds__(kBlock) void k_force_tile(Dev d, Params p) {
             // this key in the frame of the staged partners
             const int hr = (int)((cc >> 20) * ny + ((cc >> 10) & 1023)) == rowf ? 0 : 1;
             const uint32_t kx = (uint32_t)ui.x + (uint32_t)(ui.w - (hr == 0 ? xa0 : 0)) * (uint32_t)g.uoff[0];
-            const int4* __restrict__ u = d.u[sq];
+            const int32_t* __restrict__ u = d.u[sq];
             auto chunk = [&](int c, auto chk_c, int valid) {
                 constexpr bool CHK = decltype(chk_c)::value;
                 const uint4 raw = raw_next;
@@ -1417,7 +1433,7 @@ __global__ __launch_bounds__(kBlock) void k_force_tile(Dev d, Params p) {
                     }
                     int4 uj[U];
 #pragma unroll
-                    for (int k = 0; k < U; ++k) uj[k] = u[js[k]];
+                    for (int k = 0; k < U; ++k) uj[k] = get_u(u, js[k]);
                     if (!CHK && (c + 1 < nfull || ntail)) raw_next = l4[(size_t)(c + 1) * kWave];
 #pragma unroll
                     for (int k = 0; k < U; ++k) {
@@ -1531,7 +1547,7 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(Dev d, Params p) {
             const Pos x = d.q[sq][s];
             const Pos xn = make_pos(drift(x.x, p.dt, vx), drift(x.y, p.dt, vy), drift(x.z, p.dt, vz), x.cc, x.cnt);
             d.q[sq ^ 1][s] = xn;
-            if (p.precision == MD_PREC_FP32_MIXED) d.u[sq ^ 1][s] = units3(xn, x.cc, g);
+            if (p.precision == MD_PREC_FP32_MIXED) put_u(d.u[sq ^ 1], s, units3(xn, x.cc, g));
             w2 = norm2(vx, vy, vz);
             if (d.qb) {
                 const double4 xb = d.qb[s];
