@@ -357,6 +357,9 @@ void params_refresh(md_ctx* c) {
     if (p.flags & MD_F_TILE_ON) tile = p.precision == MD_PREC_FP32_MIXED;
     if (p.flags & MD_F_TILE_OFF) tile = false;
     P.half = (p.flags & MD_F_HALF_LIST) ? 1 : 0;
+    P.maxslot = 0;
+    for (const BoxGeom& g : c->geom) P.maxslot = std::max(P.maxslot, g.nslot);
+    P.redcap = (P.maxslot / kWave * 8 + kRedSeg - 1) / kRedSeg;
     P.tile = tile && !P.half ? 1 : 0;
     P.fastrcp = (p.flags & MD_F_FAST_RCP) ? 1 : 0;
 }
@@ -396,6 +399,7 @@ void free_all(md_ctx* c) {
     dfree(D.ke_part);
     dfree(D.pe_part);
     dfree(D.vir_part);
+    dfree(D.red);
     dfree(D.dshift);
     dfree(D.series_ke);
     dfree(D.series_pe);
@@ -452,6 +456,7 @@ md_status alloc_all(md_ctx* c) {
     A(D.ke_part, (size_t)c->nwave * 8);
     A(D.pe_part, (size_t)c->nwave * 8);
     A(D.vir_part, (size_t)c->nwave * 8);
+    A(D.red, (size_t)c->nbox * c->P.redcap * 3);
     A(D.dshift, (size_t)27 * c->nbox);
     A(D.series_ke, (size_t)kMaxSeries * c->nbox);
     A(D.series_pe, (size_t)kMaxSeries * c->nbox);

@@ -47,6 +47,7 @@ constexpr int kMaxCellCount = 1 << kOffBits;
 constexpr int kStripes = 1024;           // slots per box for per-step maxima
 constexpr int kStripeStride = 16;        // 128 bytes between slots
 constexpr bool kTileByDefault = false;   // staged-tile force pass chosen from the geometry
+constexpr int kRedSeg = 2048;            // energy partials per first-level segment
 
 // Position record of one slot.  cc and cnt ride in the 8 bytes a double4
 // would leave unused, so streaming a key's position also brings its cell and
@@ -113,6 +114,8 @@ struct Params {
     int32_t tile;       // FP32-mixed forces from LDS-staged partner tiles (one lane per key)
     int32_t fastrcp;    // FP64 forces from the hardware reciprocal with the correction of r^-8, r^-14
     int32_t half;       // half list (each pair once, forward stencil cells), partner forces by atomics
+    int32_t maxslot;    // slots of the largest box
+    int32_t redcap;     // first-level energy sums per box (enough for 8 lanes per key)
 };
 
 struct Dev {
@@ -146,6 +149,7 @@ struct Dev {
     double* ke_part;     // per list wave
     double* pe_part;
     double* vir_part;
+    double* red;         // [nbox][redcap][3] first-level sums of the ke, pe, vir partials
     double4* dshift;     // [nbox][27] FP64 image shift s * L
     double* series_ke;   // [kMaxSeries][nbox]
     double* series_pe;

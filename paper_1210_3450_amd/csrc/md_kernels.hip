@@ -1569,33 +1569,66 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(Dev d, Params p) {
 // box, the velocity factor left in BoxState::vscale) and a sample of the series.
 // Thermostat half step of length h: xi += (h/2) G; factor exp(-xi h) (KE scales by
 // its square); eta += xi h; xi += (h/2) G, with G = (2 KE - g T) / Q, g = 3N - 3.
-__global__ __launch_bounds__(kBlock) void k_energy_reduce(Dev d, Params p, int record, int thermo) {
+// First level: block (j, b) sums segment j (kRedSeg partials) of box b in a fixed
+// order, so the two-level total is the same on every run.
+__device__ __forceinline__ void block_sum3(double& k, double& e, double& v) {
     __shared__ double ks[kBlock], ps[kBlock], vs[kBlock];
+    ks[threadIdx.x] = k;
+    ps[threadIdx.x] = e;
+    vs[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = kBlock / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            ks[threadIdx.x] += ks[threadIdx.x + o];
+            ps[threadIdx.x] += ps[threadIdx.x + o];
+            vs[threadIdx.x] += vs[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    k = ks[0];
+    e = ps[0];
+    v = vs[0];
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(kBlock) void k_energy_segments(Dev d, Params p) {
+    const int b = blockIdx.y, j = blockIdx.x;
+    const BoxGeom& g = d.geom[b];
+    const int K = kWave / p.tpk;
+    const int w0 = g.slot_off / K, w1 = (g.slot_off + g.nslot) / K;
+    const int a0 = w0 + j * kRedSeg, a1 = min(a0 + kRedSeg, w1);
+    if (a0 >= w1) return;  // uniform over the block
+    double k = 0.0, e = 0.0, v = 0.0;
+    for (int w = a0 + threadIdx.x; w < a1; w += kBlock) {
+        k += d.ke_part[w];
+        e += d.pe_part[w];
+        v += d.vir_part[w];
+    }
+    block_sum3(k, e, v);
+    if (threadIdx.x == 0) {
+        double* r = d.red + ((size_t)b * p.redcap + j) * 3;
+        r[0] = k;
+        r[1] = e;
+        r[2] = v;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_energy_reduce(Dev d, Params p, int record, int thermo) {
     for (int b = blockIdx.x; b < p.nbox; b += gridDim.x) {
         const BoxGeom& g = d.geom[b];
         const int K = kWave / p.tpk;
-        const int w0 = g.slot_off / K, w1 = (g.slot_off + g.nslot) / K;
+        const int nseg = (g.nslot / K + kRedSeg - 1) / kRedSeg;
         double k = 0.0, e = 0.0, v = 0.0;
-        for (int w = w0 + threadIdx.x; w < w1; w += kBlock) {
-            k += d.ke_part[w];
-            e += d.pe_part[w];
-            v += d.vir_part[w];
+        for (int j = threadIdx.x; j < nseg; j += kBlock) {
+            const double* r = d.red + ((size_t)b * p.redcap + j) * 3;
+            k += r[0];
+            e += r[1];
+            v += r[2];
         }
-        ks[threadIdx.x] = k;
-        ps[threadIdx.x] = e;
-        vs[threadIdx.x] = v;
-        __syncthreads();
-        for (int o = kBlock / 2; o > 0; o >>= 1) {
-            if (threadIdx.x < o) {
-                ks[threadIdx.x] += ks[threadIdx.x + o];
-                ps[threadIdx.x] += ps[threadIdx.x + o];
-                vs[threadIdx.x] += vs[threadIdx.x + o];
-            }
-            __syncthreads();
-        }
+        block_sum3(k, e, v);
         if (threadIdx.x == 0) {
             BoxState& st = d.st[b];
-            double ke = ks[0], ke_s = ks[0], th = 0.0;  // ke_s, th: values at the sample time
+            double ke = k, ke_s = k, th = 0.0;  // ke_s, th: values at the sample time
             if (thermo && st.thQ > 0.0) {
                 const double gT = (3.0 * g.npart - 3.0) * st.thT, Q = st.thQ, h = 0.5 * p.dt;
                 double xi = st.xi, eta = st.eta, f = 1.0;
@@ -1617,13 +1650,13 @@ __global__ __launch_bounds__(kBlock) void k_energy_reduce(Dev d, Params p, int r
                 st.vscale = f;
             }
             st.ke = ke_s;
-            st.pe = ps[0];
-            st.vir = 0.5 * vs[0];  // every pair appears in both keys' lists
+            st.pe = e;
+            st.vir = 0.5 * v;  // every pair appears in both keys' lists
             if (record && st.nseries < kMaxSeries) {
                 const size_t at = (size_t)st.nseries * p.nbox + b;
                 d.series_ke[at] = ke_s;
-                d.series_pe[at] = ps[0];
-                d.series_vir[at] = 0.5 * vs[0];
+                d.series_pe[at] = e;
+                d.series_vir[at] = 0.5 * v;
                 d.series_th[at] = th;
                 st.nseries += 1;
             }
@@ -1878,6 +1911,8 @@ void launch_dutc(const Dev& d, const Params& p, hipStream_t s) {
     k_dutc<<<p.nbox < 1024 ? p.nbox : 1024, kBlock, 0, s>>>(d, p);
 }
 void launch_energy_reduce(const Dev& d, const Params& p, bool record, int thermo, hipStream_t s) {
+    const int nseg = (p.maxslot / kWave * p.tpk + kRedSeg - 1) / kRedSeg;
+    k_energy_segments<<<dim3(nseg, p.nbox), kBlock, 0, s>>>(d, p);
     k_energy_reduce<<<p.nbox < 1024 ? p.nbox : 1024, kBlock, 0, s>>>(d, p, record ? 1 : 0, thermo);
 }
 void launch_ke_partial(const Dev& d, const Params& p, hipStream_t s) {
