@@ -137,7 +137,7 @@ struct Dev {
     int32_t* cnt;        // list length per slot
     uint16_t* list;
     int32_t* cell_tmp;   // cell of each (old) slot at binning
-    int32_t* ticket;     // arrival rank within the cell at binning; then the ordered source slots
+    int32_t* ticket;     // arrival rank within the cell at binning
     int32_t* perm;       // new slot -> old slot
     int32_t* cell_cnt;
     int32_t* cell_start;

@@ -484,11 +484,12 @@ __global__ __launch_bounds__(kBlock) void k_scatter(Dev d, Params p) {
     }
 }
 
-// Arrival order within a cell depends on atomics; order each cell's members by
-// caller id so the sorted layout is a function of the positions alone.  One lane
-// per new slot: its rank among the cell's members by caller id is its place.
-// The ordered source slots go to d.ticket (free once k_scatter has run).
-__global__ __launch_bounds__(kBlock) void k_cell_rank(Dev d, Params p) {
+// Arrival order within a cell depends on atomics; each cell's members are placed
+// by caller id so the sorted layout is a function of the positions alone.  One
+// lane per particle, taken in arrival order: its rank among the cell's members by
+// caller id is its new slot, and its state is copied there (position record with
+// the new cell, fixed-point record, velocities, caller id).
+__global__ __launch_bounds__(kBlock) void k_rank_permute(Dev d, Params p) {
     if (!*d.any) return;  // no box rebuilds this step
     const int l = lane_id();
     for (int w = xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6); w < p.nwave; w += gridDim.x * 4) {
@@ -498,45 +499,29 @@ __global__ __launch_bounds__(kBlock) void k_cell_rank(Dev d, Params p) {
         const BoxGeom& g = d.geom[b];
         const int s = w * kWave + l;
         if (s - g.slot_off >= g.npart) continue;
-        const int32_t* __restrict__ id = d.id[st.sp];
-        const int o = d.perm[s];
-        const int key = id[o];
-        const int c = g.cell_off + d.cell_tmp[o];
-        const int a = d.cell_start[c], m = d.cell_cnt[c];
-        int rank = 0;
-        for (int t = a; t < a + m; ++t) rank += id[d.perm[t]] < key ? 1 : 0;
-        d.ticket[a + rank] = o;
-    }
-}
-
-// Gather into cell-sorted, coalesced arrays (A3) and write cell-relative FP32
-// coordinates for the mixed path.
-__global__ __launch_bounds__(kBlock) void k_permute(Dev d, Params p) {
-    if (!*d.any) return;  // no box rebuilds this step
-    const int l = lane_id();
-    for (int w = blockIdx.x * 4 + (threadIdx.x >> 6); w < p.nwave; w += gridDim.x * 4) {
-        const int b = d.wave_box[w];
-        const BoxState& st = d.st[b];
-        if (!st.rebuild) continue;
-        const BoxGeom& g = d.geom[b];
-        const int s = w * kWave + l;
-        if (s - g.slot_off >= g.npart) continue;
         const int sq = st.sq, sp = st.sp, nq = sq ^ 1, np = sp ^ 1;
-        const int o = d.ticket[s];  // source slot, ordered within the cell by k_cell_rank
-        Pos x = d.q[sq][o];
-        d.vx[np][s] = d.vx[sp][o];
-        d.vy[np][s] = d.vy[sp][o];
-        d.vz[np][s] = d.vz[sp][o];
-        d.id[np][s] = d.id[sp][o];
+        const int32_t* __restrict__ id = d.id[sp];
+        const int o = d.perm[s];  // a particle of this cell, in arrival order
+        const int key = id[o];
         const int cid = d.cell_tmp[o];
+        const int c = g.cell_off + cid;
+        const int a = d.cell_start[c], m = d.cell_cnt[c];
+        int rank = 0;  // its place in the cell: order by caller id
+        for (int t = a; t < a + m; ++t) rank += id[d.perm[t]] < key ? 1 : 0;
+        const int dst = a + rank;
+        Pos x = d.q[sq][o];
+        d.vx[np][dst] = d.vx[sp][o];
+        d.vy[np][dst] = d.vy[sp][o];
+        d.vz[np][dst] = d.vz[sp][o];
+        d.id[np][dst] = key;
         const int cx = cid % g.n[0], tq = cid / g.n[0];
         const int cy = tq % g.n[1], cz = tq / g.n[1];
         const uint32_t cc = (uint32_t)cx | ((uint32_t)cy << 10) | ((uint32_t)cz << 20);
         x.cc = cc;
         x.cnt = 0;
-        d.q[nq][s] = x;
-        if (p.precision == MD_PREC_FP32_MIXED) put_u(d.u[nq], s, units3(x, cc, g));
-        if (d.qb) d.qb[s] = make_double4(x.x, x.y, x.z, 0.0);
+        d.q[nq][dst] = x;
+        if (p.precision == MD_PREC_FP32_MIXED) put_u(d.u[nq], dst, units3(x, cc, g));
+        if (d.qb) d.qb[dst] = make_double4(x.x, x.y, x.z, 0.0);
     }
 }
 
@@ -1811,8 +1796,7 @@ void launch_rebuild_chain(const Dev& d, const Params& p, bool with_list, hipStre
     k_scan_box<<<p.nbox < 1024 ? p.nbox : 1024, kBlock, 0, s>>>(d, p);
     k_scan_add<<<gt, kBlock, 0, s>>>(d, p);
     k_scatter<<<gw, kBlock, 0, s>>>(d, p);
-    k_cell_rank<<<gw, kBlock, 0, s>>>(d, p);
-    k_permute<<<gw, kBlock, 0, s>>>(d, p);
+    k_rank_permute<<<gw, kBlock, 0, s>>>(d, p);
     k_flip<<<1, kBlock, 0, s>>>(d, p);
     if (with_list) {
         switch (p.tpk) {
