@@ -844,7 +844,7 @@ __device__ __forceinline__ void stripe_put(unsigned long long* base, int b, int 
 template <int PREC, int MODE, int TPK, bool ENERGY, bool HALF>
 __device__ __forceinline__ void force_finish(const Dev& d, const Params& p, const BoxGeom& g, int b, int lw, int key,
                                              bool owner, const Pos& qi, uint32_t cc, int sq, int sp, double Fx,
-                                             double Fy, double Fz, double pe, double vir) {
+                                             double Fy, double Fz, double pe, double vir, bool f_done = false) {
     const int l = lane_id();
     if (TPK > 1) {
 #pragma unroll
@@ -865,9 +865,11 @@ __device__ __forceinline__ void force_finish(const Dev& d, const Params& p, cons
     double ke = 0.0, w2 = 0.0, m2 = 0.0;
     if (MODE == kForceOnly) {
         if (owner && HALF) {  // other keys add their reactions to this particle concurrently
-            unsafeAtomicAdd(d.fx + key, Fx);
-            unsafeAtomicAdd(d.fy + key, Fy);
-            unsafeAtomicAdd(d.fz + key, Fz);
+            if (!f_done) {  // else already added through the wavefront's LDS accumulators
+                unsafeAtomicAdd(d.fx + key, Fx);
+                unsafeAtomicAdd(d.fy + key, Fy);
+                unsafeAtomicAdd(d.fz + key, Fz);
+            }
         } else if (owner) {
             d.fx[key] = Fx;
             d.fy[key] = Fy;
@@ -939,6 +941,7 @@ __device__ __forceinline__ void force_finish(const Dev& d, const Params& p, cons
 // not a branch (as Algorithm 1's mask w), and only a lane's last, partial chunk
 // of entries pays for an end-of-list check.
 constexpr int kHomeMax = 12;  // distinct key cells per wavefront served from LDS
+constexpr int kAccCap = 512;  // half list: partner accumulators per wavefront in LDS
 
 template <int PREC>
 struct ForceTab {
@@ -1014,6 +1017,75 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Params p) {
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
+
+    // Half list: the reactions of a wavefront whose keys lie in one row of cells,
+    // away from the x faces, accumulate in LDS.  Its forward partners then lie in
+    // five row segments -- the same row from the first home cell, and rows
+    // (dy, dz) = (1, 0), (-1, 1), (0, 1), (1, 1) from one cell before it, each up to
+    // one cell past the last home cell -- every one a contiguous run of slots.  The
+    // accumulators leave once, as atomic adds to consecutive slots; other wavefronts
+    // add every reaction to HBM directly.
+    using Acc = std::conditional_t<MIX, float, double>;
+    __shared__ Acc acc[HALF ? kBlock / kWave : 1][HALF ? 3 * kAccCap : 1];
+    __shared__ int32_t atab[HALF ? kBlock / kWave : 1][HALF ? kHomeMax * 27 : 1];
+    __shared__ int32_t segs[HALF ? kBlock / kWave : 1][10];  // first slot, then LDS base, of each row segment
+    bool local = false;
+    int ntot = 0;
+    if constexpr (HALF) {
+        if (tabled) {
+            const uint32_t c0 = home_cc[wib][0], c1 = home_cc[wib][nhome - 1];
+            const int x0 = (int)(c0 & 1023), x1 = (int)(c1 & 1023);
+            local = (c0 >> 10) == (c1 >> 10) && x0 >= 1 && x1 <= g.n[0] - 2;
+        }
+        if (local) {
+            const uint32_t c0 = home_cc[wib][0], c1 = home_cc[wib][nhome - 1];
+            const int x0 = (int)(c0 & 1023), x1 = (int)(c1 & 1023);
+            int lo = 0, len = 0;
+            if (l < 5) {  // row segment l: (dy, dz) = (0,0), (1,0), (-1,1), (0,1), (1,1)
+                const int oy = l == 0 ? 0 : (l == 1 ? 1 : l - 3), oz = l < 2 ? 0 : 1;
+                int y = (int)((c0 >> 10) & 1023) + oy, z = (int)(c0 >> 20) + oz;
+                if (y < 0) y += g.n[1];
+                if (y >= g.n[1]) y -= g.n[1];
+                if (z >= g.n[2]) z -= g.n[2];
+                const int row = g.cell_off + (z * g.n[1] + y) * g.n[0];
+                const int ca = row + (l == 0 ? x0 : x0 - 1), cb = row + x1 + 1;
+                lo = d.cell_start[ca];
+                len = d.cell_start[cb] + d.cell_cnt[cb] - lo;
+            }
+            const int incl = wave_incl_scan(len);
+            ntot = __builtin_amdgcn_readlane(incl, 4);
+            local = ntot <= kAccCap;  // uniform
+            if (local) {
+                if (l < 5) {
+                    segs[wib][l] = lo;
+                    segs[wib][5 + l] = incl - len;
+                }
+                for (int i = l; i < 3 * ntot; i += kWave) acc[wib][i] = Acc(0);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                for (int idx = l; idx < nhome * 27; idx += kWave) {
+                    const int hh = idx / 27, s = idx - hh * 27;
+                    int v = -1;  // backward cells hold no half-list partners
+                    if (s >= 13) {
+                        uint32_t img;
+                        const int nc = stencil_cell(home_cc[wib][hh], s, g, &img);
+                        const int r = s <= 14 ? 0 : (s - 15) / 3 + 1;
+                        v = segs[wib][5 + r] + (d.cell_start[nc] - segs[wib][r]);
+                    }
+                    atab[wib][idx] = v;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
+        }
+    }
+    auto lds_add = [&](int li, Acc x, Acc y, Acc z) {
+        __hip_atomic_fetch_add(&acc[wib][3 * li], x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_fetch_add(&acc[wib][3 * li + 1], y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_fetch_add(&acc[wib][3 * li + 2], z, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    };
 
     double Fx = 0.0, Fy = 0.0, Fz = 0.0, pe = 0.0, vir = 0.0;  // vir: sum_j f r^2 (energy passes)
     // The pair loop, instantiated twice so the choice between the LDS table and
@@ -1092,9 +1164,14 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Params p) {
                     Fy += f * dy;
                     Fz += f * dz;
                     if (HALF && in) {  // Newton's third law: the reaction on the partner
-                        unsafeAtomicAdd(d.fx + js[k], -(f * dx));
-                        unsafeAtomicAdd(d.fy + js[k], -(f * dy));
-                        unsafeAtomicAdd(d.fz + js[k], -(f * dz));
+                        if (local) {
+                            lds_add(atab[wib][h * 27 + (int)ent_s(raw, k)] + (int)ent_r(raw, k), -(f * dx), -(f * dy),
+                                    -(f * dz));
+                        } else {
+                            unsafeAtomicAdd(d.fx + js[k], -(f * dx));
+                            unsafeAtomicAdd(d.fy + js[k], -(f * dy));
+                            unsafeAtomicAdd(d.fz + js[k], -(f * dz));
+                        }
                     }
                     if (ENERGY) {
                         pe += in ? 2.0 * (e + p.c2 * r2 + p.c0) : 0.0;
@@ -1150,9 +1227,15 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Params p) {
                     by += fdy;
                     bz += fdz;
                     if (HALF && in) {  // Newton's third law: the reaction on the partner, in lengths
-                        unsafeAtomicAdd(d.fx + js[k], -(double)fdx * lamd);
-                        unsafeAtomicAdd(d.fy + js[k], -(double)fdy * lamd);
-                        unsafeAtomicAdd(d.fz + js[k], -(double)fdz * lamd);
+                        if (local) {
+                            const float lamf = g.lam;  // a power of two: exact scaling
+                            lds_add(atab[wib][h * 27 + (int)st[k]] + (int)ent_r(raw, k), -(fdx * lamf), -(fdy * lamf),
+                                    -(fdz * lamf));
+                        } else {
+                            unsafeAtomicAdd(d.fx + js[k], -(double)fdx * lamd);
+                            unsafeAtomicAdd(d.fy + js[k], -(double)fdy * lamd);
+                            unsafeAtomicAdd(d.fz + js[k], -(double)fdz * lamd);
+                        }
                     }
                     if (ENERGY) {
                         pes += in ? 2.0f * (inv3 * inv3 - inv3 + p.c2f * (r2 * lam2) + p.c0f) : 0.0f;
@@ -1179,8 +1262,31 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Params p) {
         else
             pair_loop(std::false_type{});
     }
+    bool f_done = false;
+    if constexpr (HALF) {
+        if (local) {  // own sums join the accumulators, which then leave in one pass
+            if (active) lds_add(segs[wib][5] + (key - segs[wib][0]), (Acc)Fx, (Acc)Fy, (Acc)Fz);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            for (int i = l; i < ntot; i += kWave) {
+                int r = 0;
+#pragma unroll
+                for (int rr = 1; rr < 5; ++rr) r = i >= segs[wib][5 + rr] ? rr : r;
+                const int slot = segs[wib][r] + (i - segs[wib][5 + r]);
+                const double ax = (double)acc[wib][3 * i], ay = (double)acc[wib][3 * i + 1],
+                             az = (double)acc[wib][3 * i + 2];
+                if (ax != 0.0 || ay != 0.0 || az != 0.0) {
+                    unsafeAtomicAdd(d.fx + slot, ax);
+                    unsafeAtomicAdd(d.fy + slot, ay);
+                    unsafeAtomicAdd(d.fz + slot, az);
+                }
+            }
+            f_done = true;
+        }
+    }
     force_finish<PREC, MODE, TPK, ENERGY, HALF>(d, p, g, b, lw, key, active && sub == 0, qi, cc, sq, sp, Fx, Fy, Fz,
-                                                pe, vir);
+                                                pe, vir, f_done);
 }
 
 // FP32-mixed force pass with LDS-staged partner tiles (one lane per key).  The
