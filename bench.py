@@ -491,7 +491,8 @@ def main():
                                          "correction of r^-8 and r^-14")
     if half:
         out["half_list"] = dict(half, note="MD_F_HALF_LIST: each pair once (home cell after the key, 13 forward "
-                                           "stencil cells), reactions added to partners atomically, integration "
+                                           "stencil cells), reactions accumulated per wavefront in LDS and "
+                                           "flushed with atomic adds, integration "
                                            "as a separate pass; force_ms_avg covers clearing F, the force pass "
                                            "and the integration pass")
     if not args.no_cpu:

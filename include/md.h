@@ -83,9 +83,11 @@ typedef enum {
                                       r^-14 (r^-2n ~ xt^n ((n + 1) - n xt r^2)) instead of a division */
 #define MD_F_HALF_LIST 32u         /* half list with Newton's third law (Sec. II.A, Fig. 1 holds each
                                       pair once): a key lists its partners in the home cell after
-                                      itself and in the 13 forward stencil cells; the force pass adds
-                                      each pair's reaction to the partner atomically, then a separate
-                                      pass integrates.  One lane per key (threads_per_key 0 or 1); not
+                                      itself and in the 13 forward stencil cells; the force pass sends
+                                      each pair's reaction to the partner (accumulated per wavefront in
+                                      LDS and flushed with atomic adds where the wavefront's partners
+                                      form contiguous row segments, else added atomically at once), then
+                                      a separate pass integrates.  One lane per key (threads_per_key 0 or 1); not
                                       with MD_F_VERIFY_LIST or MD_F_TILE_ON.  Forces agree with the
                                       full list within the precision's tolerance but are not bitwise
                                       reproducible (the order of the atomic additions varies). */
