@@ -638,36 +638,44 @@ __device__ __forceinline__ void list_pass(const Dev& d, const Params& p, const P
     __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
     const double rl2 = p.rl2;
     const int cap = p.cap, rows = p.rows;
-    double nx = qc[4 * (cs0 + kb)], ny = qc[4 * (cs0 + kb) + 1], nz = qc[4 * (cs0 + kb) + 2];
-    for (int a = 0; a < mb; ++a) {
-        const int key = cs0 + kb + a;
-        double4 qi;  // scalar loads, one key ahead
-        qi.x = nx;
-        qi.y = ny;
-        qi.z = nz;
-        if (a + 1 < mb) {
-            nx = qc[4 * (key + 1)];
-            ny = qc[4 * (key + 1) + 1];
-            nz = qc[4 * (key + 1) + 2];
-        }
-        int cnt = c0 == 0 ? 0 : __builtin_amdgcn_readlane(n_own, a);  // uniform running count
-        // the key's own candidate: chunk sk, bit sb (scalar)
-        const int self = pre13 + kb + a - c0;
-        const int sk = self >> 6;
-        const unsigned long long sb = 1ull << (self & 63);
-        char* __restrict__ kp = STAGED ? reinterpret_cast<char*>(stage + a * cap)
-                                       : reinterpret_cast<char*>(d.list + list_addr(key, 0, TPK, rows));
+    // The key loop, instantiated per chunk count so that every chunk's distances are
+    // computed ahead of the (serial) compaction chain, with no branches between them.
+    auto key_loop = [&](auto n_c) {
+        constexpr int N = decltype(n_c)::value;
+        double nx = qc[4 * (cs0 + kb)], ny = qc[4 * (cs0 + kb) + 1], nz = qc[4 * (cs0 + kb) + 2];
+        for (int a = 0; a < mb; ++a) {
+            const int key = cs0 + kb + a;
+            double4 qi;  // scalar loads, one key ahead
+            qi.x = nx;
+            qi.y = ny;
+            qi.z = nz;
+            if (a + 1 < mb) {
+                nx = qc[4 * (key + 1)];
+                ny = qc[4 * (key + 1) + 1];
+                nz = qc[4 * (key + 1) + 2];
+            }
+            int cnt = c0 == 0 ? 0 : __builtin_amdgcn_readlane(n_own, a);  // uniform running count
+            // the key's own candidate: chunk sk, bit sb (scalar)
+            const int self = pre13 + kb + a - c0;
+            const int sk = self >> 6;
+            const unsigned long long sb = 1ull << (self & 63);
+            char* __restrict__ kp = STAGED ? reinterpret_cast<char*>(stage + a * cap)
+                                           : reinterpret_cast<char*>(d.list + list_addr(key, 0, TPK, rows));
+            bool in[N];
 #pragma unroll
-        for (int k = 0; k < G; ++k) {
-            if (k < nch) {
+            for (int k = 0; k < N; ++k) {
                 const double r2 = WRAP ? dist2_exact(qi, make_double3(cx[k], cy[k], cz[k]), sx[k], sy[k], sz[k])
                                        : dist2_exact0(qi, make_double3(cx[k], cy[k], cz[k]));
+                in[k] = r2 < rl2;
+            }
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
                 // lanes within the list radius, minus the key itself; the half list
                 // keeps only candidates after the key (the home cell comes first and
                 // the backward stencil cells hold no candidates)
                 const unsigned long long mask =
-                    HALF ? __builtin_amdgcn_ballot_w64(r2 < rl2 && k * kWave + l > self)
-                         : __builtin_amdgcn_ballot_w64(r2 < rl2) & ~(k == sk ? sb : 0ull);
+                    HALF ? __builtin_amdgcn_ballot_w64(in[k] && k * kWave + l > self)
+                         : __builtin_amdgcn_ballot_w64(in[k]) & ~(k == sk ? sb : 0ull);
                 const uint32_t pos = __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
                                                                __builtin_amdgcn_mbcnt_lo((unsigned)mask, (unsigned)cnt));
                 unsigned long long sm = mask;
@@ -680,8 +688,24 @@ __device__ __forceinline__ void list_pass(const Dev& d, const Params& p, const P
                 }
                 cnt += __popcll(mask);
             }
+            if (l == a) n_own = cnt;
         }
-        if (l == a) n_own = cnt;
+    };
+    switch (nch) {
+        case 1: key_loop(std::integral_constant<int, 1>{}); break;
+        case 2: key_loop(std::integral_constant<int, 2>{}); break;
+        default:
+            if constexpr (G == 3) {
+                key_loop(std::integral_constant<int, 3>{});
+            } else {
+                switch (nch) {
+                    case 3: key_loop(std::integral_constant<int, 3>{}); break;
+                    case 4: key_loop(std::integral_constant<int, 4>{}); break;
+                    case 5: key_loop(std::integral_constant<int, 5>{}); break;
+                    default: key_loop(std::integral_constant<int, 6>{}); break;
+                }
+            }
+            break;
     }
 }
 
