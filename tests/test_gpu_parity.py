@@ -424,6 +424,28 @@ def test_bad_positions_report_numeric_error():
             assert e.value.status == b.MD_ENUMERIC
 
 
+def test_overfull_cell_reports_numeric_error():
+    """A cell holding more than 2048 particles (ranks no longer fit the 11-bit
+    list entries) is reported as MD_ENUMERIC by the list build, for both
+    precisions; a cell of exactly 2048 is accepted."""
+    b = B()
+    L = 8.4  # 3 cells of 2.8 per axis
+    for n, ok in ((2049, False), (2048, True)):
+        q = np.full((n, 3), 0.1) + rng(n).uniform(0.0, 2.6, size=(n, 3))  # all in cell (0, 0, 0)
+        q = np.concatenate([q, [[5.0, 5.0, 5.0]]])                        # one more particle elsewhere
+        v = np.zeros_like(q)
+        for prec in (0, 1):
+            with make_ctx(q, v, L, precision=prec) as c:
+                if ok:
+                    c.build_neighbors()
+                    assert c.stats()["max_list_len"] >= n - 1
+                else:
+                    with pytest.raises(b.MDError) as e:
+                        c.build_neighbors()
+                    assert e.value.status == b.MD_ENUMERIC
+                    assert "2048" in str(e.value)
+
+
 def test_state_errors():
     b = B()
     p = b.make_params(1000, 12.0)
