@@ -485,10 +485,11 @@ __global__ __launch_bounds__(kBlock) void k_scatter(Dev d, Params p) {
 }
 
 // Arrival order within a cell depends on atomics; each cell's members are placed
-// by caller id so the sorted layout is a function of the positions alone.  One
-// lane per particle, taken in arrival order: its rank among the cell's members by
-// caller id is its new slot, and its state is copied there (position record with
-// the new cell, fixed-point record, velocities, caller id).
+// in the order of their previous slots, so every layout is a function of the
+// initial one and the trajectory (the first build after md_set_state orders by
+// caller id).  One lane per particle, taken in arrival order: its rank among the
+// cell's members is its new slot, and its state is copied there (position record
+// with the new cell, fixed-point record, velocities, caller id).
 __global__ __launch_bounds__(kBlock) void k_rank_permute(Dev d, Params p) {
     if (!*d.any) return;  // no box rebuilds this step
     const int l = lane_id();
@@ -506,8 +507,8 @@ __global__ __launch_bounds__(kBlock) void k_rank_permute(Dev d, Params p) {
         const int cid = d.cell_tmp[o];
         const int c = g.cell_off + cid;
         const int a = d.cell_start[c], m = d.cell_cnt[c];
-        int rank = 0;  // its place in the cell: order by caller id
-        for (int t = a; t < a + m; ++t) rank += id[d.perm[t]] < key ? 1 : 0;
+        int rank = 0;  // its place in the cell: order by previous slot
+        for (int t = a; t < a + m; ++t) rank += d.perm[t] < o ? 1 : 0;
         const int dst = a + rank;
         Pos x = d.q[sq][o];
         d.vx[np][dst] = d.vx[sp][o];
