@@ -577,3 +577,19 @@ def test_bubble_single_subcell_axis():
     r = oracle.bubbles(q, (15.0, 10.0, 5.0), side=5.0, rho_gas=0.2)
     assert r.nsub == (3, 2, 1)
     assert list(r.roots) == [0] and list(r.sizes) == [3]
+
+
+def test_thermostat_splitting_is_time_reversible():
+    """thermostat(dt/2) . velocity Verlet . thermostat(dt/2) is a symmetric
+    splitting: 50 steps forward, then 50 with v and xi negated, return to the
+    start (positions and velocities to rounding, xi to zero).  An asymmetric
+    order of the half steps, or a wrong sign in the friction, breaks this."""
+    w = inputs.small_nve()
+    r1 = oracle.run_obs(w.pos, w.vel, w.box, 50, energy_every=10, T=1.5, tau=0.1)
+    assert abs(r1.xi) > 1e-3  # the thermostat acted
+    r2 = oracle.run_obs(r1.q, -r1.v, w.box, 50, energy_every=10, T=1.5, tau=0.1, xi=-r1.xi)
+    d = r2.q - w.pos
+    d -= 20.0 * np.rint(d / 20.0)
+    assert np.abs(d).max() < 1e-11
+    assert np.abs(r2.v + w.vel).max() < 1e-11
+    assert abs(r2.xi) < 1e-12
