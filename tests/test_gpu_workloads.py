@@ -98,11 +98,15 @@ def test_cavitation_protocol_reduced_size():
         assert P_liq > 0.0 > P_exp
         c.step(400, 10)
         kes, pes = c.energy_series()
+        virs, _ = c.observable_series()
         q, _ = c.get_state()
         c.build_neighbors()
         kp, pl = c.get_neighbors()
         F = c.compute_forces().cpu().numpy()
     L = w.box[0] * 1.1
+    P = (2.0 * kes[:, 0] - virs[:, 0]) / (3.0 * L ** 3)  # virial pressure along the NVE run
+    print("pressure after expansion: step 10 %.4f, step 400 %.4f" % (P[0], P[-1]))
+    assert P[0] < 0.0 and P[-1] > P[0]  # negative on expansion, then recovering (Sec. IV.C)
     q = q.cpu().numpy()
     kpr, plr = oracle.neighbors(q, L, 3.3)
     np.testing.assert_array_equal(kp.cpu().numpy(), kpr)
