@@ -127,15 +127,22 @@ def test_fcc1m_full_parity():
         assert (np.linalg.norm(F - Fr, axis=1) / A).max() <= tol
 
 
-def test_fcc32m_sampled_parity_in_bench_configuration():
-    """32,000,000 particles, FP32-mixed, default layout (as bench.py runs it):
-    all cell ids bit-exact, 2000 sampled neighbour sets bit-exact, sampled forces
-    within 1e-5 normalised, after 10 steps."""
+@pytest.mark.parametrize("name,precision,flags,tol", [
+    ("fp32_mixed", 1, 0, 1e-5),
+    ("fp64", 0, 0, 1e-12),
+    ("fp32_mixed_half_list", 1, 32, 1e-5),
+])
+def test_fcc32m_sampled_parity_in_bench_configuration(name, precision, flags, tol):
+    """32,000,000 particles in the layouts bench.py times (default lanes per key;
+    the half list with one): after 10 steps, all cell ids bit-exact, 2000 sampled
+    neighbour sets bit-exact (full lists), sampled forces within the precision's
+    bar."""
     b = B()
     w = inputs.large_32m()
     rng = np.random.Generator(np.random.PCG64(77))
     ids = np.sort(rng.choice(w.n, 2000, replace=False))
-    with b.Context(b.make_params(w.n, w.box, precision=b.MD_PREC_FP32_MIXED)) as c:
+    half = bool(flags & b.MD_F_HALF_LIST)
+    with b.Context(b.make_params(w.n, w.box, precision=precision, flags=flags)) as c:
         c.set_state(w.pos, w.vel)
         c.step(10)
         q, _ = c.get_state()
@@ -144,18 +151,21 @@ def test_fcc32m_sampled_parity_in_bench_configuration():
         F = F[torch.as_tensor(ids, device=F.device)].cpu().numpy()
         cells, _ = c.get_cells()
         cells = cells.cpu().numpy()
-        kp, pl = c.get_neighbors()
-        idt = torch.as_tensor(ids, device=kp.device)
-        starts = kp[idt].cpu().numpy()
-        ends = kp[idt + 1].cpu().numpy()
-        sets = [pl[s:e].cpu().numpy() for s, e in zip(starts, ends)]
-        del kp, pl
+        sets = None
+        if not half:
+            kp, pl = c.get_neighbors()
+            idt = torch.as_tensor(ids, device=kp.device)
+            starts = kp[idt].cpu().numpy()
+            ends = kp[idt + 1].cpu().numpy()
+            sets = [pl[s:e].cpu().numpy() for s, e in zip(starts, ends)]
+            del kp, pl
     q = q.cpu().numpy()
     qw, cref, _ = oracle.cells(q, w.box, 2.8)
     np.testing.assert_array_equal(cells, cref)
     del cref, cells
-    ref = oracle.neighbors_sample(qw, w.box, 2.8, ids)
-    for s, r in zip(sets, ref):
-        np.testing.assert_array_equal(s, r)
+    if sets is not None:
+        ref = oracle.neighbors_sample(qw, w.box, 2.8, ids)
+        for s_, r in zip(sets, ref):
+            np.testing.assert_array_equal(s_, r)
     Fr, A, _ = oracle.forces_sample(qw, w.box, 2.5, ids)
-    assert (np.linalg.norm(F - Fr, axis=1) / A).max() <= 1e-5
+    assert (np.linalg.norm(F - Fr, axis=1) / A).max() <= tol
