@@ -130,6 +130,7 @@ def test_fcc1m_full_parity():
 @pytest.mark.parametrize("name,precision,flags,tol", [
     ("fp32_mixed", 1, 0, 1e-5),
     ("fp64", 0, 0, 1e-12),
+    ("fp64_fast_reciprocal", 0, 16, 1e-12),
     ("fp32_mixed_half_list", 1, 32, 1e-5),
 ])
 def test_fcc32m_sampled_parity_in_bench_configuration(name, precision, flags, tol):
