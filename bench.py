@@ -46,6 +46,8 @@ def pairs_within_rc_per_particle(rho, rc):
 
 
 REBUILD_BYTES_PER_PARTICLE = 260.0  # binning 32, permute 104, list build 124 (per particle per rebuild)
+MIXED_NOTE = ("pair forces in FP32 on exact fixed-point cell-relative separations; positions, velocities, "
+              "integration and energy totals in FP64")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_force_mixed_fcc32m_hbm_traffic.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1210_3450_amd", "csrc", f) for f in ("md_kernels.hip", "md_internal.h")]
 
@@ -207,7 +209,7 @@ def workload_medium(B, torch, args):
                      "drift_1000_steps": drift_stats(ke[:, 0], pe[:, 0], w.n, w.dt, 100)}
     return {"metric": "particle-steps/s, 1M LJ, FP32-mixed vs FP64 on 1 MI355X",
             "value": out["fp32_mixed"]["particle_steps_per_s"], "unit": "particle-steps/s", "n_gpus": 1,
-            "steps": 1000, "higher_is_better": True, "dtype": "f32 pair forces / f64 state", "data": "synthetic",
+            "steps": 1000, "higher_is_better": True, "dtype": "f32", "dtype_note": MIXED_NOTE, "data": "synthetic",
             "config": {"workload": "fcc1M_rho0.5_rc2.5_skin0.3_dt0.005", "graphs": True}, "paths": out}
 
 
@@ -310,7 +312,7 @@ def workload_cavitation(B, torch, args):
     res["bubbles_nve_step"] = bubbles
     return {"metric": "particle-steps/s, cavitation box (uneven lists), FP32-mixed on 1 MI355X",
             "value": res["fp32_mixed"]["particle_steps_per_s"], "unit": "particle-steps/s", "n_gpus": 1,
-            "steps": args.cav_steps, "higher_is_better": True, "dtype": "f32 pair forces / f64 state",
+            "steps": args.cav_steps, "higher_is_better": True, "dtype": "f32", "dtype_note": MIXED_NOTE,
             "data": "synthetic", "config": {"workload": "sc%d^3_rho0.7_T0.9_rc3.0_expand1.1" % args.cav_side},
             "results": res}
 
@@ -353,7 +355,7 @@ def workload_batch(B, torch, args):
     return {"metric": "particle-steps/s, 256-box LJ ensemble, FP32-mixed on 1 MI355X",
             "value": ntot * args.batch_steps / (ms / 1e3), "unit": "particle-steps/s", "n_gpus": 1,
             "steps": args.batch_steps, "ms_per_step": ms / args.batch_steps, "higher_is_better": True,
-            "dtype": "f32 pair forces / f64 state", "data": "synthetic",
+            "dtype": "f32", "dtype_note": MIXED_NOTE, "data": "synthetic",
             "config": {"workload": "ensemble%d_N2000-65536_rho0.3-0.8_T0.7-1.2" % args.nbox, "n_particles": ntot,
                        "graphs": True, "threads_per_key": st["threads_per_key"]},
             "one_box_at_a_time": {"particle_steps_per_s": n_one / (t_one / 1e3), "boxes": args.baseline_boxes,
@@ -465,7 +467,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 pair forces / f64 state",
+        "dtype": "f32", "dtype_note": MIXED_NOTE,
         "data": "synthetic: FCC lattice, Maxwell-Boltzmann velocities (seeded)",
         "config": {"workload": "fcc32M_rho0.5_rc2.5_skin0.3_dt0.005" if args.ncell == 200 else w.name,
                    "n_particles": w.n, "box": w.box[0], "rc": w.rc, "skin": w.skin, "dt": w.dt,
