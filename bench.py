@@ -116,6 +116,26 @@ def run_gpu(B, torch, w, precision, steps, warmup, tpk=0, flags=0):
     }
 
 
+def copy_bandwidth(torch, nbytes=1 << 30, reps=5):
+    """Device-to-device copy rate (bytes read + written per second) of a plain
+    torch copy_ of nbytes, the best of reps, as the practical HBM ceiling."""
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / (best / 1e3) / 1e9
+
+
 def cpu_baseline(w, sample_steps):
     """The FP64 oracle, as it stands, on the same 32M state: its initial list
     build plus sample_steps velocity-Verlet steps (DUTC rebuilds included)."""
@@ -455,6 +475,7 @@ def main():
     step_bpp = bpp + (REBUILD_BYTES_PER_PARTICLE / interval if interval else 0.0)
     step_achieved = step_bpp * w.n / (mixed["ms_per_step"] / 1e3) / 1e9
     traffic = measured_traffic() if args.ncell == 200 else None
+    copy_gbs = copy_bandwidth(torch)
 
     out = {
         "metric": "particle-steps/s + Gflop/s, 32M LJ, FP32-mixed vs FP64 on 1 MI355X",
@@ -479,9 +500,11 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_unit": "HBM bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, copy-calibrated)",
                      "kernel": "k_force<FP32_MIXED> (pair forces + kicks + drift)",
-                     "bytes_per_particle": bpp, "launch_ms_avg": mixed["force_ms_avg"]},
+                     "bytes_per_particle": bpp, "launch_ms_avg": mixed["force_ms_avg"],
+                     "copy_gbs_measured": copy_gbs, "frac_of_copy": achieved / copy_gbs},
         "step_roofline": {"bound": "hbm", "achieved": step_achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                          "frac": step_achieved / HBM_PEAK_GBS, "bytes_per_particle_step": step_bpp,
+                          "frac": step_achieved / HBM_PEAK_GBS, "frac_of_copy": step_achieved / copy_gbs,
+                          "bytes_per_particle_step": step_bpp,
                           "rebuild_interval_steps": interval},
     }
     if fp64 is not None:

@@ -974,7 +974,7 @@ struct ForceTab {
 };
 template <>
 struct ForceTab<MD_PREC_FP32_MIXED> {
-    using Rec = int4;  // FP32-mixed: start slot, stencil offset o * uoff per axis
+    using Rec = int32_t;  // FP32-mixed: start slot (the stencil offsets o * uoff depend on s only)
 };
 
 // Record of stencil cell s of the cell with packed coordinates cc.
@@ -986,8 +986,7 @@ __device__ __forceinline__ typename ForceTab<PREC>::Rec force_rec(const Dev& d, 
     if constexpr (PREC == MD_PREC_FP64) {
         return (uint32_t)d.cell_start[nc] | (img << kIdxBits);
     } else {
-        return make_int4(d.cell_start[nc], (s % 3 - 1) * g.uoff[0], ((s / 3) % 3 - 1) * g.uoff[1],
-                         (s / 9 - 1) * g.uoff[2]);
+        return d.cell_start[nc];
     }
 }
 
@@ -1004,6 +1003,9 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Params p) {
     __shared__ double4 shift[MIX ? 1 : kBlock / kWave][27];  // FP64: image term per code
     __shared__ uint32_t home_cc[kBlock / kWave][kWave];
     __shared__ Rec tab[kBlock / kWave][kHomeMax * 27];
+    // FP32-mixed: stencil offset o * uoff of stencil cell s, one array per axis: 4-byte
+    // words read by stencil index, so lanes spread over the banks (or share a word)
+    __shared__ int32_t soff[MIX ? kBlock / kWave : 1][MIX ? 3 * 27 : 1];
     const int l = lane_id(), wib = threadIdx.x >> 6, sub = l % TPK;
     const int lw = xcd_block(blockIdx.x, gridDim.x) * 4 + wib;
     const int nlw = p.nwave * TPK;
@@ -1011,6 +1013,13 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Params p) {
     const int b = __builtin_amdgcn_readfirstlane(wave_ok ? d.wave_box[(lw * K) >> 6] : 0);
     if constexpr (!MIX) {
         if (l < 27) shift[wib][l] = d.dshift[b * 27 + l];
+    } else {
+        if (l < 27) {
+            const BoxGeom& gb = d.geom[b];
+            soff[wib][l] = (l % 3 - 1) * gb.uoff[0];
+            soff[wib][27 + l] = ((l / 3) % 3 - 1) * gb.uoff[1];
+            soff[wib][54 + l] = (l / 9 - 1) * gb.uoff[2];
+        }
     }
     __syncthreads();
     if (!wave_ok) return;
@@ -1222,7 +1231,7 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Params p) {
                 for (int k = 0; k < U; ++k) {
                     const bool ok = !CHK || k < valid;
                     st[k] = ok ? ent_s(raw, k) : 13u;
-                    js[k] = ok ? (uint32_t)rec(st[k]).x + ent_r(raw, k) : (uint32_t)key;
+                    js[k] = ok ? (uint32_t)rec(st[k]) + ent_r(raw, k) : (uint32_t)key;
                 }
                 int4 uj[U];
 #pragma unroll
@@ -1237,11 +1246,11 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Params p) {
                 float bx = 0.f, by = 0.f, bz = 0.f;  // plain FP32 sum of this batch
 #pragma unroll
                 for (int k = 0; k < U; ++k) {
-                    const int4 rk = rec(st[k]);
+                    const int* __restrict__ so = soff[wib] + st[k];
                     // exact integer separation in units, one rounding to FP32
-                    const float dx = (float)(uj[k].x + rk.y + nux);
-                    const float dy = (float)(uj[k].y + rk.z + nuy);
-                    const float dz = (float)(uj[k].z + rk.w + nuz);
+                    const float dx = (float)(uj[k].x + so[0] + nux);
+                    const float dy = (float)(uj[k].y + so[27] + nuy);
+                    const float dz = (float)(uj[k].z + so[54] + nuz);
                     const float r2 = dx * dx + dy * dy + dz * dz;
                     const bool in = (!CHK || k < valid) && r2 < rc2u;
                     const float inv = __builtin_amdgcn_rcpf(r2) * lam2inv;  // 1/r^2 in length units
@@ -1544,7 +1553,7 @@ __global__ __launch_bounds__(kBlock) void k_force_tile(Dev d, Params p) {
                     for (int k = 0; k < U; ++k) {
                         const bool ok = !CHK || k < valid;
                         st[k] = ok ? ent_s(raw, k) : 13u;
-                        js[k] = ok ? (uint32_t)force_rec<MD_PREC_FP32_MIXED>(d, cc, (int)st[k], g).x + ent_r(raw, k)
+                        js[k] = ok ? (uint32_t)force_rec<MD_PREC_FP32_MIXED>(d, cc, (int)st[k], g) + ent_r(raw, k)
                                    : (uint32_t)key;
                     }
                     int4 uj[U];
