@@ -1000,7 +1000,8 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Params p) {
     constexpr int U = 8;  // entries per iteration (one 16-byte chunk)
     constexpr bool MIX = PREC == MD_PREC_FP32_MIXED;
     using Rec = typename ForceTab<PREC>::Rec;
-    __shared__ double4 shift[MIX ? 1 : kBlock / kWave][27];  // FP64: image term per code
+    // FP64: image term per code, one 27-entry array per axis (8-byte words read by code)
+    __shared__ double shift[MIX ? 1 : kBlock / kWave][3 * 27];
     __shared__ uint32_t home_cc[kBlock / kWave][kWave];
     __shared__ Rec tab[kBlock / kWave][kHomeMax * 27];
     // FP32-mixed: stencil offset o * uoff of stencil cell s, one array per axis: 4-byte
@@ -1012,7 +1013,12 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Params p) {
     const bool wave_ok = lw < nlw;
     const int b = __builtin_amdgcn_readfirstlane(wave_ok ? d.wave_box[(lw * K) >> 6] : 0);
     if constexpr (!MIX) {
-        if (l < 27) shift[wib][l] = d.dshift[b * 27 + l];
+        if (l < 27) {
+            const double4 sh = d.dshift[b * 27 + l];
+            shift[wib][l] = sh.x;
+            shift[wib][27 + l] = sh.y;
+            shift[wib][54 + l] = sh.z;
+        }
     } else {
         if (l < 27) {
             const BoxGeom& gb = d.geom[b];
@@ -1172,10 +1178,10 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Params p) {
                 if (!CHK && (c + 1 < nfull || ntail)) raw_next = l4[(size_t)(c + 1) * kWave];
 #pragma unroll
                 for (int k = 0; k < U; ++k) {
-                    const double4 sh = shift[wib][img[k]];
-                    const double dx = (qj[k].x - qi.x) - sh.x;
-                    const double dy = (qj[k].y - qi.y) - sh.y;
-                    const double dz = (qj[k].z - qi.z) - sh.z;
+                    const double* __restrict__ sh = shift[wib] + img[k];
+                    const double dx = (qj[k].x - qi.x) - sh[0];
+                    const double dy = (qj[k].y - qi.y) - sh[27];
+                    const double dz = (qj[k].z - qi.z) - sh[54];
                     const double r2 = dx * dx + dy * dy + dz * dz;
                     const bool in = (!CHK || k < valid) && r2 < rc2;
                     double f, e = 0.0;
