@@ -25,6 +25,16 @@ namespace mdg {
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
+// Index of the calling wavefront within its block, in a scalar register.
+__device__ __forceinline__ int wave_in_block() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
+
+// A wave-uniform read of a value the running kernel does not write, through the
+// constant address space, so it becomes a scalar load (scalar cache).
+__device__ __forceinline__ int ld_const(const int32_t* p) {
+    return *reinterpret_cast<const __attribute__((address_space(4))) int32_t*>(
+        reinterpret_cast<uintptr_t>(p));
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs (block b runs on XCD
 // b % 8).  Give XCD x a contiguous run of logical blocks so that neighbouring
 // keys, whose partners overlap, share that XCD's L2.  Bijective on [0, nb).
@@ -116,8 +126,8 @@ __device__ __forceinline__ int4 get_u(const int32_t* u, int s) {
 __global__ __launch_bounds__(kBlock) void k_set_state(Dev d, Params p, const double* __restrict__ pos,
                                                       const double* __restrict__ vel) {
     const int l = lane_id();
-    for (int w = blockIdx.x * 4 + (threadIdx.x >> 6); w < p.nwave; w += gridDim.x * 4) {
-        const int b = d.wave_box[w];
+    for (int w = blockIdx.x * 4 + wave_in_block(); w < p.nwave; w += gridDim.x * 4) {
+        const int b = ld_const(d.wave_box + w);
         const BoxGeom& g = d.geom[b];
         const int s = w * kWave + l;
         const int k = s - g.slot_off;
@@ -134,8 +144,8 @@ __global__ __launch_bounds__(kBlock) void k_set_state(Dev d, Params p, const dou
 __global__ __launch_bounds__(kBlock) void k_get_state(Dev d, Params p, double* __restrict__ pos,
                                                       double* __restrict__ vel) {
     const int l = lane_id();
-    for (int w = blockIdx.x * 4 + (threadIdx.x >> 6); w < p.nwave; w += gridDim.x * 4) {
-        const int b = d.wave_box[w];
+    for (int w = blockIdx.x * 4 + wave_in_block(); w < p.nwave; w += gridDim.x * 4) {
+        const int b = ld_const(d.wave_box + w);
         const BoxGeom& g = d.geom[b];
         const int s = w * kWave + l;
         if (s - g.slot_off >= g.npart) continue;
@@ -157,8 +167,8 @@ __global__ __launch_bounds__(kBlock) void k_get_state(Dev d, Params p, double* _
 
 __global__ __launch_bounds__(kBlock) void k_get_forces(Dev d, Params p, double* __restrict__ f) {
     const int l = lane_id();
-    for (int w = blockIdx.x * 4 + (threadIdx.x >> 6); w < p.nwave; w += gridDim.x * 4) {
-        const int b = d.wave_box[w];
+    for (int w = blockIdx.x * 4 + wave_in_block(); w < p.nwave; w += gridDim.x * 4) {
+        const int b = ld_const(d.wave_box + w);
         const BoxGeom& g = d.geom[b];
         const int s = w * kWave + l;
         if (s - g.slot_off >= g.npart) continue;
@@ -171,8 +181,8 @@ __global__ __launch_bounds__(kBlock) void k_get_forces(Dev d, Params p, double* 
 
 __global__ __launch_bounds__(kBlock) void k_get_cells(Dev d, Params p, int32_t* __restrict__ out) {
     const int l = lane_id();
-    for (int w = blockIdx.x * 4 + (threadIdx.x >> 6); w < p.nwave; w += gridDim.x * 4) {
-        const int b = d.wave_box[w];
+    for (int w = blockIdx.x * 4 + wave_in_block(); w < p.nwave; w += gridDim.x * 4) {
+        const int b = ld_const(d.wave_box + w);
         const BoxGeom& g = d.geom[b];
         const int s = w * kWave + l;
         if (s - g.slot_off >= g.npart) continue;
@@ -184,8 +194,8 @@ __global__ __launch_bounds__(kBlock) void k_get_cells(Dev d, Params p, int32_t* 
 
 __global__ __launch_bounds__(kBlock) void k_list_counts(Dev d, Params p, int64_t* __restrict__ out) {
     const int l = lane_id();
-    for (int w = blockIdx.x * 4 + (threadIdx.x >> 6); w < p.nwave; w += gridDim.x * 4) {
-        const int b = d.wave_box[w];
+    for (int w = blockIdx.x * 4 + wave_in_block(); w < p.nwave; w += gridDim.x * 4) {
+        const int b = ld_const(d.wave_box + w);
         const BoxGeom& g = d.geom[b];
         const int s = w * kWave + l;
         if (s - g.slot_off >= g.npart) continue;
@@ -248,8 +258,8 @@ __device__ __forceinline__ int entry_slot(const Dev& d, uint32_t cc, uint32_t e,
 __global__ __launch_bounds__(kBlock) void k_list_export(Dev d, Params p, const int64_t* __restrict__ key_ptr,
                                                         int32_t* __restrict__ partners) {
     const int l = lane_id();
-    for (int w = blockIdx.x * 4 + (threadIdx.x >> 6); w < p.nwave; w += gridDim.x * 4) {
-        const int b = d.wave_box[w];
+    for (int w = blockIdx.x * 4 + wave_in_block(); w < p.nwave; w += gridDim.x * 4) {
+        const int b = ld_const(d.wave_box + w);
         const BoxGeom& g = d.geom[b];
         const int s = w * kWave + l;
         if (s - g.slot_off >= g.npart) continue;
@@ -371,7 +381,7 @@ __global__ __launch_bounds__(kBlock) void k_post_build(Dev d, Params p, int with
 // ---------------------------------------------------------------- binning
 
 __global__ __launch_bounds__(kBlock) void k_cell_clear(Dev d, Params p) {
-    if (!*d.any) return;  // no box rebuilds this step
+    if (!ld_const(d.any)) return;  // no box rebuilds this step
     for (int t = blockIdx.x; t < p.ntile; t += gridDim.x) {
         if (!d.st[d.tile_box[t]].rebuild) continue;
         int4* c = reinterpret_cast<int4*>(d.cell_cnt + (size_t)t * kTile);
@@ -384,10 +394,10 @@ __global__ __launch_bounds__(kBlock) void k_cell_clear(Dev d, Params p) {
 // Slots arrive sorted by cell from the previous build, so a wavefront issues one
 // atomic per run of equal cells and hands out tickets within the run.
 __global__ __launch_bounds__(kBlock) void k_bin(Dev d, Params p) {
-    if (!*d.any) return;  // no box rebuilds this step
+    if (!ld_const(d.any)) return;  // no box rebuilds this step
     const int l = lane_id();
-    for (int w = blockIdx.x * 4 + (threadIdx.x >> 6); w < p.nwave; w += gridDim.x * 4) {
-        const int b = d.wave_box[w];
+    for (int w = blockIdx.x * 4 + wave_in_block(); w < p.nwave; w += gridDim.x * 4) {
+        const int b = ld_const(d.wave_box + w);
         if (!d.st[b].rebuild) continue;  // uniform over the wavefront
         const BoxGeom& g = d.geom[b];
         const int s = w * kWave + l;
@@ -428,7 +438,7 @@ __global__ __launch_bounds__(kBlock) void k_bin(Dev d, Params p) {
 
 // Tile-local exclusive scan of cell counts; tile totals to tile_sum.
 __global__ __launch_bounds__(kBlock) void k_scan_tile(Dev d, Params p) {
-    if (!*d.any) return;  // no box rebuilds this step
+    if (!ld_const(d.any)) return;  // no box rebuilds this step
     for (int t = blockIdx.x; t < p.ntile; t += gridDim.x) {
         if (!d.st[d.tile_box[t]].rebuild) continue;  // uniform over the block
         const size_t base = (size_t)t * kTile + threadIdx.x * 4;
@@ -443,7 +453,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_tile(Dev d, Params p) {
 
 // Per box: exclusive scan over its tiles' totals, offset by the box's first slot.
 __global__ __launch_bounds__(kBlock) void k_scan_box(Dev d, Params p) {
-    if (!*d.any) return;  // no box rebuilds this step
+    if (!ld_const(d.any)) return;  // no box rebuilds this step
     for (int b = blockIdx.x; b < p.nbox; b += gridDim.x) {
         if (!d.st[b].rebuild) continue;
         const BoxGeom& g = d.geom[b];
@@ -460,7 +470,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_box(Dev d, Params p) {
 }
 
 __global__ __launch_bounds__(kBlock) void k_scan_add(Dev d, Params p) {
-    if (!*d.any) return;  // no box rebuilds this step
+    if (!ld_const(d.any)) return;  // no box rebuilds this step
     for (int t = blockIdx.x; t < p.ntile; t += gridDim.x) {
         if (!d.st[d.tile_box[t]].rebuild) continue;
         const int add = d.tile_pref[t];
@@ -472,10 +482,10 @@ __global__ __launch_bounds__(kBlock) void k_scan_add(Dev d, Params p) {
 }
 
 __global__ __launch_bounds__(kBlock) void k_scatter(Dev d, Params p) {
-    if (!*d.any) return;  // no box rebuilds this step
+    if (!ld_const(d.any)) return;  // no box rebuilds this step
     const int l = lane_id();
-    for (int w = blockIdx.x * 4 + (threadIdx.x >> 6); w < p.nwave; w += gridDim.x * 4) {
-        const int b = d.wave_box[w];
+    for (int w = blockIdx.x * 4 + wave_in_block(); w < p.nwave; w += gridDim.x * 4) {
+        const int b = ld_const(d.wave_box + w);
         if (!d.st[b].rebuild) continue;
         const BoxGeom& g = d.geom[b];
         const int s = w * kWave + l;
@@ -491,10 +501,10 @@ __global__ __launch_bounds__(kBlock) void k_scatter(Dev d, Params p) {
 // cell's members is its new slot, and its state is copied there (position record
 // with the new cell, fixed-point record, velocities, caller id).
 __global__ __launch_bounds__(kBlock) void k_rank_permute(Dev d, Params p) {
-    if (!*d.any) return;  // no box rebuilds this step
+    if (!ld_const(d.any)) return;  // no box rebuilds this step
     const int l = lane_id();
-    for (int w = xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6); w < p.nwave; w += gridDim.x * 4) {
-        const int b = d.wave_box[w];
+    for (int w = xcd_block(blockIdx.x, gridDim.x) * 4 + wave_in_block(); w < p.nwave; w += gridDim.x * 4) {
+        const int b = ld_const(d.wave_box + w);
         const BoxState& st = d.st[b];
         if (!st.rebuild) continue;
         const BoxGeom& g = d.geom[b];
@@ -716,7 +726,7 @@ __device__ __forceinline__ void list_pass(const Dev& d, const Params& p, const P
 // against 4 wavefronts per SIMD with 32 KB of staging per block).
 template <int TPK, bool HALF>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_list(Dev d, Params p) {
-    if (!*d.any) return;  // no box rebuilds this step
+    if (!ld_const(d.any)) return;  // no box rebuilds this step
     __shared__ __align__(16) uint16_t stage_all[kBlock / kWave][kStage];
     uint16_t* stage = stage_all[threadIdx.x >> 6];
     const int l = lane_id();
@@ -724,18 +734,23 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) 
     const int cap = p.cap, rows = p.rows;
     // XCD-aware: each XCD sweeps a contiguous run of cells, so the stencil rows a
     // cell loads are still in that XCD's L2 for its neighbours
-    for (int c = xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6); c < ncells; c += gridDim.x * 4) {
+    // the wavefront's index in the block, as a scalar: the cell loop and every per-cell
+    // table read (tile's box, box state and geometry) then stay in scalar registers and
+    // the scalar cache instead of serialised vector loads
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    for (int c = xcd_block(blockIdx.x, gridDim.x) * 4 + wv; c < ncells; c += gridDim.x * 4) {
         const int t = c / kTile;
-        const int b = d.tile_box[t];
+        // tables this kernel does not write, read through the scalar cache
+        const int b = ld_const(d.tile_box + t);
         const BoxState& st = d.st[b];
-        if (!st.rebuild) continue;
+        if (!ld_const(&st.rebuild)) continue;
         const BoxGeom& g = d.geom[b];
-        const int local = c - g.cell_off;
-        if (local >= g.ncell) continue;
-        const int m = __builtin_amdgcn_readfirstlane(d.cell_cnt[c]);
+        const int local = c - ld_const(&g.cell_off);
+        if (local >= ld_const(&g.ncell)) continue;
+        const int m = ld_const(d.cell_cnt + c);
         if (m == 0) continue;
-        const int cs0 = __builtin_amdgcn_readfirstlane(d.cell_start[c]);
-        Pos* __restrict__ q = d.q[__builtin_amdgcn_readfirstlane(st.sq)];
+        const int cs0 = ld_const(d.cell_start + c);
+        Pos* __restrict__ q = d.q[ld_const(&st.sq)];
         const int cx = local % g.n[0], cy = (local / g.n[0]) % g.n[1], cz = local / (g.n[0] * g.n[1]);
         // stencil cell s = lane s < 27: start, count and image term
         int start = 0, cnt = 0;
@@ -1007,11 +1022,11 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Params p) {
     // FP32-mixed: stencil offset o * uoff of stencil cell s, one array per axis: 4-byte
     // words read by stencil index, so lanes spread over the banks (or share a word)
     __shared__ int32_t soff[MIX ? kBlock / kWave : 1][MIX ? 3 * 27 : 1];
-    const int l = lane_id(), wib = threadIdx.x >> 6, sub = l % TPK;
+    const int l = lane_id(), wib = wave_in_block(), sub = l % TPK;
     const int lw = xcd_block(blockIdx.x, gridDim.x) * 4 + wib;
     const int nlw = p.nwave * TPK;
     const bool wave_ok = lw < nlw;
-    const int b = __builtin_amdgcn_readfirstlane(wave_ok ? d.wave_box[(lw * K) >> 6] : 0);
+    const int b = wave_ok ? ld_const(d.wave_box + ((lw * K) >> 6)) : 0;
     if constexpr (!MIX) {
         if (l < 27) {
             const double4 sh = d.dshift[b * 27 + l];
@@ -1629,8 +1644,8 @@ __global__ __launch_bounds__(kBlock) void k_zero_f(Dev d, Params p) {
 template <bool ENERGY>
 __global__ __launch_bounds__(kBlock) void k_kick_close(Dev d, Params p) {
     const int l = lane_id();
-    for (int w = blockIdx.x * 4 + (threadIdx.x >> 6); w < p.nwave; w += gridDim.x * 4) {
-        const int b = d.wave_box[w];
+    for (int w = blockIdx.x * 4 + wave_in_block(); w < p.nwave; w += gridDim.x * 4) {
+        const int b = ld_const(d.wave_box + w);
         const BoxGeom& g = d.geom[b];
         const int s = w * kWave + l;
         const int sp = d.st[b].sp;
@@ -1657,8 +1672,8 @@ __global__ __launch_bounds__(kBlock) void k_kick_close(Dev d, Params p) {
 template <bool CLOSE>
 __global__ __launch_bounds__(kBlock) void k_kick_drift(Dev d, Params p) {
     const int l = lane_id();
-    for (int w = blockIdx.x * 4 + (threadIdx.x >> 6); w < p.nwave; w += gridDim.x * 4) {
-        const int b = d.wave_box[w];
+    for (int w = blockIdx.x * 4 + wave_in_block(); w < p.nwave; w += gridDim.x * 4) {
+        const int b = ld_const(d.wave_box + w);
         const BoxGeom& g = d.geom[b];
         const int s = w * kWave + l;
         const int sq = d.st[b].sq, sp = d.st[b].sp;
@@ -1800,8 +1815,8 @@ __global__ __launch_bounds__(kBlock) void k_energy_reduce(Dev d, Params p, int r
 // reduction reads (a slot wave's sum in its first list wave, zeros in the others).
 __global__ __launch_bounds__(kBlock) void k_ke_partial(Dev d, Params p) {
     const int l = lane_id();
-    for (int w = blockIdx.x * 4 + (threadIdx.x >> 6); w < p.nwave; w += gridDim.x * 4) {
-        const int b = d.wave_box[w];
+    for (int w = blockIdx.x * 4 + wave_in_block(); w < p.nwave; w += gridDim.x * 4) {
+        const int b = ld_const(d.wave_box + w);
         const BoxGeom& g = d.geom[b];
         const int s = w * kWave + l, sp = d.st[b].sp;
         const double k = s - g.slot_off < g.npart ? 0.5 * p.mass * norm2(d.vx[sp][s], d.vy[sp][s], d.vz[sp][s])
@@ -1818,8 +1833,8 @@ __global__ __launch_bounds__(kBlock) void k_ke_partial(Dev d, Params p) {
 // Apply the pending thermostat factor to the velocities (end of a run of steps).
 __global__ __launch_bounds__(kBlock) void k_vscale(Dev d, Params p) {
     const int l = lane_id();
-    for (int w = blockIdx.x * 4 + (threadIdx.x >> 6); w < p.nwave; w += gridDim.x * 4) {
-        const int b = d.wave_box[w];
+    for (int w = blockIdx.x * 4 + wave_in_block(); w < p.nwave; w += gridDim.x * 4) {
+        const int b = ld_const(d.wave_box + w);
         const BoxGeom& g = d.geom[b];
         const int s = w * kWave + l, sp = d.st[b].sp;
         if (s - g.slot_off >= g.npart) continue;
@@ -1834,8 +1849,8 @@ __global__ __launch_bounds__(kBlock) void k_vscale(Dev d, Params p) {
 // key's list lacks.  O(n^2) per box.
 __global__ __launch_bounds__(kBlock) void k_verify(Dev d, Params p) {
     const int l = lane_id();
-    for (int w = blockIdx.x * 4 + (threadIdx.x >> 6); w < p.nwave; w += gridDim.x * 4) {
-        const int b = d.wave_box[w];
+    for (int w = blockIdx.x * 4 + wave_in_block(); w < p.nwave; w += gridDim.x * 4) {
+        const int b = ld_const(d.wave_box + w);
         const BoxGeom& g = d.geom[b];
         const int s = w * kWave + l;
         if (s - g.slot_off >= g.npart) continue;
@@ -1866,8 +1881,8 @@ __global__ __launch_bounds__(kBlock) void k_verify(Dev d, Params p) {
 __global__ __launch_bounds__(kBlock) void k_scale(Dev d, Params p, const double* __restrict__ alpha_q,
                                                   const double* __restrict__ scale_v) {
     const int l = lane_id();
-    for (int w = blockIdx.x * 4 + (threadIdx.x >> 6); w < p.nwave; w += gridDim.x * 4) {
-        const int b = d.wave_box[w];
+    for (int w = blockIdx.x * 4 + wave_in_block(); w < p.nwave; w += gridDim.x * 4) {
+        const int b = ld_const(d.wave_box + w);
         const BoxGeom& g = d.geom[b];
         const int s = w * kWave + l;
         if (s - g.slot_off >= g.npart) continue;
