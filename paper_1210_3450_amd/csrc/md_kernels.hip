@@ -398,13 +398,13 @@ __global__ __launch_bounds__(kBlock) void k_bin(Dev d, Params p) {
     const int l = lane_id();
     for (int w = blockIdx.x * 4 + wave_in_block(); w < p.nwave; w += gridDim.x * 4) {
         const int b = ld_const(d.wave_box + w);
-        if (!d.st[b].rebuild) continue;  // uniform over the wavefront
+        if (!ld_const(&d.st[b].rebuild)) continue;  // uniform over the wavefront
         const BoxGeom& g = d.geom[b];
         const int s = w * kWave + l;
         const bool valid = s - g.slot_off < g.npart;  // the valid lanes are a prefix
         int cid = -1;
         if (valid) {
-            const int sq = d.st[b].sq;
+            const int sq = ld_const(&d.st[b].sq);
             Pos x = d.q[sq][s];
             const double x0 = x.x, y0 = x.y, z0 = x.z;
             bool bad = false;
@@ -486,7 +486,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(Dev d, Params p) {
     const int l = lane_id();
     for (int w = blockIdx.x * 4 + wave_in_block(); w < p.nwave; w += gridDim.x * 4) {
         const int b = ld_const(d.wave_box + w);
-        if (!d.st[b].rebuild) continue;
+        if (!ld_const(&d.st[b].rebuild)) continue;
         const BoxGeom& g = d.geom[b];
         const int s = w * kWave + l;
         if (s - g.slot_off >= g.npart) continue;
@@ -506,11 +506,11 @@ __global__ __launch_bounds__(kBlock) void k_rank_permute(Dev d, Params p) {
     for (int w = xcd_block(blockIdx.x, gridDim.x) * 4 + wave_in_block(); w < p.nwave; w += gridDim.x * 4) {
         const int b = ld_const(d.wave_box + w);
         const BoxState& st = d.st[b];
-        if (!st.rebuild) continue;
+        if (!ld_const(&st.rebuild)) continue;
         const BoxGeom& g = d.geom[b];
         const int s = w * kWave + l;
         if (s - g.slot_off >= g.npart) continue;
-        const int sq = st.sq, sp = st.sp, nq = sq ^ 1, np = sp ^ 1;
+        const int sq = ld_const(&st.sq), sp = ld_const(&st.sp), nq = sq ^ 1, np = sp ^ 1;
         const int32_t* __restrict__ id = d.id[sp];
         const int o = d.perm[s];  // a particle of this cell, in arrival order
         const int key = id[o];
