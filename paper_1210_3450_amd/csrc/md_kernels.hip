@@ -65,6 +65,21 @@ __device__ __forceinline__ int wave_incl_scan(int v) {
     return v;
 }
 
+// Inclusive running maximum over the 64 lanes of non-negative values, by DPP lane
+// moves: shifts by 1, 2, 4, 8 within each row of 16 lanes, then the last lane of
+// each row broadcast into the rows after it.  A lane whose source is outside its
+// row, or whose row the mask leaves out, receives 0, the identity.  Every lane
+// must be active.
+__device__ __forceinline__ int wave_incl_max(int v) {
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false));  // row_shr:1
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false));  // row_shr:2
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false));  // row_shr:4
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false));  // row_shr:8
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false));  // row_bcast:15 into rows 1, 3
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false));  // row_bcast:31 into rows 2, 3
+    return v;
+}
+
 // Exclusive scan across a 256-thread block; *total gets the block sum.
 __device__ int block_excl_scan(int v, int* total) {
     __shared__ int ws[kBlock / kWave];
@@ -606,17 +621,35 @@ typedef const __attribute__((address_space(4))) double const_double;
 // a * cap + (e % TPK) * (cap / TPK) + e / TPK, i.e. already in per-lane chunk
 // order) and leave in whole 16-byte chunks afterwards; otherwise each entry is
 // stored to the list directly.
+// A candidate's stencil cell: each non-empty stencil cell s marks its first
+// candidate with s + 1 in a byte window of the pass (the wavefront's `mark`,
+// G * 64 bytes), and a running maximum over the window, started from the cell
+// that was open at the end of the previous pass (`open`), gives every candidate
+// the last cell starting at or before it.
 constexpr int kStage = 2048;  // LDS list entries per wavefront (16 KB per block: 6 blocks per CU)
+constexpr int kMarkBytes = 6 * kWave;  // candidate window of a pass (G <= 6 chunks)
 
 template <int TPK, bool WRAP, bool STAGED, bool HALF>
 __device__ __forceinline__ void list_pass(const Dev& d, const Params& p, const Pos* __restrict__ q,
                                           const const_double* qc, int cs0, int kb, int mb, int c0, int total,
-                                          int start, int pre, double shx, double shy, double shz, int pre13,
-                                          int& n_own, uint16_t* stage) {
+                                          int start, int pre, int scnt, double shx, double shy, double shz,
+                                          int pre13, int& n_own, int& open, uint16_t* stage, uint8_t* mark) {
     constexpr int G = WRAP ? 3 : 6;
+    static_assert(G * kWave <= kMarkBytes, "mark window");
     const int l = lane_id();
     const double nan = __longlong_as_double(0x7ff8000000000000ll);
     const int nch = min(G, (total - c0 + kWave - 1) >> 6);  // uniform, >= 1
+    // the window's marks: cleared as words, then one byte per cell starting in it
+    uint32_t* mw = reinterpret_cast<uint32_t*>(mark);
+    if (l < G * kWave / 4) mw[l] = 0u;
+    if (G * kWave / 4 > kWave && l < G * kWave / 4 - kWave) mw[kWave + l] = 0u;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (l < 27 && scnt > 0 && pre >= c0 && pre < c0 + G * kWave) mark[pre - c0] = (uint8_t)(l + 1);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     double cx[G], cy[G], cz[G], sx[G], sy[G], sz[G];
     uint32_t ent[G];
 #pragma unroll
@@ -624,12 +657,9 @@ __device__ __forceinline__ void list_pass(const Dev& d, const Params& p, const P
         if (k < nch) {
             const int ci = c0 + k * kWave + l;
             const bool valid = ci < total;
-            int sc = 0;  // last stencil cell whose range starts at or before ci
-            for (int step = 16; step > 0; step >>= 1) {
-                const int tt = sc + step;
-                const int pv = __shfl(pre, tt < 27 ? tt : 26);
-                if (tt < 27 && pv <= ci) sc = tt;
-            }
+            const int run = max(wave_incl_max((int)mark[k * kWave + l]), open);
+            open = __builtin_amdgcn_readlane(run, 63);
+            const int sc = max(run - 1, 0);  // last stencil cell whose range starts at or before ci
             // shuffles run on every lane: a bpermute from an inactive lane reads 0
             const int st_sc = __shfl(start, sc), pre_sc = __shfl(pre, sc);
             ent[k] = (uint32_t)((sc << kOffBits) | ((ci - pre_sc) & (kMaxCellCount - 1)));
@@ -687,15 +717,23 @@ __device__ __forceinline__ void list_pass(const Dev& d, const Params& p, const P
                 const unsigned long long mask =
                     HALF ? __builtin_amdgcn_ballot_w64(in[k] && k * kWave + l > self)
                          : __builtin_amdgcn_ballot_w64(in[k]) & ~(k == sk ? sb : 0ull);
-                const uint32_t pos = __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
-                                                               __builtin_amdgcn_mbcnt_lo((unsigned)mask, (unsigned)cnt));
+                // the lane's place among the accepted lanes; the running count is added
+                // to the (scalar) base address instead where the layout allows
+                const uint32_t rel =
+                    __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
                 unsigned long long sm = mask;
                 if (cnt + __popcll(mask) > cap)  // overflow: keep the entries that fit (rare)
-                    sm = __builtin_amdgcn_ballot_w64(__builtin_amdgcn_inverse_ballot_w64(mask) && pos < (uint32_t)cap);
+                    sm = __builtin_amdgcn_ballot_w64(__builtin_amdgcn_inverse_ballot_w64(mask) &&
+                                                     (int)rel < cap - cnt);  // cnt may exceed cap
                 if (__builtin_amdgcn_inverse_ballot_w64(sm)) {
-                    const uint32_t off = STAGED ? ((pos % TPK) * (uint32_t)(cap / TPK) + pos / TPK) * 2u
-                                                : list_off_bytes<TPK>(pos);
-                    *reinterpret_cast<uint16_t*>(kp + off) = (uint16_t)ent[k];
+                    if constexpr (STAGED && TPK == 1) {
+                        (reinterpret_cast<uint16_t*>(kp) + cnt)[rel] = (uint16_t)ent[k];
+                    } else {
+                        const uint32_t pos = (uint32_t)cnt + rel;
+                        const uint32_t off = STAGED ? ((pos % TPK) * (uint32_t)(cap / TPK) + pos / TPK) * 2u
+                                                    : list_off_bytes<TPK>(pos);
+                        *reinterpret_cast<uint16_t*>(kp + off) = (uint16_t)ent[k];
+                    }
                 }
                 cnt += __popcll(mask);
             }
@@ -728,7 +766,7 @@ template <int TPK, bool HALF>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_list(Dev d, Params p) {
     if (!ld_const(d.any)) return;  // no box rebuilds this step
     __shared__ __align__(16) uint16_t stage_all[kBlock / kWave][kStage];
-    uint16_t* stage = stage_all[threadIdx.x >> 6];
+    __shared__ __align__(16) uint8_t mark_all[kBlock / kWave][kMarkBytes];
     const int l = lane_id();
     const int ncells = p.ntile * kTile;
     const int cap = p.cap, rows = p.rows;
@@ -736,8 +774,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) 
     // cell loads are still in that XCD's L2 for its neighbours
     // the wavefront's index in the block, as a scalar: the cell loop and every per-cell
     // table read (tile's box, box state and geometry) then stay in scalar registers and
-    // the scalar cache instead of serialised vector loads
+    // the scalar cache instead of serialised vector loads; the staging buffer's base
+    // is scalar too
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    uint16_t* stage = stage_all[wv];
+    uint8_t* mark = mark_all[wv];
     for (int c = xcd_block(blockIdx.x, gridDim.x) * 4 + wv; c < ncells; c += gridDim.x * 4) {
         const int t = c / kTile;
         // tables this kernel does not write, read through the scalar cache
@@ -783,14 +824,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) 
             int n_own = 0;  // lane a: partners of key kb + a so far
             const bool staged = mb * cap <= kStage;  // uniform
             if (staged) {
+                int open = 0;  // no stencil cell open before the first candidate
                 if (wrap) {
                     for (int c0 = 0; c0 < total; c0 += 3 * kWave)
-                        list_pass<TPK, true, true, HALF>(d, p, q, qc, cs0, kb, mb, c0, total, start, pre, shx, shy,
-                                                         shz, pre13, n_own, stage);
+                        list_pass<TPK, true, true, HALF>(d, p, q, qc, cs0, kb, mb, c0, total, start, pre, cnt, shx,
+                                                         shy, shz, pre13, n_own, open, stage, mark);
                 } else {
                     for (int c0 = 0; c0 < total; c0 += 6 * kWave)
-                        list_pass<TPK, false, true, HALF>(d, p, q, qc, cs0, kb, mb, c0, total, start, pre, shx, shy,
-                                                          shz, pre13, n_own, stage);
+                        list_pass<TPK, false, true, HALF>(d, p, q, qc, cs0, kb, mb, c0, total, start, pre, cnt, shx,
+                                                          shy, shz, pre13, n_own, open, stage, mark);
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
@@ -814,13 +856,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) 
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             } else if (wrap) {
+                int open = 0;
                 for (int c0 = 0; c0 < total; c0 += 3 * kWave)
-                    list_pass<TPK, true, false, HALF>(d, p, q, qc, cs0, kb, mb, c0, total, start, pre, shx, shy, shz,
-                                                      pre13, n_own, stage);
+                    list_pass<TPK, true, false, HALF>(d, p, q, qc, cs0, kb, mb, c0, total, start, pre, cnt, shx, shy,
+                                                      shz, pre13, n_own, open, stage, mark);
             } else {
+                int open = 0;
                 for (int c0 = 0; c0 < total; c0 += 6 * kWave)
-                    list_pass<TPK, false, false, HALF>(d, p, q, qc, cs0, kb, mb, c0, total, start, pre, shx, shy,
-                                                       shz, pre13, n_own, stage);
+                    list_pass<TPK, false, false, HALF>(d, p, q, qc, cs0, kb, mb, c0, total, start, pre, cnt, shx,
+                                                       shy, shz, pre13, n_own, open, stage, mark);
             }
             if (l < mb) {
                 const int nk = n_own < cap ? n_own : cap;
