@@ -78,6 +78,12 @@ def case(name):
         q[80:100, 0] = q[80:100, 0] + L          # one box up
         q[100:120, 1] = q[100:120, 1] - L        # one box down
         return q, inputs.maxwell_boltzmann(600, 1.0, 1.0, rng(3)), L
+    if name == "dense07":  # rho = 0.7: about 500 candidates per cell, so interior cells
+        # (6 per axis) take two candidate passes, with and without LDS staging
+        a = (4.0 / 0.7) ** (1.0 / 3.0)
+        L = 10 * a
+        q = inputs.jittered(inputs.fcc_positions(10, a), 0.15, L, rng(11))
+        return q, inputs.maxwell_boltzmann(q.shape[0], 1.0, 1.0, rng(12)), L
     if name == "minimal":  # 3 cells per axis, two particles through the boundary
         L = 8.4
         q = np.array([[0.2, 4.0, 4.0], [8.1, 4.2, 3.9]])
@@ -85,7 +91,7 @@ def case(name):
     raise KeyError(name)
 
 
-CASES = ["fcc4000", "jitter_ragged", "clustered", "edges", "minimal"]
+CASES = ["fcc4000", "jitter_ragged", "clustered", "edges", "minimal", "dense07"]
 
 
 def oracle_state(q, L, rl=2.8):
