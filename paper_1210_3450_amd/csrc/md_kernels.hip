@@ -80,6 +80,18 @@ __device__ __forceinline__ int wave_incl_max(int v) {
     return v;
 }
 
+// Inclusive sum over the 64 lanes by the same DPP lane moves (0 is the identity).
+// Every lane must be active.
+__device__ __forceinline__ int wave_incl_sum(int v) {
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);
+    return v;
+}
+
 // Exclusive scan across a 256-thread block; *total gets the block sum.
 __device__ int block_excl_scan(int v, int* total) {
     __shared__ int ws[kBlock / kWave];
@@ -650,6 +662,7 @@ __device__ __forceinline__ void list_pass(const Dev& d, const Params& p, const P
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int sbase = start - pre;  // stencil cell s: slot of its candidate ci is sbase + ci
     double cx[G], cy[G], cz[G], sx[G], sy[G], sz[G];
     uint32_t ent[G];
 #pragma unroll
@@ -661,9 +674,11 @@ __device__ __forceinline__ void list_pass(const Dev& d, const Params& p, const P
             open = __builtin_amdgcn_readlane(run, 63);
             const int sc = max(run - 1, 0);  // last stencil cell whose range starts at or before ci
             // shuffles run on every lane: a bpermute from an inactive lane reads 0
-            const int st_sc = __shfl(start, sc), pre_sc = __shfl(pre, sc);
+            const int base_sc = __shfl(sbase, sc), pre_sc = __shfl(pre, sc);
             ent[k] = (uint32_t)((sc << kOffBits) | ((ci - pre_sc) & (kMaxCellCount - 1)));
-            const Pos qj = q[valid ? st_sc + ci - pre_sc : cs0];
+            // 32-bit byte offset from the (scalar) array base: slots stay below 2^27
+            const uint32_t boff = (uint32_t)(valid ? base_sc + ci : cs0) * (uint32_t)sizeof(Pos);
+            const Pos qj = *reinterpret_cast<const Pos*>(reinterpret_cast<const char*>(q) + boff);
             cx[k] = valid ? qj.x : nan;  // NaN distance: never accepted
             cy[k] = qj.y;
             cz[k] = qj.z;
@@ -813,7 +828,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) 
             if (HALF && l < 13) cnt = 0;
         }
         const bool wrap = __ballot(img) != 0ull;  // uniform: this cell touches the box boundary
-        const int incl = wave_incl_scan(cnt);
+        const int incl = wave_incl_sum(cnt);
         const int pre = incl - cnt;
         const int total = __builtin_amdgcn_readlane(incl, 26);
         const int pre13 = __builtin_amdgcn_readlane(pre, 13);  // the home cell's first candidate
@@ -840,10 +855,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) 
                 // write-out: item (a, t, c) = chunk c of key a's lane t, 16 bytes; lanes
                 // of consecutive keys write consecutive chunks of the list
                 const int cpt = cap / TPK / 8;  // chunks per key lane in the buffer
-                const int nitem = mb * TPK * cpt;
+                const int nitem = mb * TPK * cpt;  // <= kStage / 8 (staged)
+                // it / (mb * TPK) in FP32: (it + 1/2) / dv lies at least 1/(2 dv) from an
+                // integer, far above the rounding error for it < 2^12, dv <= 2^9
+                const int dv = mb * TPK;
+                const float rdv = 1.0f / (float)dv;
                 for (int i0 = 0; i0 < nitem; i0 += kWave) {  // same trip count on every lane
                     const int it = i0 + l;
-                    const int c = it / (mb * TPK), at = it - c * (mb * TPK);
+                    const int c = (int)(((float)it + 0.5f) * rdv), at = it - c * dv;
                     const int a = at / TPK, t = at - a * TPK;
                     const int na = __shfl(n_own, a & 63);  // every lane takes part in the shuffle
                     const int nlane = na > t ? (na - t + TPK - 1) / TPK : 0;
@@ -871,7 +890,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) 
                 d.cnt[cs0 + kb + l] = nk;
                 q[cs0 + kb + l].cnt = nk;
             }
-            need = max(need, wave_max_i(l < mb ? n_own : 0));
+            need = max(need, __builtin_amdgcn_readlane(wave_incl_max(l < mb ? n_own : 0), 63));
         }
         if (l == 0) atomicMax(&d.tile_need[t], need);
     }
