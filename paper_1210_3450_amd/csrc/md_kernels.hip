@@ -638,7 +638,7 @@ typedef const __attribute__((address_space(4))) double const_double;
 // G * 64 bytes), and a running maximum over the window, started from the cell
 // that was open at the end of the previous pass (`open`), gives every candidate
 // the last cell starting at or before it.
-constexpr int kStage = 2048;  // LDS list entries per wavefront (16 KB per block: 6 blocks per CU)
+constexpr int kStage = 2048;  // LDS list entries per wavefront (16 KB per block, 17.5 KB with the marks: 7 blocks per CU)
 constexpr int kMarkBytes = 6 * kWave;  // candidate window of a pass (G <= 6 chunks)
 
 template <int TPK, bool WRAP, bool STAGED, bool HALF>
@@ -773,12 +773,14 @@ __device__ __forceinline__ void list_pass(const Dev& d, const Params& p, const P
     }
 }
 
-// Six wavefronts per SIMD (at most 80 VGPRs, a few spilled): the build is bound by
+// Seven wavefronts per SIMD (at most 72 VGPRs, no vector spills in the full-list
+// build): the build issues about as many scalar as vector instructions and is bound by
 // the latency of its scalar-vector chain per (key, chunk), which more resident
-// wavefronts hide (measured: 13.2 -> 11.5 ms per rebuild chain at 32M particles,
-// against 4 wavefronts per SIMD with 32 KB of staging per block).
+// wavefronts hide (measured at 32M particles, rebuild chain per rebuild: 4 wavefronts
+// 13.2 ms, 6 wavefronts 11.5 ms in an earlier form; 6 -> 7 -> 8 wavefronts now
+// 9.36 -> 9.08 -> 9.19 ms, the last with spills).
 template <int TPK, bool HALF>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_list(Dev d, Params p) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7, 8))) void k_list(Dev d, Params p) {
     if (!ld_const(d.any)) return;  // no box rebuilds this step
     __shared__ __align__(16) uint16_t stage_all[kBlock / kWave][kStage];
     __shared__ __align__(16) uint8_t mark_all[kBlock / kWave][kMarkBytes];
