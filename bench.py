@@ -416,7 +416,7 @@ def main():
                     help="first run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: the path has no multi-GPU form in this build "
+        print("bench.py measures one GPU: the path has no multi-GPU form "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
