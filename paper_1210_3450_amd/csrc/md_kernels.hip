@@ -35,6 +35,20 @@ __device__ __forceinline__ int ld_const(const int32_t* p) {
         reinterpret_cast<uintptr_t>(p));
 }
 
+// A box's geometry, read through the scalar cache: no kernel writes it, so the
+// wavefront-uniform reads become scalar loads instead of a chain of vector loads
+// that every store in a loop would force to repeat.
+__device__ __forceinline__ BoxGeom ld_geom(const BoxGeom* p) {
+    static_assert(sizeof(BoxGeom) % 4 == 0, "BoxGeom is copied as 32-bit words");
+    const __attribute__((address_space(4))) int32_t* src =
+        reinterpret_cast<const __attribute__((address_space(4))) int32_t*>(reinterpret_cast<uintptr_t>(p));
+    BoxGeom g;
+    int32_t* dst = reinterpret_cast<int32_t*>(&g);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(BoxGeom) / 4); ++i) dst[i] = src[i];  // unused words are never loaded
+    return g;
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs (block b runs on XCD
 // b % 8).  Give XCD x a contiguous run of logical blocks so that neighbouring
 // keys, whose partners overlap, share that XCD's L2.  Bijective on [0, nb).
@@ -426,7 +440,7 @@ __global__ __launch_bounds__(kBlock) void k_bin(Dev d, Params p) {
     for (int w = blockIdx.x * 4 + wave_in_block(); w < p.nwave; w += gridDim.x * 4) {
         const int b = ld_const(d.wave_box + w);
         if (!ld_const(&d.st[b].rebuild)) continue;  // uniform over the wavefront
-        const BoxGeom& g = d.geom[b];
+        const BoxGeom g = ld_geom(d.geom + b);
         const int s = w * kWave + l;
         const bool valid = s - g.slot_off < g.npart;  // the valid lanes are a prefix
         int cid = -1;
@@ -514,7 +528,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(Dev d, Params p) {
     for (int w = blockIdx.x * 4 + wave_in_block(); w < p.nwave; w += gridDim.x * 4) {
         const int b = ld_const(d.wave_box + w);
         if (!ld_const(&d.st[b].rebuild)) continue;
-        const BoxGeom& g = d.geom[b];
+        const BoxGeom g = ld_geom(d.geom + b);
         const int s = w * kWave + l;
         if (s - g.slot_off >= g.npart) continue;
         d.perm[d.cell_start[g.cell_off + d.cell_tmp[s]] + d.ticket[s]] = s;
@@ -534,7 +548,7 @@ __global__ __launch_bounds__(kBlock) void k_rank_permute(Dev d, Params p) {
         const int b = ld_const(d.wave_box + w);
         const BoxState& st = d.st[b];
         if (!ld_const(&st.rebuild)) continue;
-        const BoxGeom& g = d.geom[b];
+        const BoxGeom g = ld_geom(d.geom + b);
         const int s = w * kWave + l;
         if (s - g.slot_off >= g.npart) continue;
         const int sq = ld_const(&st.sq), sp = ld_const(&st.sp), nq = sq ^ 1, np = sp ^ 1;
@@ -802,9 +816,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7, 8))) 
         const int b = ld_const(d.tile_box + t);
         const BoxState& st = d.st[b];
         if (!ld_const(&st.rebuild)) continue;
-        const BoxGeom& g = d.geom[b];
-        const int local = c - ld_const(&g.cell_off);
-        if (local >= ld_const(&g.ncell)) continue;
+        const BoxGeom g = ld_geom(d.geom + b);
+        const int local = c - g.cell_off;
+        if (local >= g.ncell) continue;
         const int m = ld_const(d.cell_cnt + c);
         if (m == 0) continue;
         const int cs0 = ld_const(d.cell_start + c);
