@@ -30,6 +30,17 @@ __device__ __forceinline__ int wave_in_block() { return __builtin_amdgcn_readfir
 
 // A wave-uniform read of a value the running kernel does not write, through the
 // constant address space, so it becomes a scalar load (scalar cache).
+// Streaming accesses of the force pass (list chunks, velocities): each byte is used
+// once per pass, so they carry the non-temporal hint and leave the L2 to the partner
+// records that neighbouring wavefronts gather again.
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ uint4 ld_stream(const uint4* p) {
+    const u32x4_t v = __builtin_nontemporal_load(reinterpret_cast<const u32x4_t*>(p));
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ double ld_stream(const double* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ void st_stream(double* p, double v) { __builtin_nontemporal_store(v, p); }
+
 __device__ __forceinline__ int ld_const(const int32_t* p) {
     return *reinterpret_cast<const __attribute__((address_space(4))) int32_t*>(
         reinterpret_cast<uintptr_t>(p));
@@ -1012,12 +1023,12 @@ __device__ __forceinline__ void force_finish(const Dev& d, const Params& p, cons
         }
     } else {  // kForceMid
         if (owner) {
-            double vx = kick(kick(d.vx[sp][key], p.h, Fx), p.h, Fx);
-            double vy = kick(kick(d.vy[sp][key], p.h, Fy), p.h, Fy);
-            double vz = kick(kick(d.vz[sp][key], p.h, Fz), p.h, Fz);
-            d.vx[sp][key] = vx;
-            d.vy[sp][key] = vy;
-            d.vz[sp][key] = vz;
+            double vx = kick(kick(ld_stream(d.vx[sp] + key), p.h, Fx), p.h, Fx);
+            double vy = kick(kick(ld_stream(d.vy[sp] + key), p.h, Fy), p.h, Fy);
+            double vz = kick(kick(ld_stream(d.vz[sp] + key), p.h, Fz), p.h, Fz);
+            st_stream(d.vx[sp] + key, vx);
+            st_stream(d.vy[sp] + key, vy);
+            st_stream(d.vz[sp] + key, vz);
             const Pos xn = make_pos(drift(qi.x, p.dt, vx), drift(qi.y, p.dt, vy), drift(qi.z, p.dt, vz), qi.cc,
                                     qi.cnt);
             d.q[sq ^ 1][key] = xn;
@@ -1246,7 +1257,7 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Params p) {
             const uint32_t w = k < 2 ? raw.x : k < 4 ? raw.y : k < 6 ? raw.z : raw.w;
             return (k & 1) ? (w >> 16) & (kMaxCellCount - 1) : w & (kMaxCellCount - 1);
         };
-        uint4 raw_next = nl > 0 ? l4[0] : make_uint4(0u, 0u, 0u, 0u);
+        uint4 raw_next = nl > 0 ? ld_stream(l4) : make_uint4(0u, 0u, 0u, 0u);
         if constexpr (!MIX) {
             const Pos* __restrict__ q = d.q[sq];
             const double rc2 = p.rc2, c2x8 = 8.0 * p.c2;
@@ -1269,7 +1280,7 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Params p) {
                     qj[k] = *reinterpret_cast<const Pos*>(reinterpret_cast<const char*>(q) + (js[k] << 5));
                 // next chunk's entries, issued after the gathers: the load counter
                 // retires in order, so this load does not delay them
-                if (!CHK && (c + 1 < nfull || ntail)) raw_next = l4[(size_t)(c + 1) * kWave];
+                if (!CHK && (c + 1 < nfull || ntail)) raw_next = ld_stream(l4 + (size_t)(c + 1) * kWave);
 #pragma unroll
                 for (int k = 0; k < U; ++k) {
                     const double* __restrict__ sh = shift[wib] + img[k];
@@ -1340,7 +1351,7 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Params p) {
                     const U3 t = *reinterpret_cast<const U3*>(reinterpret_cast<const char*>(u) + js[k] * 12u);
                     uj[k] = make_int4(t.x, t.y, t.z, 0);
                 }
-                if (!CHK && (c + 1 < nfull || ntail)) raw_next = l4[(size_t)(c + 1) * kWave];
+                if (!CHK && (c + 1 < nfull || ntail)) raw_next = ld_stream(l4 + (size_t)(c + 1) * kWave);
                 // the stencil offsets are read again below rather than held across the gathers
                 __builtin_amdgcn_sched_barrier(0);
                 float bx = 0.f, by = 0.f, bz = 0.f;  // plain FP32 sum of this batch
@@ -1619,7 +1630,7 @@ __global__ __launch_bounds__(kBlock) void k_force_tile(Dev d, Params p) {
         const int4 ui = units3(qi, cc, g);
         const float rc2u = g.rc2u, lam2inv = g.lam2inv, lam2 = g.lam * g.lam, c2x8 = 8.0f * p.c2f;
         float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f, pes = 0.f, virs = 0.f;
-        uint4 raw_next = nl > 0 ? l4[0] : make_uint4(0u, 0u, 0u, 0u);
+        uint4 raw_next = nl > 0 ? ld_stream(l4) : make_uint4(0u, 0u, 0u, 0u);
         // one chunk of 8 entries: fetch the 8 partners, then the pair math on exact
         // integer separations (one rounding to FP32 each)
         auto pairs = [&](auto tile_c) {
@@ -1640,7 +1651,7 @@ __global__ __launch_bounds__(kBlock) void k_force_tile(Dev d, Params p) {
                         const bool ok = !CHK || k < valid;
                         li[k] = (int)tb[ok ? ent_s(raw, k) : 13u] + (ok ? (int)ent_r(raw, k) : 0);
                     }
-                    if (!CHK && (c + 1 < nfull || ntail)) raw_next = l4[(size_t)(c + 1) * kWave];
+                    if (!CHK && (c + 1 < nfull || ntail)) raw_next = ld_stream(l4 + (size_t)(c + 1) * kWave);
 #pragma unroll
                     for (int k = 0; k < U; ++k) {
                         dxi[k] = (int)((uint32_t)tx[li[k]] - kx);
@@ -1659,7 +1670,7 @@ __global__ __launch_bounds__(kBlock) void k_force_tile(Dev d, Params p) {
                     int4 uj[U];
 #pragma unroll
                     for (int k = 0; k < U; ++k) uj[k] = get_u(u, js[k]);
-                    if (!CHK && (c + 1 < nfull || ntail)) raw_next = l4[(size_t)(c + 1) * kWave];
+                    if (!CHK && (c + 1 < nfull || ntail)) raw_next = ld_stream(l4 + (size_t)(c + 1) * kWave);
 #pragma unroll
                     for (int k = 0; k < U; ++k) {
                         const int so = (int)st[k];
