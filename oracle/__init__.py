@@ -106,8 +106,6 @@ def lib():
         L.orc_run.argtypes = [C.c_int64, P_D, P_D, P_D, P_D, C.POINTER(OrcParams), C.c_int64,
                               C.c_int64, P_D, P_D, C.POINTER(OrcStats), C.c_int32]
         L.orc_run.restype = C.c_int
-        L.orc_initial_forces.argtypes = [C.c_int64, P_D, P_D, C.POINTER(OrcParams), P_D]
-        L.orc_initial_forces.restype = C.c_double
         L.orc_bubbles.argtypes = [C.c_int64, P_D, P_D, C.c_double, C.c_double, C.POINTER(C.c_uint8), P_I32]
         L.orc_bubbles.restype = C.c_int64
         L.orc_subcell_grid.argtypes = [P_D, C.c_double, P_I32, P_D, P_D, C.c_double]
@@ -355,15 +353,6 @@ def run_obs(q, v, L, nsteps, rc=2.5, skin=0.3, dt=0.005, mass=1.0, mode=CUT_EQ1,
     if rcode != 0:
         raise ValueError("orc_run_obs failed with code %d" % rcode)
     return ObsResult(q, v, F, ke[:ns], pe[:ns], vir[:ns], tho[:ns], th.xi, th.eta, st.steps, st.rebuilds)
-
-
-def initial_forces(q, L, rc=2.5, skin=0.3, mode=CUT_EQ1):
-    q = _q(q)
-    Lb = _box(L)
-    F = np.zeros((q.shape[0], 3))
-    p = OrcParams(rc, skin, 0.005, 1.0, mode, REBUILD_DUTC, 0, 0)
-    pe = lib().orc_initial_forces(q.shape[0], _pd(q), _pd(Lb), C.byref(p), _pd(F))
-    return q, F, pe
 
 
 def csr_sets(kp, pl):

@@ -639,23 +639,6 @@ int orc_run(int64_t n, double *q, double *v, double *F, const double *L, const o
     return orc_run_obs(n, q, v, F, L, p, NULL, nsteps, energy_every, ke_out, pe_out, NULL, NULL, stats, F_valid);
 }
 
-/* Initial list and forces only (no step): wraps q, builds, fills F, returns PE. */
-double orc_initial_forces(int64_t n, double *q, const double *L, const orc_params *p, double *F) {
-    orc_sys s;
-    memset(&s, 0, sizeof(s));
-    s.n = n; s.q = q; s.F = F;
-    memcpy(s.L, L, sizeof(double) * 3);
-    orc_coeffs(p->rc, p->cutoff, &s.c2, &s.c0);
-    s.qb = (double *)malloc(sizeof(double) * 3 * (size_t)n);
-    s.kp = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1));
-    s.cap = 64 * n + 64;
-    s.pl = (int32_t *)malloc(sizeof(int32_t) * (size_t)s.cap);
-    double pe = NAN;
-    if (sys_build(&s, p) == 0) pe = orc_forces_list(n, q, s.L, p->rc, s.c2, s.c0, s.kp, s.pl, F, NULL, NULL);
-    free(s.qb); free(s.kp); free(s.pl);
-    return pe;
-}
-
 /* ------------------------------------------------------------------ bubbles
  *
  * Bubble identification of Sec. IV.B.  The box is cut into subcells of edge

@@ -292,6 +292,7 @@ md_status alloc_cells(md_ctx* c) {
     dfree(c->D.cell_start);
     dfree(c->D.tile_sum);
     dfree(c->D.tile_pref);
+    dfree(c->D.tile_need);
     md_status s;
     if ((s = dalloc(c, &c->D.tile_box, c->ntile)) != MD_OK) return s;
     if ((s = dalloc(c, &c->D.cell_cnt, (size_t)c->ntile * kTile)) != MD_OK) return s;
