@@ -270,6 +270,20 @@ md_status md_bubbles(md_ctx *ctx, int32_t box, double side, double rho_gas, uint
                      int32_t *labels, int64_t *roots, int64_t *sizes, int64_t cap,
                      md_bubble_info *info);
 
+/* The same analysis for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * arguments, results, errors and ordering exactly as md_bubbles, but every work
+ * buffer lives in a fixed device array of the library (about 32 MiB per GPU,
+ * taken when the library's code is loaded on that GPU and held until the
+ * process ends), so the call performs no device allocation or free.  Limit:
+ * at most 2^20 subcells per call (MD_EINVAL beyond).  All calls on one GPU
+ * share that array and each call clears what it needs first; calls that
+ * overlap in time on one GPU (several threads, or several streams) race and
+ * must be serialised by the caller.  Synchronizing. */
+md_status md_bubbles_noalloc(md_ctx *ctx, int32_t box, double side, double rho_gas, uint8_t *counts,
+                             int32_t *labels, int64_t *roots, int64_t *sizes, int64_t cap,
+                             md_bubble_info *info);
+
 /* ---- diagnostics and parity (synchronizing) ----------------------------- */
 
 /* Cell of every particle at the last binning, box-local linear id

@@ -84,6 +84,8 @@ _SIGS = {
     "md_get_thermostat": (_S, [_P, _PD, _PD]),
     "md_bubbles": (_S, [_P, C.c_int32, C.c_double, C.c_double, _P, _P, _PI64, _PI64, C.c_int64,
                         C.POINTER(md_bubble_info)]),
+    "md_bubbles_noalloc": (_S, [_P, C.c_int32, C.c_double, C.c_double, _P, _P, _PI64, _PI64, C.c_int64,
+                                C.POINTER(md_bubble_info)]),
     "md_get_cells": (_S, [_P, _P, _PI32]),
     "md_get_neighbors": (_S, [_P, _P, _P, C.c_int64, _PI64]),
     "md_get_stats": (_S, [_P, C.POINTER(md_stats)]),
@@ -270,12 +272,14 @@ class Context:
         return xi, eta
 
     # ---- bubble analysis
-    def bubbles(self, box=0, side=3.0, rho_gas=0.2, fields=True, cap=None):
-        """Bubbles of one box (md_bubbles).  Returns a dict: nsub (nx, ny, nz), side,
-        threshold, ngas, nbubbles, largest, roots and sizes (numpy int64, ascending
-        roots; all bubbles unless cap is given) and, with fields=True, the byte
-        counts and labels per subcell as device tensors (uint8, int32)."""
+    def bubbles(self, box=0, side=3.0, rho_gas=0.2, fields=True, cap=None, noalloc=False):
+        """Bubbles of one box (md_bubbles, or md_bubbles_noalloc with noalloc=True).
+        Returns a dict: nsub (nx, ny, nz), side, threshold, ngas, nbubbles, largest,
+        roots and sizes (numpy int64, ascending roots; all bubbles unless cap is
+        given) and, with fields=True, the byte counts and labels per subcell as
+        device tensors (uint8, int32)."""
         import torch
+        md_bubbles = md_bubbles_noalloc if noalloc else globals()["md_bubbles"]
         info = md_bubble_info()
         counts = labels = None
         torch.cuda.synchronize(self.device)

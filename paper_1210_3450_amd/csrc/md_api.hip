@@ -676,6 +676,14 @@ md_status create_impl(const md_params* boxes, int32_t nbox, void* stream, md_ctx
         delete c;
         return MD_EHIP;
     }
+    // the fixed scratch of md_bubbles_noalloc: its device address on this device,
+    // taken once per device while the device is current
+    he = bubbles_scratch_init(c->device);
+    if (he != hipSuccess) {
+        g_create_err = std::string("hipGetSymbolAddress (bubble scratch): ") + hipGetErrorString(he);
+        delete c;
+        return MD_EHIP;
+    }
     if (stream) {
         c->stream = (hipStream_t)stream;
     } else {
@@ -1113,6 +1121,66 @@ md_status md_bubbles(md_ctx* c, int32_t box, double side, double rho_gas, uint8_
     info->ngas = ngas;
     info->nbubbles = (int64_t)rs.size();
     info->largest = largest;
+    return MD_OK;
+}
+
+md_status md_bubbles_noalloc(md_ctx* c, int32_t box, double side, double rho_gas, uint8_t* counts, int32_t* labels,
+                             int64_t* roots, int64_t* sizes, int64_t cap, md_bubble_info* info) {
+    md_status s;
+    if ((s = check_ctx(c)) != MD_OK) return s;
+    if (!info) return fail(c, MD_EINVAL, "info must not be NULL");
+    if (box < 0 || box >= c->nbox) return fail(c, MD_EINVAL, "box %d out of range [0, %d)", box, c->nbox);
+    if (!finite_pos(side)) return fail(c, MD_EINVAL, "side must be finite and > 0");
+    if (!(rho_gas >= 0.0) || !std::isfinite(rho_gas)) return fail(c, MD_EINVAL, "rho_gas must be finite and >= 0");
+    if (cap < 0 || (cap > 0 && (!roots || !sizes))) return fail(c, MD_EINVAL, "roots and sizes need cap entries");
+    if (!c->have_state) return fail(c, MD_ESTATE, "no state: call md_set_state first");
+    unsigned char* base = bubbles_scratch(c->device);
+    if (!base) return fail(c, MD_EHIP, "no fixed bubble scratch on device %d", c->device);
+    SubGrid sg{};
+    const double* L = c->boxes[box].box;
+    int64_t nsub = 1;
+    for (int a = 0; a < 3; ++a) {
+        const double n = std::floor(L[a] / side);
+        if (n < 1.0 || n > 1024.0)
+            return fail(c, MD_EINVAL, "floor(L / side) = %.0f on axis %d: need 1..1024 subcells", n, a);
+        sg.L[a] = L[a];
+        sg.n[a] = (int32_t)n;
+        sg.inv[a] = (double)sg.n[a] / L[a];
+        nsub *= sg.n[a];
+    }
+    if (nsub > kNaMaxSub)
+        return fail(c, MD_EINVAL, "%lld subcells exceed the fixed scratch of md_bubbles_noalloc (%d subcells)",
+                    (long long)nsub, kNaMaxSub);
+    const double vol = (L[0] / sg.n[0]) * (L[1] / sg.n[1]) * (L[2] / sg.n[2]);
+    sg.thr = rho_gas * vol;
+    sg.nsub = (int32_t)nsub;
+    launch_bubbles_scratch(c->D, box, c->geom[box].npart, sg, base, counts, c->stream);
+    LAUNCHCHK(c);
+    int64_t *d_root, *d_rsize;
+    int32_t* d_lab;
+    NaMisc* d_misc;
+    bubbles_scratch_results(base, &d_root, &d_rsize, &d_lab, &d_misc);
+    if (labels)
+        HIPCHK(c, hipMemcpyAsync(labels, d_lab, sizeof(int32_t) * nsub, hipMemcpyDeviceToDevice, c->stream));
+    NaMisc m{};
+    HIPCHK(c, hipMemcpyAsync(&m, d_misc, sizeof m, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (m.bad) return fail(c, MD_ENUMERIC, "box %d: a position is not finite or lies outside [-L, 2L)", box);
+    const int64_t k = std::min<int64_t>(cap, m.nroots);
+    if (k > 0) {
+        HIPCHK(c, hipMemcpyAsync(roots, d_root, sizeof(int64_t) * k, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipMemcpyAsync(sizes, d_rsize, sizeof(int64_t) * k, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    *info = md_bubble_info{};
+    for (int a = 0; a < 3; ++a) {
+        info->nsub[a] = sg.n[a];
+        info->side[a] = L[a] / sg.n[a];
+    }
+    info->threshold = sg.thr;
+    info->ngas = (int64_t)m.ngas;
+    info->nbubbles = m.nroots;
+    info->largest = m.largest;
     return MD_OK;
 }
 

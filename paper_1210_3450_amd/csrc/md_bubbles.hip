@@ -16,12 +16,19 @@
 //   k_sub_label  label = root (path halving on the way), sizes by atomics
 //   k_sub_roots  compacts (root, size) pairs; the host sorts them by root
 //
+// md_bubbles_noalloc runs the same count / flag / hook / label kernels on a
+// fixed device array instead of allocated buffers and replaces the last step by
+// an ordered compaction (root counts per segment, one-block scan, write-out in
+// subcell order), so the bubbles arrive sorted without a host-side buffer.
+//
 // Union-find on the GPU after the published lock-free scheme of linking a root
 // to a smaller root with compare-and-swap and compressing paths with plain
 // ancestor stores (connected components as in ECL-CC, Jaiganesh and Burtscher,
 // HPDC 2018).  Every parent pointer only ever moves to an ancestor, so every
 // loop terminates: finds follow strictly decreasing indices, and each failed
 // compare-and-swap means another thread's link succeeded.
+#include <mutex>
+
 #include "md.h"
 #include "md_internal.h"
 
@@ -131,6 +138,165 @@ __global__ __launch_bounds__(kBlock) void k_sub_roots(SubGrid sg, const int32_t*
     }
 }
 
+// ---------------------------------------------------------------- fixed scratch
+//
+// The allocation-free variant (md_bubbles_noalloc) keeps every work buffer in one
+// file-scope device array.  In host code `scratch` is only a host-side stand-in:
+// its device address is taken once per device with hipGetSymbolAddress
+// (bubbles_scratch_init) and only that address is ever handed to kernels.
+// Layout (kNaMaxSub subcells): cnt u32, par i32, lab i32, size i32, root i64,
+// rsize i64 per subcell, then the per-segment root counts and offsets of the
+// ordered compaction, then the status words.
+constexpr size_t kNaCnt = 0;
+constexpr size_t kNaPar = kNaCnt + 4 * (size_t)kNaMaxSub;
+constexpr size_t kNaLab = kNaPar + 4 * (size_t)kNaMaxSub;
+constexpr size_t kNaSize = kNaLab + 4 * (size_t)kNaMaxSub;
+constexpr size_t kNaRoot = kNaSize + 4 * (size_t)kNaMaxSub;
+constexpr size_t kNaRsize = kNaRoot + 8 * (size_t)kNaMaxSub;
+constexpr size_t kNaSegCnt = kNaRsize + 8 * (size_t)kNaMaxSub;
+constexpr size_t kNaSegOff = kNaSegCnt + 4 * (size_t)kNaSegs;
+constexpr size_t kNaMisc = kNaSegOff + 4 * (size_t)kNaSegs;
+constexpr size_t kNaBytes = kNaMisc + sizeof(NaMisc);
+static_assert(kNaMaxSub % kNaSeg == 0, "whole segments");
+static_assert(kNaSegs <= kBlock * 4, "one block scans the segment counts");
+
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_na_mu;
+unsigned char* g_na_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t bubbles_scratch_init(int device) {
+    std::lock_guard<std::mutex> lk(g_na_mu);
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    if (g_na_ptr[device]) return hipSuccess;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_na_ptr[device] = static_cast<unsigned char*>(p);
+    return hipSuccess;
+}
+
+unsigned char* bubbles_scratch(int device) {
+    std::lock_guard<std::mutex> lk(g_na_mu);
+    return device >= 0 && device < kMaxDevices ? g_na_ptr[device] : nullptr;
+}
+
+BubbleWork bubbles_scratch_work(unsigned char* base) {
+    BubbleWork w{};
+    w.cnt = reinterpret_cast<uint32_t*>(base + kNaCnt);
+    w.par = reinterpret_cast<int32_t*>(base + kNaPar);
+    w.lab = reinterpret_cast<int32_t*>(base + kNaLab);
+    w.size = reinterpret_cast<int32_t*>(base + kNaSize);
+    w.roots = nullptr;  // the ordered compaction writes root / rsize instead
+    w.flag = reinterpret_cast<int32_t*>(base + kNaMisc);  // NaMisc::bad
+    return w;
+}
+
+// Clears the per-subcell counters and the status words (a fill kernel, not a
+// memset, so the sequence may be captured in a graph).
+__global__ __launch_bounds__(kBlock) void k_na_clear(uint32_t* __restrict__ cnt, int32_t nsub, NaMisc* misc) {
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < nsub; i += gridDim.x * kBlock) cnt[i] = 0u;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *misc = NaMisc{};
+}
+
+// Roots (lab[i] == i) per segment of kNaSeg subcells; gas subcells and the largest
+// bubble by atomics (order-independent).
+__global__ __launch_bounds__(kBlock) void k_na_segcount(SubGrid sg, const int32_t* __restrict__ lab,
+                                                        const int32_t* __restrict__ size,
+                                                        int32_t* __restrict__ segcnt, NaMisc* misc) {
+    __shared__ int red[kBlock];
+    const int s = blockIdx.x;
+    const int i0 = s * kNaSeg, i1 = min(i0 + kNaSeg, sg.nsub);
+    int nr = 0, ng = 0, big = 0;
+    for (int i = i0 + threadIdx.x; i < i1; i += kBlock) {
+        const int32_t r = lab[i];
+        ng += r >= 0 ? 1 : 0;
+        if (r == i) {
+            nr += 1;
+            big = max(big, size[i]);
+        }
+    }
+    red[threadIdx.x] = nr;
+    __syncthreads();
+    for (int o = kBlock / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) segcnt[s] = red[0];
+    if (ng) atomicAdd(&misc->ngas, (unsigned long long)ng);
+    if (big) atomicMax(&misc->largest, big);
+}
+
+// One block: exclusive scan of the segment counts; the total is the bubble count.
+__global__ __launch_bounds__(kBlock) void k_na_segscan(int32_t nseg, const int32_t* __restrict__ segcnt,
+                                                       int32_t* __restrict__ segoff, NaMisc* misc) {
+    __shared__ int part[kBlock];
+    constexpr int kPer = 4;  // segments per thread (nseg <= kBlock * kPer)
+    int v[kPer], tot = 0;
+    for (int k = 0; k < kPer; ++k) {
+        const int j = threadIdx.x * kPer + k;
+        v[k] = j < nseg ? segcnt[j] : 0;
+        tot += v[k];
+    }
+    part[threadIdx.x] = tot;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int t = 0; t < kBlock; ++t) {
+            const int x = part[t];
+            part[t] = run;
+            run += x;
+        }
+        misc->nroots = run;
+    }
+    __syncthreads();
+    int run = part[threadIdx.x];
+    for (int k = 0; k < kPer; ++k) {
+        const int j = threadIdx.x * kPer + k;
+        if (j < nseg) segoff[j] = run;
+        run += v[k];
+    }
+}
+
+// Roots of each segment in ascending subcell order at the segment's offset.
+__global__ __launch_bounds__(kBlock) void k_na_segwrite(SubGrid sg, const int32_t* __restrict__ lab,
+                                                        const int32_t* __restrict__ size,
+                                                        const int32_t* __restrict__ segoff,
+                                                        int64_t* __restrict__ root, int64_t* __restrict__ rsize) {
+    __shared__ int part[kBlock];
+    constexpr int kPer = kNaSeg / kBlock;  // consecutive subcells per thread
+    const int s = blockIdx.x;
+    const int i0 = s * kNaSeg + threadIdx.x * kPer;
+    int n = 0;
+    for (int k = 0; k < kPer; ++k) {
+        const int i = i0 + k;
+        n += (i < sg.nsub && lab[i] == i) ? 1 : 0;
+    }
+    part[threadIdx.x] = n;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int t = 0; t < kBlock; ++t) {
+            const int x = part[t];
+            part[t] = run;
+            run += x;
+        }
+    }
+    __syncthreads();
+    int at = segoff[s] + part[threadIdx.x];
+    for (int k = 0; k < kPer; ++k) {
+        const int i = i0 + k;
+        if (i < sg.nsub && lab[i] == i) {
+            root[at] = i;
+            rsize[at] = size[i];
+            ++at;
+        }
+    }
+}
+
 static int grid_for(int64_t n) {
     const int64_t b = (n + kBlock - 1) / kBlock;
     return (int)(b < 1 ? 1 : (b > 16384 ? 16384 : b));
@@ -143,6 +309,31 @@ void launch_bubbles(const Dev& d, int32_t b, int32_t npart, const SubGrid& sg, c
     k_sub_hook<<<grid_for(sg.nsub), kBlock, 0, s>>>(sg, w.par);
     k_sub_label<<<grid_for(sg.nsub), kBlock, 0, s>>>(sg, w.par, w.lab, w.size);
     k_sub_roots<<<grid_for(sg.nsub), kBlock, 0, s>>>(sg, w.lab, w.size, w.roots, w.flag + 1);
+}
+
+void launch_bubbles_scratch(const Dev& d, int32_t b, int32_t npart, const SubGrid& sg, unsigned char* base,
+                            uint8_t* bytes, hipStream_t s) {
+    const BubbleWork w = bubbles_scratch_work(base);
+    NaMisc* misc = reinterpret_cast<NaMisc*>(base + kNaMisc);
+    int32_t* segcnt = reinterpret_cast<int32_t*>(base + kNaSegCnt);
+    int32_t* segoff = reinterpret_cast<int32_t*>(base + kNaSegOff);
+    const int nseg = (sg.nsub + kNaSeg - 1) / kNaSeg;
+    k_na_clear<<<grid_for(sg.nsub), kBlock, 0, s>>>(w.cnt, sg.nsub, misc);
+    k_sub_count<<<grid_for(npart), kBlock, 0, s>>>(d, b, sg, w.cnt, &misc->bad);
+    k_sub_flags<<<grid_for(sg.nsub), kBlock, 0, s>>>(sg, w.cnt, bytes, w.par, w.size);
+    k_sub_hook<<<grid_for(sg.nsub), kBlock, 0, s>>>(sg, w.par);
+    k_sub_label<<<grid_for(sg.nsub), kBlock, 0, s>>>(sg, w.par, w.lab, w.size);
+    k_na_segcount<<<nseg, kBlock, 0, s>>>(sg, w.lab, w.size, segcnt, misc);
+    k_na_segscan<<<1, kBlock, 0, s>>>(nseg, segcnt, segoff, misc);
+    k_na_segwrite<<<nseg, kBlock, 0, s>>>(sg, w.lab, w.size, segoff, reinterpret_cast<int64_t*>(base + kNaRoot),
+                                          reinterpret_cast<int64_t*>(base + kNaRsize));
+}
+
+void bubbles_scratch_results(unsigned char* base, int64_t** root, int64_t** rsize, int32_t** lab, NaMisc** misc) {
+    *root = reinterpret_cast<int64_t*>(base + kNaRoot);
+    *rsize = reinterpret_cast<int64_t*>(base + kNaRsize);
+    *lab = reinterpret_cast<int32_t*>(base + kNaLab);
+    *misc = reinterpret_cast<NaMisc*>(base + kNaMisc);
 }
 
 }  // namespace mdg

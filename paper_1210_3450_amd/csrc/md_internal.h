@@ -204,6 +204,28 @@ struct BubbleWork {
 void launch_bubbles(const Dev& d, int32_t b, int32_t npart, const SubGrid& sg, const BubbleWork& w, uint8_t* bytes,
                     hipStream_t s);
 
+// Allocation-free bubble analysis: every work buffer lives in a fixed device
+// array of the library (md_bubbles.hip), sized for kNaMaxSub subcells.
+constexpr int32_t kNaMaxSub = 1 << 20;        // subcells per call at most
+constexpr int32_t kNaSeg = 2048;              // subcells per segment of the ordered compaction
+constexpr int32_t kNaSegs = kNaMaxSub / kNaSeg;
+struct NaMisc {
+    int32_t bad;               // a position was not finite or outside [-L, 2L)
+    int32_t nroots;            // bubbles found
+    unsigned long long ngas;   // gas subcells
+    int32_t largest;           // subcells of the largest bubble
+    int32_t pad;
+};
+// Takes the array's device address on `device` (which must be current) once and
+// keeps it; later calls return at once.
+hipError_t bubbles_scratch_init(int device);
+// That address, or nullptr if bubbles_scratch_init has not succeeded on `device`.
+unsigned char* bubbles_scratch(int device);
+void launch_bubbles_scratch(const Dev& d, int32_t b, int32_t npart, const SubGrid& sg, unsigned char* base,
+                            uint8_t* bytes, hipStream_t s);
+// Where the results sit inside the array at `base` (device addresses).
+void bubbles_scratch_results(unsigned char* base, int64_t** root, int64_t** rsize, int32_t** lab, NaMisc** misc);
+
 // Host-side launchers (md_kernels.hip).  All take the stream to launch on.
 void launch_set_state(const Dev& d, const Params& p, const double* pos, const double* vel,
                       int32_t nwave, hipStream_t s);
