@@ -43,7 +43,8 @@ struct md_ctx {
     std::vector<md_params> boxes;  // per box as given (box lengths change on rescale)
     std::vector<BoxGeom> geom;
     int64_t ntotal = 0;
-    int32_t nslot = 0, nwave = 0, ntile = 0;
+    int32_t nslot = 0, nwave = 0, ntile = 0, nrows = 0;
+    bool tile_fallback = false;    // a row tile overflowed its staging capacity: gather format from then on
     Params P{};
     Dev D{};
     // device allocations not reachable through D
@@ -154,6 +155,8 @@ md_status validate(const md_params* b, int32_t nbox, std::string& why) {
         if ((p.flags & MD_F_FAST_RCP) && p.precision != MD_PREC_FP64)
             return bad("MD_F_FAST_RCP applies to the FP64 path only");
         if ((p.flags & MD_F_TILE_ON) && (p.flags & MD_F_TILE_OFF)) return bad("MD_F_TILE_ON with MD_F_TILE_OFF");
+        if ((p.flags & MD_F_TILE_ON) && p.threads_per_key > 1)
+            return bad("MD_F_TILE_ON takes one lane per key (threads_per_key 0 or 1)");
         if (!(p.threads_per_key == 0 || p.threads_per_key == 1 || p.threads_per_key == 2 ||
               p.threads_per_key == 4 || p.threads_per_key == 8))
             return bad("threads_per_key must be 0, 1, 2, 4 or 8");
@@ -200,7 +203,7 @@ void lj_coeffs(double rc, int mode, double* c2, double* c0) {
 void layout(md_ctx* c) {
     const double rl = c->prm.rc + c->prm.skin;
     c->geom.assign(c->nbox, BoxGeom{});
-    int32_t slot = 0, tile = 0;
+    int32_t slot = 0, tile = 0, rows = 0;
     int64_t id = 0;
     for (int b = 0; b < c->nbox; ++b) {
         BoxGeom& g = c->geom[b];
@@ -217,7 +220,10 @@ void layout(md_ctx* c) {
         int e;
         (void)std::frexp(csmax, &e);  // csmax in [2^(e-1), 2^e)
         g.ucs = std::ldexp(1.0, kUnitBits - e);
-        for (int a = 0; a < 3; ++a) g.uoff[a] = (int32_t)std::lrint(g.cs[a] * g.ucs);
+        for (int a = 0; a < 3; ++a) {
+            g.uoff[a] = (int32_t)std::lrint(g.cs[a] * g.ucs);
+            g.nuoff[a] = (int32_t)(uint32_t)((uint64_t)g.n[a] * (uint64_t)(uint32_t)g.uoff[a]);
+        }
         g.lam = (float)std::ldexp(1.0, e - kUnitBits);
         g.lam2inv = (float)(g.ucs * g.ucs);
         g.rc2u = (float)(p.rc * p.rc * g.ucs * g.ucs);
@@ -232,7 +238,10 @@ void layout(md_ctx* c) {
         slot += g.nslot;
         g.id_off = (int32_t)id;
         id += p.n;
+        g.row_off = rows;
+        rows += g.n[1] * g.n[2];
     }
+    c->nrows = rows;
     c->nslot = slot;
     c->nwave = slot / kWave;
     c->ntile = tile;
@@ -257,11 +266,12 @@ int32_t estimate_cap(const md_ctx* c) {
 md_status upload_geometry(md_ctx* c) {
     HIPCHK(c, hipMemcpyAsync(c->D.geom, c->geom.data(), sizeof(BoxGeom) * c->nbox, hipMemcpyHostToDevice,
                              c->stream));
-    std::vector<int32_t> wb(c->nwave), tb(c->ntile);
+    std::vector<int32_t> wb(c->nwave), tb(c->ntile), rb(c->nrows);
     for (int b = 0; b < c->nbox; ++b) {
         const BoxGeom& g = c->geom[b];
         for (int w = 0; w < g.nslot / kWave; ++w) wb[g.slot_off / kWave + w] = b;
         for (int t = 0; t < g.ntile; ++t) tb[g.tile_off + t] = b;
+        for (int r = 0; r < g.n[1] * g.n[2]; ++r) rb[g.row_off + r] = b;
     }
     std::vector<double4> dsh(27 * c->nbox);
     for (int b = 0; b < c->nbox; ++b) {
@@ -278,6 +288,8 @@ md_status upload_geometry(md_ctx* c) {
                              c->stream));
     HIPCHK(c, hipMemcpyAsync(c->D.tile_box, tb.data(), sizeof(int32_t) * tb.size(), hipMemcpyHostToDevice,
                              c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->D.row_box, rb.data(), sizeof(int32_t) * rb.size(), hipMemcpyHostToDevice,
+                             c->stream));
     HIPCHK(c, hipMemcpyAsync(c->D.dshift, dsh.data(), sizeof(double4) * dsh.size(), hipMemcpyHostToDevice,
                              c->stream));
     // the vectors above are pageable: finish the copies before they go away
@@ -293,7 +305,30 @@ md_status alloc_cells(md_ctx* c) {
     dfree(c->D.tile_sum);
     dfree(c->D.tile_pref);
     dfree(c->D.tile_need);
+    dfree(c->D.rtile);
+    dfree(c->D.row_box);
+    dfree(c->D.row_nt);
+    dfree(c->D.row_t0);
+    dfree(c->D.cell_rt);
+    dfree(c->D.rt_tmp);
+    dfree(c->D.ke_part);
+    dfree(c->D.pe_part);
+    dfree(c->D.vir_part);
+    dfree(c->D.red);
     md_status s;
+    const size_t ncellpad = (size_t)c->ntile * kTile;
+    // energy partials: per list wavefront, or per row tile (at most one per cell)
+    const size_t nparts = std::max((size_t)c->nwave * 8, ncellpad);
+    if ((s = dalloc(c, &c->D.rtile, ncellpad)) != MD_OK) return s;
+    if ((s = dalloc(c, &c->D.row_box, c->nrows)) != MD_OK) return s;
+    if ((s = dalloc(c, &c->D.row_nt, c->nrows)) != MD_OK) return s;
+    if ((s = dalloc(c, &c->D.row_t0, c->nrows)) != MD_OK) return s;
+    if ((s = dalloc(c, &c->D.cell_rt, ncellpad)) != MD_OK) return s;
+    if ((s = dalloc(c, &c->D.rt_tmp, ncellpad)) != MD_OK) return s;
+    if ((s = dalloc(c, &c->D.ke_part, nparts)) != MD_OK) return s;
+    if ((s = dalloc(c, &c->D.pe_part, nparts)) != MD_OK) return s;
+    if ((s = dalloc(c, &c->D.vir_part, nparts)) != MD_OK) return s;
+    if ((s = dalloc(c, &c->D.red, (size_t)c->nbox * c->P.redcap * 3)) != MD_OK) return s;
     if ((s = dalloc(c, &c->D.tile_box, c->ntile)) != MD_OK) return s;
     if ((s = dalloc(c, &c->D.cell_cnt, (size_t)c->ntile * kTile)) != MD_OK) return s;
     if ((s = dalloc(c, &c->D.cell_start, (size_t)c->ntile * kTile)) != MD_OK) return s;
@@ -340,6 +375,8 @@ void params_refresh(md_ctx* c) {
     P.mass = p.mass;
     P.skin = p.skin;
     P.rc2f = (float)P.rc2;
+    P.irc2f = (float)(1.0 / P.rc2);
+    P.clamp = p.cutoff == MD_CUT_EQ1 ? 1 : 0;
     P.c2f = (float)c2;
     P.c0f = (float)c0;
     P.policy = p.rebuild;
@@ -347,21 +384,35 @@ void params_refresh(md_ctx* c) {
     P.nwave = c->nwave;
     P.ntile = c->ntile;
     P.precision = p.precision;
-    // Staged tiles pay off when a block's 256 keys span at most two rows of cells
-    // and their partners fit the tile (about 9 * 256 partners per key row, at most
-    // 20 particles per cell); otherwise the force pass gathers from global memory.
-    bool tile = p.precision == MD_PREC_FP32_MIXED && kTileByDefault;
-    for (const BoxGeom& g : c->geom) {
-        const double ppc = (double)g.npart / (double)g.ncell;
-        tile = tile && ppc <= 20.0 && (double)g.n[0] >= (double)kBlock / ppc + 3.0;
-    }
-    if (p.flags & MD_F_TILE_ON) tile = p.precision == MD_PREC_FP32_MIXED;
-    if (p.flags & MD_F_TILE_OFF) tile = false;
     P.half = (p.flags & MD_F_HALF_LIST) ? 1 : 0;
+    // Row tiles (FP32-mixed, full list, one lane per key): the force pass reads every
+    // partner from LDS; the gather format serves the other layouts and boxes whose
+    // cells are too crowded for a tile's staging capacity.
+    P.tile = p.precision == MD_PREC_FP32_MIXED && !P.half && P.tpk == 1 && !(p.flags & MD_F_TILE_OFF) &&
+                     !c->tile_fallback
+                 ? 1
+                 : 0;
+    P.kt = kRtBlock;
+    P.scap = kStageCap;
+    P.nrows = c->nrows;
     P.maxslot = 0;
-    for (const BoxGeom& g : c->geom) P.maxslot = std::max(P.maxslot, g.nslot);
-    P.redcap = (P.maxslot / kWave * 8 + kRedSeg - 1) / kRedSeg;
-    P.tile = tile && !P.half ? 1 : 0;
+    P.maxcell = 0;
+    for (const BoxGeom& g : c->geom) {
+        P.maxslot = std::max(P.maxslot, g.nslot);
+        P.maxcell = std::max(P.maxcell, g.ncell);
+    }
+    P.redcap = (std::max(P.maxslot / kWave * 8, P.maxcell) + kRedSeg - 1) / kRedSeg;
+    // Row-tile force kernel: one resident round of blocks, each looping over the tiles
+    // (block k takes tiles k, k + grid, ...).  With the XCD-aware order each XCD then
+    // sweeps the same band of rows plane after plane, so the rows it stages stay in its
+    // L2; a grid of one block per tile measured 16% slower at 32M particles.
+    if (P.tgrid <= 0) {
+        hipDeviceProp_t prop;
+        int cus = 256;
+        if (hipGetDeviceProperties(&prop, c->device) == hipSuccess && prop.multiProcessorCount > 0)
+            cus = prop.multiProcessorCount;
+        P.tgrid = cus * rowtile_blocks_per_cu(P);
+    }
     P.fastrcp = (p.flags & MD_F_FAST_RCP) ? 1 : 0;
 }
 
@@ -395,6 +446,14 @@ void free_all(md_ctx* c) {
     dfree(D.tile_sum);
     dfree(D.tile_pref);
     dfree(D.tile_need);
+    dfree(D.rtile);
+    dfree(D.row_box);
+    dfree(D.row_nt);
+    dfree(D.row_t0);
+    dfree(D.ntiles);
+    dfree(D.box_t0);
+    dfree(D.cell_rt);
+    dfree(D.rt_tmp);
     dfree(D.vmax_s);
     dfree(D.disp_s);
     dfree(D.ke_part);
@@ -454,10 +513,8 @@ md_status alloc_all(md_ctx* c) {
     A(D.perm, ns);
     A(D.vmax_s, (size_t)c->nbox * kStripes * kStripeStride);
     A(D.disp_s, (size_t)c->nbox * kStripes * kStripeStride);
-    A(D.ke_part, (size_t)c->nwave * 8);
-    A(D.pe_part, (size_t)c->nwave * 8);
-    A(D.vir_part, (size_t)c->nwave * 8);
-    A(D.red, (size_t)c->nbox * c->P.redcap * 3);
+    A(D.ntiles, 2);
+    A(D.box_t0, (size_t)c->nbox + 1);
     A(D.dshift, (size_t)27 * c->nbox);
     A(D.series_ke, (size_t)kMaxSeries * c->nbox);
     A(D.series_pe, (size_t)kMaxSeries * c->nbox);
@@ -469,6 +526,7 @@ md_status alloc_all(md_ctx* c) {
 #undef A
     if ((s = alloc_cells(c)) != MD_OK) return s;
     HIPCHK(c, hipMemsetAsync(D.any, 0, sizeof(int32_t), c->stream));
+    HIPCHK(c, hipMemsetAsync(D.ntiles, 0, 2 * sizeof(int32_t), c->stream));
     HIPCHK(c, hipMemsetAsync(D.vmax_s, 0, sizeof(unsigned long long) * c->nbox * kStripes * kStripeStride, c->stream));
     HIPCHK(c, hipMemsetAsync(D.disp_s, 0, sizeof(unsigned long long) * c->nbox * kStripes * kStripeStride, c->stream));
     HIPCHK(c, hipHostMalloc((void**)&c->st_h, sizeof(BoxState) * c->nbox, hipHostMallocDefault));
@@ -603,6 +661,24 @@ int32_t max_need(const md_ctx* c) {
     return m;
 }
 
+// Some box has a one-cell row tile whose staged region exceeds the capacity.
+bool tile_overflow(const md_ctx* c) {
+    for (int b = 0; b < c->nbox; ++b)
+        if (c->st_h[b].err & 4) return true;
+    return false;
+}
+
+// From now on the gather format: its lists need no staging capacity.  The caller
+// has synchronized; the mirrored states lose the overflow bit.
+md_status switch_to_gather(md_ctx* c) {
+    c->tile_fallback = true;
+    drop_graphs(c);
+    params_refresh(c);
+    for (int b = 0; b < c->nbox; ++b) c->st_h[b].err &= ~4;
+    return MD_OK;
+}
+
+
 // Full list build for every box, growing the list until it fits.
 md_status build_list(md_ctx* c) {
     md_status s;
@@ -612,6 +688,12 @@ md_status build_list(md_ctx* c) {
         LAUNCHCHK(c);
         if ((s = sync_states(c)) != MD_OK) return s;
         if ((s = status_from_states(c)) != MD_OK) return s;
+        if (tile_overflow(c)) {  // rebuild in the gather format
+            switch_to_gather(c);
+            for (int b = 0; b < c->nbox; ++b) c->st_h[b].need = 0;
+            if ((s = push_states(c)) != MD_OK) return s;
+            continue;
+        }
         const int32_t need = max_need(c);
         if (need <= c->P.cap) {
             c->have_cells = c->have_list = true;
@@ -701,6 +783,9 @@ md_status create_impl(const md_params* boxes, int32_t nbox, void* stream, md_ctx
     // per key to fill the chip; large ones are bound by partner gathers, where the
     // FP64 path's 32-byte records gain from two lanes reading adjacent entries
     if (tpk == 0) tpk = c->ntotal < 262144 ? 4 : (c->prm.precision == MD_PREC_FP64 ? 2 : 1);
+    // the FP32-mixed row-tile path takes one lane per key at every size
+    if (c->prm.threads_per_key == 0 && c->prm.precision == MD_PREC_FP32_MIXED && !(c->prm.flags & MD_F_TILE_OFF))
+        tpk = 1;
     if (c->prm.flags & MD_F_HALF_LIST) tpk = 1;
     c->P.tpk = tpk;
     params_refresh(c);
@@ -792,10 +877,9 @@ md_status md_rescale_box(md_ctx* c, double alpha) {
     c->prm.box[0] = c->boxes[0].box[0];
     c->prm.box[1] = c->boxes[0].box[1];
     c->prm.box[2] = c->boxes[0].box[2];
-    const int32_t old_ntile = c->ntile;
     layout(c);
     params_refresh(c);
-    if (c->ntile != old_ntile && (s = alloc_cells(c)) != MD_OK) return s;
+    if ((s = alloc_cells(c)) != MD_OK) return s;
     if ((s = upload_geometry(c)) != MD_OK) return s;
     c->have_cells = c->have_list = c->have_F = false;
     return MD_OK;
@@ -876,7 +960,7 @@ md_status md_step(md_ctx* c, int32_t nsteps, int32_t energy_every) {
             const int32_t gk = done + k;
             if (k == 1) {
                 launch_ke_partial(c->D, c->P, c->stream);
-                launch_energy_reduce(c->D, c->P, false, 2, c->stream);
+                launch_energy_reduce(c->D, c->P, false, 2, false, c->stream);
                 launch_kick_drift(c->D, c->P, c->stream);
                 launch_dutc(c->D, c->P, c->stream);
             }
@@ -884,7 +968,7 @@ md_status md_step(md_ctx* c, int32_t nsteps, int32_t energy_every) {
             const bool last = k == chunk;
             if ((s = enqueue_rebuild(c, true)) != MD_OK) return s;
             if ((s = enqueue_force(c, kForceEnd, true)) != MD_OK) return s;
-            launch_energy_reduce(c->D, c->P, energy, last ? 1 : 3, c->stream);
+            launch_energy_reduce(c->D, c->P, energy, last ? 1 : 3, c->P.tile != 0, c->stream);
             if (last) {
                 launch_vscale(c->D, c->P, c->stream);
             } else {
@@ -903,7 +987,7 @@ md_status md_step(md_ctx* c, int32_t nsteps, int32_t energy_every) {
             if (energy || last) {
                 if ((s = enqueue_rebuild(c, true)) != MD_OK) return s;
                 if ((s = enqueue_force(c, kForceEnd, energy)) != MD_OK) return s;
-                if (energy) launch_energy_reduce(c->D, c->P, true, 0, c->stream);
+                if (energy) launch_energy_reduce(c->D, c->P, true, 0, c->P.tile != 0, c->stream);
                 if (!last) {
                     launch_kick_drift(c->D, c->P, c->stream);
                     launch_dutc(c->D, c->P, c->stream);
@@ -924,10 +1008,15 @@ md_status md_step(md_ctx* c, int32_t nsteps, int32_t energy_every) {
             if ((s = push_states(c)) != MD_OK) return s;
         }
         const int32_t need = max_need(c);
-        if (need > c->P.cap) {
-            // overflowed: restore the chunk's starting state, grow, rebuild, replay
-            if ((s = alloc_list(c, need + need / 4 + 8)) != MD_OK) return s;
-            c->regrows += 1;
+        const bool tover = tile_overflow(c);
+        if (need > c->P.cap || tover) {
+            // overflowed (list capacity, or a row tile's staging capacity): restore the
+            // chunk's starting state, grow or change the list format, rebuild, replay
+            if (tover) switch_to_gather(c);
+            if (need > c->P.cap) {
+                if ((s = alloc_list(c, need + need / 4 + 8)) != MD_OK) return s;
+                c->regrows += 1;
+            }
             for (int b = 0; b < c->nbox; ++b) {
                 BoxState st = before[b];
                 st.sq = st.sp = 0;
@@ -961,7 +1050,7 @@ static md_status energies(md_ctx* c) {
     if (!c->have_list && (s = build_list(c)) != MD_OK) return s;
     if ((s = enqueue_force(c, kForceOnly, true)) != MD_OK) return s;
     c->have_F = true;
-    launch_energy_reduce(c->D, c->P, false, 0, c->stream);
+    launch_energy_reduce(c->D, c->P, false, 0, c->P.tile != 0, c->stream);
     LAUNCHCHK(c);
     return sync_states(c);
 }

@@ -8,13 +8,13 @@
 //   q[2]      Pos records (x, y, z in FP64, the packed cell coordinates of the last
 //             build, the list length), 32 bytes, ping-pong: the force kernel gathers
 //             partners from q[sq] and writes drifted positions to q[1-sq].
-//   u[2]      cell-relative positions in fixed point, 3 int32 per slot (12 bytes,
-//             no padding, so a partner gather touches fewer cache lines; FP32-mixed path),
-//             ping-pong with q: u = rint((x - (c + 1/2) cs) * ucs) per axis,
-//             c = the particle's cell at the last build, ucs a power of two
-//             (units per length, the same on every axis).  A pair's separation
-//             u_j - u_i + o * uoff (o = stencil offset, uoff = one cell side in
-//             units) is exact in int32; it is converted to FP32 once, and lengths
+//   u[2]      positions in fixed point, 3 int32 per slot (12 bytes, no padding;
+//             FP32-mixed path), ping-pong with q: per axis
+//             U = c * uoff + rint((x - (c + 1/2) cs) * ucs) modulo 2^32, c = the
+//             particle's cell at the last build, uoff = rint(cs * ucs) one cell side
+//             in units, ucs a power of two (units per length, the same on every
+//             axis).  A pair's separation U_j - U_i - r * n * uoff (r = periodic
+//             image) is exact in int32; it is converted to FP32 once, and lengths
 //             stay in units until the per-particle force is scaled back.
 //   v*[2]     float64 velocity components (SoA), ping-pong only across a re-sort.
 //   id[2]     caller index of the particle in each slot.
@@ -26,7 +26,18 @@
 //             lane reads 8 entries.  Entry = s << 11 | offset: s = stencil cell of
 //             the partner (z-major over offsets (ox, oy, oz) in {-1,0,1}^3, 0..26)
 //             and the partner's rank within that cell (cells hold at most 2048).
+//             Row-tile format (FP32-mixed, one lane per key): entry = 12 * the
+//             partner's index in its key's staged row tile (below): the LDS byte
+//             offset of its 12-byte record.
 //   cells     per box ncell counters and starts, box ranges aligned to 1024-cell tiles.
+//   row tiles (FP32-mixed path) each row of cells (fixed cy, cz) is cut into runs of
+//             consecutive cells [xa, xb) holding at most kt keys whose staged partner
+//             region fits scap records.  The region is the 9 rows (cy+dy, cz+dz),
+//             dy, dz in {-1,0,1}, over the unwrapped cells xa-1 .. xb; a row's run is
+//             one contiguous range of slots, plus one wrapped cell at either x end
+//             ("pieces": row r = (dz+1)*3 + (dy+1), side 0 = cell x = -1, 1 = the
+//             run inside [0, n), 2 = cell x = n).  Staged index order: piece by piece,
+//             slots in order, so every cell's members are consecutive.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -46,7 +57,10 @@ constexpr int kOffBits = 11;             // list entry: partner rank within its 
 constexpr int kMaxCellCount = 1 << kOffBits;
 constexpr int kStripes = 1024;           // slots per box for per-step maxima
 constexpr int kStripeStride = 16;        // 128 bytes between slots
-constexpr bool kTileByDefault = false;   // staged-tile force pass chosen from the geometry
+constexpr int kTileWMax = 64;            // cells per row tile at most
+constexpr int kScapMax = 5461;           // staged records per row tile at most (16-bit entries of 12 * index)
+constexpr int kRtBlock = 256;            // threads per block of the row-tile force kernel (keys per tile)
+constexpr int kStageCap = 2432;          // staged records per row tile (28.5 KB of LDS)
 constexpr int kRedSeg = 2048;            // energy partials per first-level segment
 
 // Position record of one slot.  cc and cnt ride in the 8 bytes a double4
@@ -65,6 +79,7 @@ struct BoxGeom {
     double ucs;      // fixed-point units per length, a power of two with cs * ucs in [2^27, 2^28)
                      // for the largest cell side (the same unit on every axis)
     int32_t uoff[3]; // one cell side in units, per axis: rint(cs * ucs)
+    int32_t nuoff[3];// one box length in units modulo 2^32, per axis: n * uoff (the periodic image term)
     float lam;       // length per unit, 1 / ucs (exact)
     float lam2inv;   // ucs^2 (exact)
     float rc2u;      // rc^2 in units^2
@@ -78,7 +93,7 @@ struct BoxGeom {
     int32_t npart;
     int32_t nslot;
     int32_t id_off;    // first caller index of this box
-    int32_t pad;
+    int32_t row_off;   // first global row of cells (row = cz * ny + cy within the box)
 };
 
 struct BoxState {
@@ -86,7 +101,8 @@ struct BoxState {
     int32_t rebuild;           // list build pending for this box
     int32_t sq;                // current q / u buffer
     int32_t sp;                // current v / id buffer
-    int32_t err;               // bit 0: bad position at binning; bit 1: a cell over 2048 particles
+    int32_t err;               // bit 0: bad position at binning; bit 1: a cell over 2048 particles;
+                               // bit 2: a one-cell row tile whose partner region exceeds scap
     int32_t need;              // longest list seen at any build (for overflow detection)
     int32_t built;             // builds done
     unsigned long long missed; // verifier: pairs within rc absent from the list
@@ -101,7 +117,7 @@ struct BoxState {
 
 struct Params {
     double rc2, rl2, c2, c0, dt, h, mass, skin;  // h = dt / (2 m)
-    float rc2f, c2f, c0f, padf;
+    float rc2f, c2f, c0f, irc2f;  // irc2f: 1 / rc^2 (FP32)
     int32_t cap;        // list entries per key (multiple of 8 * tpk)
     int32_t tpk;        // lanes per key
     int32_t rows;       // cap / tpk, a multiple of 8
@@ -111,10 +127,16 @@ struct Params {
     int32_t ntile;      // cell tiles over all boxes
     int32_t precision;  // MD_PREC_*
     int32_t record;     // energy reduction appends to the series
-    int32_t tile;       // FP32-mixed forces from LDS-staged partner tiles (one lane per key)
+    int32_t tile;       // row-tile list format and forces from LDS-staged tiles (FP32-mixed, one lane per key)
+    int32_t kt;         // keys per row tile at most (a single cell may hold more)
+    int32_t scap;       // staged partner records per row tile at most (LDS: 16 bytes each)
+    int32_t tgrid;      // blocks of the row-tile force kernel: one resident round (each loops over tiles)
+    int32_t clamp;      // Eq. 1 cutoff (f(rc) = 0): FP32-mixed forces clamp 1/r^2 at 1/rc^2 instead of masking
+    int32_t nrows;      // rows of cells over all boxes
     int32_t fastrcp;    // FP64 forces from the hardware reciprocal with the correction of r^-8, r^-14
     int32_t half;       // half list (each pair once, forward stencil cells), partner forces by atomics
     int32_t maxslot;    // slots of the largest box
+    int32_t maxcell;    // cells of the largest box
     int32_t redcap;     // first-level energy sums per box (enough for 8 lanes per key)
 };
 
@@ -144,6 +166,14 @@ struct Dev {
     int32_t* tile_sum;
     int32_t* tile_pref;
     int32_t* tile_need;  // longest list per cell tile at the last build
+    int4* rtile;         // row tiles: (box, row cz * ny + cy, xa, xb), in global row order
+    int32_t* row_box;    // box of each global row
+    int32_t* row_nt;     // row tiles per row
+    int32_t* row_t0;     // first row tile of each row (exclusive scan of row_nt)
+    int32_t* ntiles;     // [0] row tiles in all, [1] longest staged region
+    int32_t* box_t0;     // [nbox + 1] first row tile of each box, then the total
+    int32_t* cell_rt;    // row tile of each cell
+    int32_t* rt_tmp;     // per cell: xa | xb << 16 of the row's k-th tile at (row's first cell + k)
     unsigned long long* vmax_s;  // [nbox][kStripes] striped max |v|^2 (bits), stride kStripeStride
     unsigned long long* disp_s;  // [nbox][kStripes] striped max |q - q_build|^2 (bits)
     double* ke_part;     // per list wave
@@ -238,6 +268,10 @@ void launch_list_counts(const Dev& d, const Params& p, int64_t* cnt_by_id, int32
 void launch_list_export(const Dev& d, const Params& p, const int64_t* key_ptr, int32_t* partners,
                         int32_t nwave, hipStream_t s);
 void launch_mark_rebuild(const Dev& d, const Params& p, hipStream_t s);
+// Row tiles of every box from the current cell counts (after binning and scans).
+void launch_row_tiles(const Dev& d, const Params& p, hipStream_t s);
+// Resident blocks per compute unit of the row-tile force kernel.
+int rowtile_blocks_per_cu(const Params& p);
 void launch_rebuild_chain(const Dev& d, const Params& p, bool with_list, hipStream_t s);
 void launch_force(const Dev& d, const Params& p, int mode, bool energy, hipStream_t s);
 void launch_kick_drift(const Dev& d, const Params& p, hipStream_t s);
@@ -245,7 +279,9 @@ void launch_dutc(const Dev& d, const Params& p, hipStream_t s);
 // thermo: bit 0 applies the thermostat half step that ends a step (after the
 // closing kick), bit 1 the one that starts the next step; the velocity factor
 // goes to BoxState::vscale for the next kick (or k_vscale).
-void launch_energy_reduce(const Dev& d, const Params& p, bool record, int thermo, hipStream_t s);
+// tl: the partials are per row tile (written by the row-tile force kernel), else per
+// list wavefront.
+void launch_energy_reduce(const Dev& d, const Params& p, bool record, int thermo, bool tl, hipStream_t s);
 void launch_ke_partial(const Dev& d, const Params& p, hipStream_t s);
 void launch_vscale(const Dev& d, const Params& p, hipStream_t s);
 void launch_verify(const Dev& d, const Params& p, hipStream_t s);

@@ -155,10 +155,23 @@ __device__ __forceinline__ Pos make_pos(double x, double y, double z, uint32_t c
     return r;
 }
 
+// Global fixed-point coordinate of x, modulo 2^32: c * uoff + the cell-relative
+// units, c = the particle's cell at the last build.  Any two particles' difference
+// (plus a periodic image term n * uoff) is their exact separation in units, since
+// it stays far inside int32; a block can therefore stage any run of cells with a
+// plain copy.
+__device__ __forceinline__ int gunit(double x, int c, double cs, double ucs, int32_t uoff) {
+    return (int)((uint32_t)to_units(x, c, cs, ucs) + (uint32_t)c * (uint32_t)uoff);
+}
 __device__ __forceinline__ int4 units3(const Pos& x, uint32_t cc, const BoxGeom& g) {
-    return make_int4(to_units(x.x, cc & 1023, g.cs[0], g.ucs), to_units(x.y, (cc >> 10) & 1023, g.cs[1], g.ucs),
-                     to_units(x.z, cc >> 20, g.cs[2], g.ucs), (int)(cc & 1023));  // w: the cell's x index
-
+    return make_int4(gunit(x.x, cc & 1023, g.cs[0], g.ucs, g.uoff[0]),
+                     gunit(x.y, (cc >> 10) & 1023, g.cs[1], g.ucs, g.uoff[1]),
+                     gunit(x.z, cc >> 20, g.cs[2], g.ucs, g.uoff[2]), 0);
+}
+// The image term of a periodic image r (r = +1 where the partner's cell index wrapped
+// below 0), per axis, modulo 2^32: -r * n * uoff.
+__device__ __forceinline__ int img_units(int r, int n, int32_t uoff) {
+    return (int)(uint32_t)(-(int64_t)r * (int64_t)n * (int64_t)uoff);
 }
 
 
@@ -307,6 +320,30 @@ __device__ __forceinline__ int entry_slot(const Dev& d, uint32_t cc, uint32_t e,
     return d.cell_start[stencil_cell(cc, (int)(e >> kOffBits), g, &img)] + (int)(e & (kMaxCellCount - 1));
 }
 
+__device__ __forceinline__ void tile_piece(const Dev& d, const BoxGeom& g, int cy, int cz, int xa, int xb, int p,
+                                           int& s0, int& len, int& ox, int& oy, int& oz);
+
+// First slots and lengths of the 27 pieces staged for the row tile of the key whose
+// cell is cc (diagnostics: decoding of row-tile entries).
+__device__ void tile_pieces_of(const Dev& d, const BoxGeom& g, uint32_t cc, int* ps0, int* plen) {
+    const int cx = (int)(cc & 1023), cy = (int)((cc >> 10) & 1023), cz = (int)(cc >> 20);
+    const int4 tr = d.rtile[d.cell_rt[g.cell_off + (cz * g.n[1] + cy) * g.n[0] + cx]];
+    for (int pc = 0; pc < 27; ++pc) {
+        int ox, oy, oz;
+        tile_piece(d, g, cy, cz, tr.z, tr.w, pc, ps0[pc], plen[pc], ox, oy, oz);
+    }
+}
+
+// Slot behind a row-tile entry (12 * staged index), given the tile's pieces.
+__device__ int tile_slot(const int* ps0, const int* plen, uint32_t e) {
+    int idx = (int)(e / (uint32_t)sizeof(U3));
+    for (int pc = 0; pc < 27; ++pc) {
+        if (idx < plen[pc]) return ps0[pc] + idx;
+        idx -= plen[pc];
+    }
+    return ps0[13];  // not reached for an entry the build wrote
+}
+
 __global__ __launch_bounds__(kBlock) void k_list_export(Dev d, Params p, const int64_t* __restrict__ key_ptr,
                                                         int32_t* __restrict__ partners) {
     const int l = lane_id();
@@ -320,8 +357,15 @@ __global__ __launch_bounds__(kBlock) void k_list_export(Dev d, Params p, const i
         const int64_t base = key_ptr[id[s]];
         const int n = d.cnt[s];
         const uint32_t cc = d.q[d.st[b].sq][s].cc;
-        for (int e = 0; e < n; ++e)
-            partners[base + e] = id[entry_slot(d, cc, d.list[list_addr(s, e, p.tpk, p.rows)], g)];
+        if (p.tile) {
+            int ps0[27], plen[27];
+            tile_pieces_of(d, g, cc, ps0, plen);
+            for (int e = 0; e < n; ++e)
+                partners[base + e] = id[tile_slot(ps0, plen, d.list[list_addr(s, e, p.tpk, p.rows)])];
+        } else {
+            for (int e = 0; e < n; ++e)
+                partners[base + e] = id[entry_slot(d, cc, d.list[list_addr(s, e, p.tpk, p.rows)], g)];
+        }
         for (int a = 1; a < n; ++a) {  // ascending, insertion sort
             const int32_t x = partners[base + a];
             int c = a - 1;
@@ -434,6 +478,7 @@ __global__ __launch_bounds__(kBlock) void k_post_build(Dev d, Params p, int with
 
 __global__ __launch_bounds__(kBlock) void k_cell_clear(Dev d, Params p) {
     if (!ld_const(d.any)) return;  // no box rebuilds this step
+    if (p.tile && blockIdx.x == 0 && threadIdx.x == 0) d.ntiles[1] = 0;  // longest staged region, rebuilt below
     for (int t = blockIdx.x; t < p.ntile; t += gridDim.x) {
         if (!d.st[d.tile_box[t]].rebuild) continue;
         int4* c = reinterpret_cast<int4*>(d.cell_cnt + (size_t)t * kTile);
@@ -588,6 +633,156 @@ __global__ __launch_bounds__(kBlock) void k_rank_permute(Dev d, Params p) {
     }
 }
 
+// ---------------------------------------------------------------- row tiles
+
+__device__ __forceinline__ int wrap_idx(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+// Piece p = r * 3 + side (r = (dz+1)*3 + (dy+1)) of the staged partner region of the
+// row tile with home cells [xa, xb) of row (cy, cz): its first slot, its length (0 if
+// the piece is absent) and the image terms its fixed-point records take on, so that
+// every staged record is in the unwrapped frame of the home row.
+//   side 0: unwrapped cell x = -1, i.e. cell n-1 one box length down (only if xa == 0)
+//   side 1: cells max(xa-1, 0) .. min(xb, n-1), one contiguous run of slots
+//   side 2: unwrapped cell x = n, i.e. cell 0 one box length up (only if xb == n)
+__device__ __forceinline__ void tile_piece(const Dev& d, const BoxGeom& g, int cy, int cz, int xa, int xb, int p,
+                                           int& s0, int& len, int& ox, int& oy, int& oz) {
+    const int r = (p * 11) >> 5, side = p - 3 * r;  // p / 3 for p < 27
+    const int rz = (r * 11) >> 5, ry = r - 3 * rz;
+    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    const int y = cy + ry - 1, z = cz + rz - 1;
+    s0 = 0;
+    len = 0;
+    // image terms modulo 2^32: a cell index that wrapped below 0 takes -n * uoff, above n-1 +n * uoff
+    ox = side == 0 ? -g.nuoff[0] : (side == 2 ? g.nuoff[0] : 0);
+    oy = y < 0 ? -g.nuoff[1] : (y >= ny ? g.nuoff[1] : 0);
+    oz = z < 0 ? -g.nuoff[2] : (z >= nz ? g.nuoff[2] : 0);
+    int x0, x1;
+    if (side == 0) {
+        if (xa > 0) return;
+        x0 = x1 = nx - 1;
+    } else if (side == 2) {
+        if (xb < nx) return;
+        x0 = x1 = 0;
+    } else {
+        x0 = max(xa - 1, 0);
+        x1 = min(xb, nx - 1);
+    }
+    const int rowc = g.cell_off + (wrap_idx(z, nz) * ny + wrap_idx(y, ny)) * nx;
+    s0 = d.cell_start[rowc + x0];
+    len = d.cell_start[rowc + x1] + d.cell_cnt[rowc + x1] - s0;
+}
+
+// Cuts every row of cells into row tiles, greedily from x = 0: a tile grows by the
+// next cell while its keys stay within kt, its staged region within scap records and
+// its width within kTileWMax cells.  One wavefront per row; the column sums of the
+// 3 x 3 rows around it (cells x = -1 .. n, unwrapped) go to LDS first.  A one-cell
+// tile whose region exceeds scap sets error bit 2 of its box (the context then
+// falls back to the gather format).
+__global__ __launch_bounds__(kBlock) void k_row_tiles(Dev d, Params p) {
+    if (!ld_const(d.any)) return;  // no box rebuilds this step
+    __shared__ int col_all[kBlock / kWave][kMaxCellsPerAxis + 3];  // unwrapped x -> index x + 1
+    __shared__ int hom_all[kBlock / kWave][kMaxCellsPerAxis + 1];
+    const int wv = wave_in_block(), l = lane_id();
+    int* col = col_all[wv];
+    int* hom = hom_all[wv];
+    for (int row = blockIdx.x * 4 + wv; row < p.nrows; row += gridDim.x * 4) {
+        const int b = ld_const(d.row_box + row);
+        const BoxGeom g = ld_geom(d.geom + b);
+        const int lr = row - g.row_off, nx = g.n[0], ny = g.n[1], nz = g.n[2];
+        const int cy = lr % ny, cz = lr / ny;
+        for (int x = l - 1; x <= nx; x += kWave) {
+            const int xw = wrap_idx(x, nx);
+            int sum = 0;
+#pragma unroll
+            for (int r = 0; r < 9; ++r) {
+                const int yw = wrap_idx(cy + r % 3 - 1, ny), zw = wrap_idx(cz + r / 3 - 1, nz);
+                sum += d.cell_cnt[g.cell_off + (zw * ny + yw) * nx + xw];
+            }
+            col[x + 1] = sum;
+            if (x >= 0 && x < nx) hom[x] = d.cell_cnt[g.cell_off + (cz * ny + cy) * nx + x];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (l == 0) {
+            const int base = g.cell_off + lr * nx;  // the row's cells hold its tiles in rt_tmp
+            int nt = 0, xa = 0, big = 0;
+            bool over = false;
+            while (xa < nx) {
+                int keys = hom[xa], stg = col[xa] + col[xa + 1] + col[xa + 2];
+                int xb = xa + 1;
+                while (xb < nx && xb - xa < kTileWMax && keys + hom[xb] <= p.kt && stg + col[xb + 2] <= p.scap) {
+                    keys += hom[xb];
+                    stg += col[xb + 2];
+                    ++xb;
+                }
+                over = over || stg > p.scap;
+                big = max(big, stg);
+                d.rt_tmp[base + nt] = xa | (xb << 16);
+                ++nt;
+                xa = xb;
+            }
+            d.row_nt[row] = nt;
+            if (over) atomicOr(&d.st[b].err, 4);
+            atomicMax(d.ntiles + 1, big);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
+// One block: exclusive scan of the tiles per row (global row order), the tile
+// total, and each box's first tile.
+__global__ __launch_bounds__(kBlock) void k_row_scan(Dev d, Params p) {
+    if (!ld_const(d.any)) return;
+    __shared__ int part[kBlock];
+    const int n = p.nrows;
+    const int per = (n + kBlock - 1) / kBlock;
+    const int a = min((int)threadIdx.x * per, n), e = min(a + per, n);
+    int sum = 0;
+    for (int i = a; i < e; ++i) sum += d.row_nt[i];
+    part[threadIdx.x] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int t = 0; t < kBlock; ++t) {
+            const int x = part[t];
+            part[t] = run;
+            run += x;
+        }
+        d.ntiles[0] = run;
+        d.box_t0[p.nbox] = run;
+    }
+    __syncthreads();
+    int run = part[threadIdx.x];
+    for (int i = a; i < e; ++i) {
+        const int b = d.row_box[i];
+        if (i == 0 || d.row_box[i - 1] != b) d.box_t0[b] = run;  // a box's rows are consecutive
+        d.row_t0[i] = run;
+        run += d.row_nt[i];
+    }
+}
+
+// Row tiles into their global slots, and the tile of every cell.  One wavefront
+// per row, one lane per tile.
+__global__ __launch_bounds__(kBlock) void k_row_write(Dev d, Params p) {
+    if (!ld_const(d.any)) return;
+    const int l = lane_id();
+    for (int row = blockIdx.x * 4 + wave_in_block(); row < p.nrows; row += gridDim.x * 4) {
+        const int b = ld_const(d.row_box + row);
+        const BoxGeom g = ld_geom(d.geom + b);
+        const int lr = row - g.row_off, base = g.cell_off + lr * g.n[0];
+        const int nt = d.row_nt[row], t0 = d.row_t0[row];
+        for (int k = l; k < nt; k += kWave) {
+            const int v = d.rt_tmp[base + k];
+            const int xa = v & 0xffff, xb = v >> 16;
+            d.rtile[t0 + k] = make_int4(b, lr, xa, xb);
+            for (int x = xa; x < xb; ++x) d.cell_rt[base + x] = t0 + k;
+        }
+    }
+}
+
 // ---------------------------------------------------------------- pair list
 
 // Squared minimum-image distance exactly as the plain definition evaluates it:
@@ -669,8 +864,9 @@ constexpr int kMarkBytes = 6 * kWave;  // candidate window of a pass (G <= 6 chu
 template <int TPK, bool WRAP, bool STAGED, bool HALF>
 __device__ __forceinline__ void list_pass(const Dev& d, const Params& p, const Pos* __restrict__ q,
                                           const const_double* qc, int cs0, int kb, int mb, int c0, int total,
-                                          int start, int pre, int scnt, double shx, double shy, double shz,
-                                          int pre13, int& n_own, int& open, uint16_t* stage, uint8_t* mark) {
+                                          int start, int pre, int ekey, int scnt, double shx, double shy,
+                                          double shz, int pre13, int& n_own, int& open, uint16_t* stage,
+                                          uint8_t* mark) {
     constexpr int G = WRAP ? 3 : 6;
     static_assert(G * kWave <= kMarkBytes, "mark window");
     const int l = lane_id();
@@ -699,8 +895,10 @@ __device__ __forceinline__ void list_pass(const Dev& d, const Params& p, const P
             open = __builtin_amdgcn_readlane(run, 63);
             const int sc = max(run - 1, 0);  // last stencil cell whose range starts at or before ci
             // shuffles run on every lane: a bpermute from an inactive lane reads 0
-            const int base_sc = __shfl(sbase, sc), pre_sc = __shfl(pre, sc);
-            ent[k] = (uint32_t)((sc << kOffBits) | ((ci - pre_sc) & (kMaxCellCount - 1)));
+            const int base_sc = __shfl(sbase, sc), ek_sc = __shfl(ekey, sc);
+            // gather format: stencil cell << 11 | rank; row-tile format: the staged record's
+            // LDS byte offset (12-byte records)
+            ent[k] = (uint32_t)(ek_sc + ci) * (p.tile ? (uint32_t)sizeof(U3) : 1u);
             // 32-bit byte offset from the (scalar) array base: slots stay below 2^27
             const uint32_t boff = (uint32_t)(valid ? base_sc + ci : cs0) * (uint32_t)sizeof(Pos);
             const Pos qj = *reinterpret_cast<const Pos*>(reinterpret_cast<const char*>(q) + boff);
@@ -857,6 +1055,21 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7, 8))) 
         const bool wrap = __ballot(img) != 0ull;  // uniform: this cell touches the box boundary
         const int incl = wave_incl_sum(cnt);
         const int pre = incl - cnt;
+        // entry of candidate ci of stencil cell s = l: ekey + ci (gather format: s << 11
+        // plus its rank; row-tile format: its index in the staged region of the home
+        // cell's row tile, whose piece p = r * 3 + side holds unwrapped cells in order)
+        int ekey = (l << kOffBits) - pre;
+        if (p.tile) {
+            const int4 tr = d.rtile[ld_const(d.cell_rt + c)];
+            int ps0 = 0, plen = 0, pox, poy, poz;
+            if (l < 27) tile_piece(d, g, cy, cz, tr.z, tr.w, l, ps0, plen, pox, poy, poz);
+            const int pbase = wave_incl_sum(plen) - plen;
+            const int r = l / 3, x = cx + l % 3 - 1;
+            const int pc = r * 3 + (x < 0 ? 0 : (x >= g.n[0] ? 2 : 1));
+            const int base_pc = __shfl(pbase, pc), s0_main = __shfl(ps0, r * 3 + 1);
+            const int ebase = base_pc + (pc == r * 3 + 1 ? start - s0_main : 0);
+            ekey = ebase - pre;
+        }
         const int total = __builtin_amdgcn_readlane(incl, 26);
         const int pre13 = __builtin_amdgcn_readlane(pre, 13);  // the home cell's first candidate
         const const_double* qc = (const const_double*)q;     // 4 doubles per particle
@@ -869,11 +1082,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7, 8))) 
                 int open = 0;  // no stencil cell open before the first candidate
                 if (wrap) {
                     for (int c0 = 0; c0 < total; c0 += 3 * kWave)
-                        list_pass<TPK, true, true, HALF>(d, p, q, qc, cs0, kb, mb, c0, total, start, pre, cnt, shx,
+                        list_pass<TPK, true, true, HALF>(d, p, q, qc, cs0, kb, mb, c0, total, start, pre, ekey, cnt, shx,
                                                          shy, shz, pre13, n_own, open, stage, mark);
                 } else {
                     for (int c0 = 0; c0 < total; c0 += 6 * kWave)
-                        list_pass<TPK, false, true, HALF>(d, p, q, qc, cs0, kb, mb, c0, total, start, pre, cnt, shx,
+                        list_pass<TPK, false, true, HALF>(d, p, q, qc, cs0, kb, mb, c0, total, start, pre, ekey, cnt, shx,
                                                           shy, shz, pre13, n_own, open, stage, mark);
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -904,12 +1117,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7, 8))) 
             } else if (wrap) {
                 int open = 0;
                 for (int c0 = 0; c0 < total; c0 += 3 * kWave)
-                    list_pass<TPK, true, false, HALF>(d, p, q, qc, cs0, kb, mb, c0, total, start, pre, cnt, shx, shy,
+                    list_pass<TPK, true, false, HALF>(d, p, q, qc, cs0, kb, mb, c0, total, start, pre, ekey, cnt, shx, shy,
                                                       shz, pre13, n_own, open, stage, mark);
             } else {
                 int open = 0;
                 for (int c0 = 0; c0 < total; c0 += 6 * kWave)
-                    list_pass<TPK, false, false, HALF>(d, p, q, qc, cs0, kb, mb, c0, total, start, pre, cnt, shx,
+                    list_pass<TPK, false, false, HALF>(d, p, q, qc, cs0, kb, mb, c0, total, start, pre, ekey, cnt, shx,
                                                        shy, shz, pre13, n_own, open, stage, mark);
             }
             if (l < mb) {
@@ -1073,26 +1286,12 @@ __device__ __forceinline__ void force_finish(const Dev& d, const Params& p, cons
 constexpr int kHomeMax = 12;  // distinct key cells per wavefront served from LDS
 constexpr int kAccCap = 512;  // half list: partner accumulators per wavefront in LDS
 
-template <int PREC>
-struct ForceTab {
-    using Rec = uint32_t;  // FP64: start slot | image code << 27
-};
-template <>
-struct ForceTab<MD_PREC_FP32_MIXED> {
-    using Rec = int32_t;  // FP32-mixed: start slot (the stencil offsets o * uoff depend on s only)
-};
-
-// Record of stencil cell s of the cell with packed coordinates cc.
-template <int PREC>
-__device__ __forceinline__ typename ForceTab<PREC>::Rec force_rec(const Dev& d, uint32_t cc, int s,
-                                                                  const BoxGeom& g) {
+// Record of stencil cell s of the cell with packed coordinates cc: its start slot
+// and the periodic image code of the partners in it (start | code << 27).
+__device__ __forceinline__ uint32_t force_rec(const Dev& d, uint32_t cc, int s, const BoxGeom& g) {
     uint32_t img;
     const int nc = stencil_cell(cc, s, g, &img);
-    if constexpr (PREC == MD_PREC_FP64) {
-        return (uint32_t)d.cell_start[nc] | (img << kIdxBits);
-    } else {
-        return d.cell_start[nc];
-    }
+    return (uint32_t)d.cell_start[nc] | (img << kIdxBits);
 }
 
 // HALF (half list, kForceOnly, one lane per key): the reaction -f d of every pair
@@ -1104,13 +1303,13 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Params p) {
     constexpr int K = kWave / TPK;
     constexpr int U = 8;  // entries per iteration (one 16-byte chunk)
     constexpr bool MIX = PREC == MD_PREC_FP32_MIXED;
-    using Rec = typename ForceTab<PREC>::Rec;
+    using Rec = uint32_t;
     // FP64: image term per code, one 27-entry array per axis (8-byte words read by code)
     __shared__ double shift[MIX ? 1 : kBlock / kWave][3 * 27];
     __shared__ uint32_t home_cc[kBlock / kWave][kWave];
     __shared__ Rec tab[kBlock / kWave][kHomeMax * 27];
-    // FP32-mixed: stencil offset o * uoff of stencil cell s, one array per axis: 4-byte
-    // words read by stencil index, so lanes spread over the banks (or share a word)
+    // FP32-mixed: image term -r * n * uoff (modulo 2^32) of image code r, one array per
+    // axis: 4-byte words read by code, so lanes spread over the banks (or share a word)
     __shared__ int32_t soff[MIX ? kBlock / kWave : 1][MIX ? 3 * 27 : 1];
     const int l = lane_id(), wib = wave_in_block(), sub = l % TPK;
     const int lw = xcd_block(blockIdx.x, gridDim.x) * 4 + wib;
@@ -1127,9 +1326,9 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Params p) {
     } else {
         if (l < 27) {
             const BoxGeom& gb = d.geom[b];
-            soff[wib][l] = (l % 3 - 1) * gb.uoff[0];
-            soff[wib][27 + l] = ((l / 3) % 3 - 1) * gb.uoff[1];
-            soff[wib][54 + l] = (l / 9 - 1) * gb.uoff[2];
+            soff[wib][l] = img_units(l % 3 - 1, gb.n[0], gb.uoff[0]);
+            soff[wib][27 + l] = img_units((l / 3) % 3 - 1, gb.n[1], gb.uoff[1]);
+            soff[wib][54 + l] = img_units(l / 9 - 1, gb.n[2], gb.uoff[2]);
         }
     }
     __syncthreads();
@@ -1156,7 +1355,7 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Params p) {
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         for (int idx = l; idx < nhome * 27; idx += kWave) {
             const int hh = idx / 27;
-            tab[wib][idx] = force_rec<PREC>(d, home_cc[wib][hh], idx - hh * 27, g);
+            tab[wib][idx] = force_rec(d, home_cc[wib][hh], idx - hh * 27, g);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -1246,7 +1445,7 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Params p) {
             if constexpr (TB)
                 return tb[s];
             else
-                return force_rec<PREC>(d, cc, (int)s, g);
+                return force_rec(d, cc, (int)s, g);
         };
         // entry k of a chunk: stencil cell and rank (8 entries in 4 words)
         auto ent_s = [](const uint4& raw, int k) -> uint32_t {
@@ -1329,20 +1528,24 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Params p) {
         } else {
             const int32_t* __restrict__ u = d.u[sq];
             const int4 ui = units3(qi, cc, g);  // own coordinate from the record: no extra load
-            const int nux = -ui.x, nuy = -ui.y, nuz = -ui.z;
             // lengths stay in fixed-point units: r^2 in units^2, 1/r^2 rescaled once
             const float rc2u = g.rc2u, lam2inv = g.lam2inv, lam2 = g.lam * g.lam, c2x8 = 8.0f * p.c2f;
+            const float irc2 = p.irc2f;
+            // the clamp serves full lists only: a half list's reactions go to partners directly
+            const bool clampf = p.clamp != 0 && !HALF;
             const double lamd = (double)g.lam;
             float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f, pes = 0.f, virs = 0.f;
             auto chunk = [&](int c, auto chk_c, int valid) {
                 constexpr bool CHK = decltype(chk_c)::value;
                 const uint4 raw = raw_next;
-                uint32_t st[U], js[U];
+                uint32_t st[U], js[U], img[U];
 #pragma unroll
                 for (int k = 0; k < U; ++k) {
                     const bool ok = !CHK || k < valid;
                     st[k] = ok ? ent_s(raw, k) : 13u;
-                    js[k] = ok ? (uint32_t)rec(st[k]) + ent_r(raw, k) : (uint32_t)key;
+                    const uint32_t t = rec(st[k]);
+                    js[k] = ok ? (t & kIdxMask) + ent_r(raw, k) : (uint32_t)key;
+                    img[k] = ok ? t >> kIdxBits : 13u;
                 }
                 int4 uj[U];
 #pragma unroll
@@ -1357,16 +1560,20 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Params p) {
                 float bx = 0.f, by = 0.f, bz = 0.f;  // plain FP32 sum of this batch
 #pragma unroll
                 for (int k = 0; k < U; ++k) {
-                    const int* __restrict__ so = soff[wib] + st[k];
-                    // exact integer separation in units, one rounding to FP32
-                    const float dx = (float)(uj[k].x + so[0] + nux);
-                    const float dy = (float)(uj[k].y + so[27] + nuy);
-                    const float dz = (float)(uj[k].z + so[54] + nuz);
+                    const int* __restrict__ so = soff[wib] + img[k];
+                    // exact integer separation in units (modulo 2^32, far inside int32),
+                    // one rounding to FP32
+                    const float dx = (float)(int)((uint32_t)uj[k].x + (uint32_t)so[0] - (uint32_t)ui.x);
+                    const float dy = (float)(int)((uint32_t)uj[k].y + (uint32_t)so[27] - (uint32_t)ui.y);
+                    const float dz = (float)(int)((uint32_t)uj[k].z + (uint32_t)so[54] - (uint32_t)ui.z);
                     const float r2 = dx * dx + dy * dy + dz * dz;
                     const bool in = (!CHK || k < valid) && r2 < rc2u;
-                    const float inv = __builtin_amdgcn_rcpf(r2) * lam2inv;  // 1/r^2 in length units
+                    const float inv0 = __builtin_amdgcn_rcpf(r2) * lam2inv;  // 1/r^2 in length units
+                    // Eq. 1 (f(rc) = 0): entries beyond rc evaluated at rc, as the row-tile pass does
+                    const float inv = clampf ? fmaxf(inv0, irc2) : inv0;
                     const float inv3 = inv * inv * inv;
-                    const float f = in ? (inv3 * inv) * (24.0f - 48.0f * inv3) + c2x8 : 0.0f;
+                    const float fv = (inv3 * inv) * (24.0f - 48.0f * inv3) + c2x8;
+                    const float f = (clampf ? (!CHK || k < valid) : in) ? fv : 0.0f;
                     const float fdx = f * dx, fdy = f * dy, fdz = f * dz;
                     bx += fdx;
                     by += fdy;
@@ -1383,7 +1590,8 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Params p) {
                         }
                     }
                     if (ENERGY) {
-                        pes += in ? 2.0f * (inv3 * inv3 - inv3 + p.c2f * (r2 * lam2) + p.c0f) : 0.0f;
+                        const float i3 = inv0 * inv0 * inv0;
+                        pes += in ? 2.0f * (i3 * i3 - i3 + p.c2f * (r2 * lam2) + p.c0f) : 0.0f;
                         virs += in ? f * r2 : 0.0f;  // units^2: times lam^2 below
                     }
                 }
@@ -1434,288 +1642,243 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Params p) {
                                                 pe, vir, f_done);
 }
 
-// FP32-mixed force pass with LDS-staged partner tiles (one lane per key).  The
-// 256 keys of a block live in one or two rows of cells; every partner of theirs
-// lies in the 9 neighbouring rows (dy, dz in {-1,0,1}) of each home row, over the
-// x range of the home cells widened by one cell each side (periodic wrap adds at
-// most one cell per end).  Those row pieces are contiguous runs of slots: the
-// block copies them once, coalesced, into LDS, already shifted into the home
-// row's frame (fixed-point units; x measured from the first home cell, y and z
-// from the home row), so a pair separation is one integer subtraction with
-// wrap-around and partner reads are LDS reads.  Blocks whose keys span more rows,
-// two boxes, or more than kTileCap partners, and wavefronts with more than
-// kHomeMax home cells, gather from global memory instead.
-constexpr int kTileCap = 3072;    // staged partner records per block
-constexpr int kTileParts = 64;    // pieces: 2 home rows x 9 rows x (left wrap, main, right wrap)
-constexpr int kTileChunks = 128;  // 64-record copy chunks
-
-template <int MODE, bool ENERGY>
-__global__ __launch_bounds__(kBlock) void k_force_tile(Dev d, Params p) {
-    constexpr int U = 8;
-    constexpr int kTabPer = (kHomeMax * 27 + kWave - 1) / kWave;  // table entries per lane
-    __shared__ int32_t tx[kTileCap], ty[kTileCap], tz[kTileCap];
-    __shared__ uint16_t ltab[kBlock / kWave][kHomeMax * 27];
-    __shared__ uint32_t home_cc[kBlock / kWave][kHomeMax];
-    __shared__ int32_t pt_s0[kTileParts], pt_len[kTileParts], pt_base[kTileParts];
-    __shared__ int32_t pt_ay[kTileParts], pt_az[kTileParts], pt_xk[kTileParts];
-    __shared__ int32_t ch_part[kTileChunks], ch_off[kTileChunks];
-    __shared__ int32_t blk[4];  // tiled flag, chunk count, first home row, x of the first home cell
-    const int l = lane_id(), wib = threadIdx.x >> 6;
-    const int lw0 = xcd_block(blockIdx.x, gridDim.x) * 4;
-    const int lw = lw0 + wib;
-    const bool wave_ok = lw < p.nwave;
-
-    // this wavefront's keys, their box and their home cells
-    const int b = __builtin_amdgcn_readfirstlane(d.wave_box[wave_ok ? lw : lw0]);
-    const BoxGeom& g = d.geom[b];  // b is uniform: scalar loads
-    const int sq = d.st[b].sq;
-    const int nx = g.n[0], ny = g.n[1];
-    const int key = lw * kWave + l;
-    const bool active = wave_ok && key - g.slot_off < g.npart;
-    const Pos qi = d.q[sq][active ? key : g.slot_off];
-    const uint32_t cc = active ? qi.cc : 0xffffffffu;
-    const uint32_t cprev = __shfl_up(cc, 1);
-    const bool head = active && (l == 0 || cprev != cc);
-    const unsigned long long hm = __ballot(head);
-    const int nhome = __popcll(hm);
-    const int h = __popcll(hm & (l == 63 ? ~0ull : ((2ull << l) - 1ull))) - 1;
-    const bool few_homes = nhome <= kHomeMax;  // uniform over the wavefront
-    // stencil-cell starts for this wavefront's table, fetched while the block
-    // geometry is worked out: tcs = start slot, tpp = piece without the home row
-    // term, trow = the home cell's row
-    int tcs[kTabPer], tpp[kTabPer], trow[kTabPer];
-    if (few_homes) {
-        if (head) home_cc[wib][h] = cc;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+// FP32-mixed pair forces from a row tile staged in LDS (row-tile list format, one
+// lane per key).  A block takes a row tile: wavefront 0 works out the 27 pieces of
+// its staged region, the block copies them from the fixed-point array into LDS as
+// 16-byte records (coalesced runs of slots; the pieces' image terms added, so every
+// record is in the unwrapped frame of the home row), then each lane walks one key's
+// list, whose entries are the records' LDS byte offsets.  A pair separation is one
+// integer subtraction per axis (exact, modulo 2^32) and one conversion to FP32; the
+// arithmetic after that, and the summation order, are those of the gather kernel,
+// so both give the same forces bit for bit.  The integration (kicks, drift,
+// fixed-point re-encoding, DUTC maximum) follows in the same pass; energy partials
+// are summed per tile in a fixed order.  A tile whose region exceeds scap (the
+// host then falls back to the gather format and replays) is skipped.
+// CLAMP (the Eq. 1 cutoff, whose f(rc) is 0): a list entry beyond rc is evaluated at
+// rc instead of being masked, 1/r^2 = max(1/r^2, 1/rc^2) (one instruction for a
+// compare and a select); f(rc) rounds to a few 1e-9 in FP32.
+template <int MODE, bool ENERGY, bool CLAMP>
+__global__ __launch_bounds__(kRtBlock) void k_force_t(Dev d, Params p) {
+    constexpr int NW = kRtBlock / kWave;  // wavefronts per block
+    constexpr int U = 8;       // entries per 16-byte list chunk
+    constexpr int kPc = 27;    // pieces of a staged region
+    constexpr int kCopy = 4;   // copy chunks per wavefront in flight
+    extern __shared__ U3 stg[];  // p.scap records of 12 bytes
+    __shared__ double red[3][NW];
+    const int l = lane_id(), wib = wave_in_block();
+    const int ntl = ld_const(d.ntiles);
+    for (int t = xcd_block(blockIdx.x, gridDim.x); t < ntl; t += gridDim.x) {
+        const int4 tr = d.rtile[t];
+        const int b = __builtin_amdgcn_readfirstlane(tr.x);
+        const BoxGeom g = ld_geom(d.geom + b);
+        const int lr = __builtin_amdgcn_readfirstlane(tr.y), xa = __builtin_amdgcn_readfirstlane(tr.z),
+                  xb = __builtin_amdgcn_readfirstlane(tr.w);
+        const int cy = lr % g.n[1], cz = lr / g.n[1];
+        const int sq = ld_const(&d.st[b].sq), sp = ld_const(&d.st[b].sp);
+        // every wavefront works out the pieces itself (lane p holds piece p): no barrier
+        int ps0 = 0, plen = 0, pox = 0, poy = 0, poz = 0;
+        if (l < kPc) tile_piece(d, g, cy, cz, xa, xb, l, ps0, plen, pox, poy, poz);
+        const int pincl = wave_incl_sum(plen);
+        const int S = __builtin_amdgcn_readlane(pincl, kPc - 1);
+        // keys: the home cells [xa, xb) of the home row (inside piece 13)
+        const int rowc = g.cell_off + (cz * g.n[1] + cy) * g.n[0];
+        const int k0 = ld_const(d.cell_start + rowc + xa);
+        const int k1 = ld_const(d.cell_start + rowc + xb - 1) + ld_const(d.cell_cnt + rowc + xb - 1);
+        if (S > p.scap) continue;  // uniform over the block; nothing staged yet
+        // this thread's first key: its record, velocity and first two list chunks, fetched
+        // while the block stages (a list holds at least 8 entries per lane, 16 when rows >= 16)
+        int kb = k0;
+        int key = kb + (int)threadIdx.x;
+        bool active = key < k1;
+        int ks = active ? key : k0;
+        Pos qi = d.q[sq][ks];
+        double v0x = ld_stream(d.vx[sp] + ks), v0y = ld_stream(d.vy[sp] + ks), v0z = ld_stream(d.vz[sp] + ks);
+        const uint4* __restrict__ l4 = reinterpret_cast<const uint4*>(d.list) + (size_t)(ks >> 6) * p.rows * 8 + (ks & 63);
+        uint4 raw_a = ld_stream(l4);
+        uint4 raw_b = p.rows >= 16 ? ld_stream(l4 + kWave) : make_uint4(0u, 0u, 0u, 0u);
+        // stage: 64-record chunk c of the pieces goes to wavefront c % NW; the chunk's
+        // piece is the number of pieces whose chunks all lie before it.  Per piece p
+        // (first chunk cs): record c * 64 + l of the pieces' chunk space comes from slot
+        // src_p + c * 64 + l and goes to dst_p + c * 64 + l while c * 64 + l < end_p.
+        {
+            const int pch = (plen + kWave - 1) >> 6;  // 64-record copy chunks of piece l
+            const int chincl = wave_incl_sum(pch);
+            const int NC = __builtin_amdgcn_readlane(chincl, kPc - 1);
+            const int cs = chincl - pch;
+            const int src = ps0 - kWave * cs, dst = (pincl - plen) - kWave * cs, end = plen + kWave * cs;
+            const int32_t* __restrict__ u = d.u[sq];
+            for (int c0 = wib; c0 < NC; c0 += NW * kCopy) {
+                U3 v[kCopy];
+                int at[kCopy], ox[kCopy], oy[kCopy], oz[kCopy];
 #pragma unroll
-        for (int k = 0; k < kTabPer; ++k) {
-            const int idx = l + k * kWave;
-            tpp[k] = 0;
-            tcs[k] = 0;
-            trow[k] = 0;
-            if (idx < nhome * 27) {
-                const int hh = idx / 27, st = idx - hh * 27;
-                const uint32_t hc = home_cc[wib][hh];
-                const int v = (int)(hc & 1023) + st % 3 - 1;
-                tpp[k] = (st / 3) * 3 + (v < 0 ? 0 : (v >= nx ? 2 : 1));
-                trow[k] = (int)(hc >> 20) * ny + (int)((hc >> 10) & 1023);
-                uint32_t img;
-                tcs[k] = d.cell_start[stencil_cell(hc, st, g, &img)];
-            }
-        }
-    }
-
-    // ---- block geometry and the piece table (wavefront 0); piece lane
-    // hr * 27 + rr * 3 + side = (home row hr, stencil row rr, side)
-    if (wib == 0) {
-        bool ok = lw0 + 3 < p.nwave && d.wave_box[lw0 + 3] == b;  // four full wavefronts of one box
-        const int kf = lw0 * kWave, kl = min(kf + kBlock - 1, g.slot_off + g.npart - 1);
-        const uint32_t ccf = __builtin_amdgcn_readfirstlane(d.q[sq][kf].cc);
-        const uint32_t ccl = __builtin_amdgcn_readfirstlane(d.q[sq][kl].cc);
-        const int cyf = (ccf >> 10) & 1023, czf = ccf >> 20;
-        const int cxl = ccl & 1023, cyl = (ccl >> 10) & 1023, czl = ccl >> 20;
-        const int rowf = czf * ny + cyf, nhr = czl * ny + cyl - rowf + 1;
-        const int xa0 = ccf & 1023, xb0 = nhr == 1 ? cxl : nx - 1, xb1 = cxl;  // home row 1 starts at x = 0
-        ok = ok && (nhr == 1 || nhr == 2) && xb0 - xa0 + 3 <= nx && (nhr == 1 || xb1 + 3 <= nx);
-        int len = 0, s0 = 0, ay = 0, az = 0, xk = 0;
-        if (ok && l < nhr * 27) {
-            const int hr = l / 27, rr = (l % 27) / 3, side = l % 3;
-            const int dy = rr % 3 - 1, dz = rr / 3 - 1;
-            const int xa = hr == 0 ? xa0 : 0, xb = hr == 0 ? xb0 : xb1;
-            int y = (hr == 0 ? cyf : cyl) + dy, z = (hr == 0 ? czf : czl) + dz;
-            y = y < 0 ? y + ny : (y >= ny ? y - ny : y);
-            z = z < 0 ? z + g.n[2] : (z >= g.n[2] ? z - g.n[2] : z);
-            // side 0: virtual x = -1 is real nx - 1; side 2: virtual x = nx is real 0
-            if (side == 1 || (side == 0 && xa == 0) || (side == 2 && xb == nx - 1)) {
-                const int x0 = side == 0 ? nx - 1 : (side == 2 ? 0 : max(xa - 1, 0));
-                const int x1 = side == 0 ? nx - 1 : (side == 2 ? 0 : min(xb + 1, nx - 1));
-                const int rowc = g.cell_off + (z * ny + y) * nx;
-                s0 = d.cell_start[rowc + x0];
-                len = d.cell_start[rowc + x1] + d.cell_cnt[rowc + x1] - s0;
-                ay = dy * g.uoff[1];
-                az = dz * g.uoff[2];
-                xk = (side == 0 ? -nx : (side == 2 ? nx : 0)) - xa;
-            }
-        }
-        const int incl = wave_incl_scan(len);
-        const int nchk = (len + kWave - 1) >> 6;
-        const int cincl = wave_incl_scan(nchk);
-        const int NC = __builtin_amdgcn_readlane(cincl, 63);
-        ok = ok && __builtin_amdgcn_readlane(incl, 63) <= kTileCap && NC <= kTileChunks;
-        if (ok) {
-            pt_s0[l] = s0;
-            pt_len[l] = len;
-            pt_base[l] = incl - len;
-            pt_ay[l] = ay;
-            pt_az[l] = az;
-            pt_xk[l] = xk;
-            for (int c = 0; c < nchk; ++c) {
-                ch_part[cincl - nchk + c] = l;
-                ch_off[cincl - nchk + c] = c * kWave;
-            }
-        }
-        if (l == 0) {
-            blk[0] = ok ? 1 : 0;
-            blk[1] = NC;
-            blk[2] = rowf;
-            blk[3] = xa0;
-        }
-    }
-    __syncthreads();
-    const bool tiled = blk[0] != 0;  // uniform over the block
-    const int rowf = blk[2], xa0 = blk[3];
-    const bool use_tile = tiled && few_homes;  // uniform over the wavefront
-    if (tiled) {
-        // ---- copy the pieces: chunk c (64 records of one piece) goes to wavefront c % 4
-        const int NC = blk[1];
-        const int32_t* __restrict__ u = d.u[sq];
-        const uint32_t uox = (uint32_t)g.uoff[0];
-        for (int c0 = wib; c0 < NC; c0 += 4 * 8) {
-            int4 v[8];
-            int li[8], pcs[8];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const int c = c0 + 4 * k;
-                li[k] = -1;
-                if (c < NC) {  // uniform
-                    const int pc = ch_part[c], i = ch_off[c] + l;
-                    pcs[k] = pc;
-                    if (i < pt_len[pc]) {
-                        v[k] = get_u(u, pt_s0[pc] + i);
-                        v[k].w = (int)(d.q[sq][pt_s0[pc] + i].cc & 1023u);  // its cell's x index
-                        li[k] = pt_base[pc] + i;
+                for (int k = 0; k < kCopy; ++k) {
+                    const int c = c0 + NW * k;
+                    at[k] = -1;
+                    if (c < NC) {  // uniform
+                        const int pc = __popcll(__ballot(l < kPc && chincl <= c));
+                        const int i = c * kWave + l;
+                        ox[k] = __builtin_amdgcn_readlane(pox, pc);
+                        oy[k] = __builtin_amdgcn_readlane(poy, pc);
+                        oz[k] = __builtin_amdgcn_readlane(poz, pc);
+                        if (i < __builtin_amdgcn_readlane(end, pc)) {
+                            v[k] = *reinterpret_cast<const U3*>(u + 3 * (__builtin_amdgcn_readlane(src, pc) + i));
+                            at[k] = __builtin_amdgcn_readlane(dst, pc) + i;
+                        }
                     }
                 }
-            }
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                if (li[k] >= 0) {
-                    // x in the home row's frame, modulo 2^32 (differences stay exact)
-                    const int pc = pcs[k];
-                    tx[li[k]] = (int)((uint32_t)v[k].x + (uint32_t)(v[k].w + pt_xk[pc]) * uox);
-                    ty[li[k]] = v[k].y + pt_ay[pc];
-                    tz[li[k]] = v[k].z + pt_az[pc];
-                }
+                for (int k = 0; k < kCopy; ++k)
+                    if (at[k] >= 0)
+                        stg[at[k]] = U3{(int)((uint32_t)v[k].x + (uint32_t)ox[k]), (int)((uint32_t)v[k].y + (uint32_t)oy[k]),
+                                        (int)((uint32_t)v[k].z + (uint32_t)oz[k])};
             }
         }
-    }
-    if (use_tile) {
-#pragma unroll
-        for (int k = 0; k < kTabPer; ++k) {
-            const int idx = l + k * kWave;
-            if (idx < nhome * 27) {
-                const int pp = (trow[k] == rowf ? 0 : 27) + tpp[k];
-                ltab[wib][idx] = (uint16_t)(pt_base[pp] + tcs[k] - pt_s0[pp]);
-            }
-        }
-    }
-    __syncthreads();
-    if (!wave_ok) return;
-    const int sp = d.st[b].sp;
-    double Fx = 0.0, Fy = 0.0, Fz = 0.0, pe = 0.0, vir = 0.0;
-    if (active) {
-        const int nl = qi.cnt;
-        const int nfull = nl >> 3, ntail = nl & 7;
-        const uint4* __restrict__ l4 = reinterpret_cast<const uint4*>(d.list + (size_t)lw * p.rows * kWave) + l;
-        auto ent_s = [](const uint4& raw, int k) -> uint32_t {
-            const uint32_t w = k < 2 ? raw.x : k < 4 ? raw.y : k < 6 ? raw.z : raw.w;
-            return (k & 1) ? w >> 27 : (w >> kOffBits) & 31u;
-        };
-        auto ent_r = [](const uint4& raw, int k) -> uint32_t {
-            const uint32_t w = k < 2 ? raw.x : k < 4 ? raw.y : k < 6 ? raw.z : raw.w;
-            return (k & 1) ? (w >> 16) & (kMaxCellCount - 1) : w & (kMaxCellCount - 1);
-        };
-        const int4 ui = units3(qi, cc, g);
+        __syncthreads();
         const float rc2u = g.rc2u, lam2inv = g.lam2inv, lam2 = g.lam * g.lam, c2x8 = 8.0f * p.c2f;
-        float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f, pes = 0.f, virs = 0.f;
-        uint4 raw_next = nl > 0 ? ld_stream(l4) : make_uint4(0u, 0u, 0u, 0u);
-        // one chunk of 8 entries: fetch the 8 partners, then the pair math on exact
-        // integer separations (one rounding to FP32 each)
-        auto pairs = [&](auto tile_c) {
-            constexpr bool TL = decltype(tile_c)::value;
-            const uint16_t* __restrict__ tb = ltab[wib] + h * 27;
-            // this key in the frame of the staged partners
-            const int hr = (int)((cc >> 20) * ny + ((cc >> 10) & 1023)) == rowf ? 0 : 1;
-            const uint32_t kx = (uint32_t)ui.x + (uint32_t)(ui.w - (hr == 0 ? xa0 : 0)) * (uint32_t)g.uoff[0];
-            const int32_t* __restrict__ u = d.u[sq];
+        const float irc2 = p.irc2f;  // 1 / rc^2 in length units (FP32)
+        const double lam = (double)g.lam;  // units back to lengths (a power of two)
+        const char* __restrict__ sb = reinterpret_cast<const char*>(stg);
+        double e_ke = 0.0, e_pe = 0.0, e_vir = 0.0;
+        for (;;) {  // rounds of kRtBlock keys: a one-cell tile may hold more (uniform)
+            const uint32_t cc = qi.cc;
+            const int4 ui = units3(qi, cc, g);  // own coordinate, from the record: no extra load
+            const uint32_t kx = (uint32_t)ui.x, ky = (uint32_t)ui.y, kz = (uint32_t)ui.z;
+            const int nl = active ? qi.cnt : 0;
+            const int nfull = nl >> 3, ntail = nl & 7;
+            float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy2 = 0.f, cz2 = 0.f, pes = 0.f, virs = 0.f;
+            // list chunks two ahead: the next chunk's load has a whole chunk of math to land
             auto chunk = [&](int c, auto chk_c, int valid) {
                 constexpr bool CHK = decltype(chk_c)::value;
-                const uint4 raw = raw_next;
-                int dxi[U], dyi[U], dzi[U];
-                if constexpr (TL) {
-                    int li[U];
+                const uint4 raw = raw_a;
+                U3 rj[U];
 #pragma unroll
-                    for (int k = 0; k < U; ++k) {
-                        const bool ok = !CHK || k < valid;
-                        li[k] = (int)tb[ok ? ent_s(raw, k) : 13u] + (ok ? (int)ent_r(raw, k) : 0);
-                    }
-                    if (!CHK && (c + 1 < nfull || ntail)) raw_next = ld_stream(l4 + (size_t)(c + 1) * kWave);
-#pragma unroll
-                    for (int k = 0; k < U; ++k) {
-                        dxi[k] = (int)((uint32_t)tx[li[k]] - kx);
-                        dyi[k] = ty[li[k]] - ui.y;
-                        dzi[k] = tz[li[k]] - ui.z;
-                    }
-                } else {
-                    uint32_t st[U], js[U];
-#pragma unroll
-                    for (int k = 0; k < U; ++k) {
-                        const bool ok = !CHK || k < valid;
-                        st[k] = ok ? ent_s(raw, k) : 13u;
-                        js[k] = ok ? (uint32_t)force_rec<MD_PREC_FP32_MIXED>(d, cc, (int)st[k], g) + ent_r(raw, k)
-                                   : (uint32_t)key;
-                    }
-                    int4 uj[U];
-#pragma unroll
-                    for (int k = 0; k < U; ++k) uj[k] = get_u(u, js[k]);
-                    if (!CHK && (c + 1 < nfull || ntail)) raw_next = ld_stream(l4 + (size_t)(c + 1) * kWave);
-#pragma unroll
-                    for (int k = 0; k < U; ++k) {
-                        const int so = (int)st[k];
-                        dxi[k] = uj[k].x - ui.x + (so % 3 - 1) * g.uoff[0];
-                        dyi[k] = uj[k].y - ui.y + ((so / 3) % 3 - 1) * g.uoff[1];
-                        dzi[k] = uj[k].z - ui.z + (so / 9 - 1) * g.uoff[2];
-                    }
+                for (int k = 0; k < U; ++k) {
+                    const uint32_t w = k < 2 ? raw.x : k < 4 ? raw.y : k < 6 ? raw.z : raw.w;
+                    uint32_t off = (k & 1) ? w >> 16 : w & 0xffffu;
+                    if (CHK && k >= valid) off = 0u;  // padding entries: any record, masked below
+                    rj[k] = *reinterpret_cast<const U3*>(sb + off);
+                }
+                if (!CHK) {
+                    raw_a = raw_b;
+                    if (8 * (c + 2) < nl) raw_b = ld_stream(l4 + (size_t)(c + 2) * kWave);
                 }
                 float bx = 0.f, by = 0.f, bz = 0.f;  // plain FP32 sum of this batch
 #pragma unroll
                 for (int k = 0; k < U; ++k) {
-                    const float dx = (float)dxi[k], dy = (float)dyi[k], dz = (float)dzi[k];
+                    // exact integer separation in units, one rounding to FP32
+                    const float dx = (float)(int)((uint32_t)rj[k].x - kx);
+                    const float dy = (float)(int)((uint32_t)rj[k].y - ky);
+                    const float dz = (float)(int)((uint32_t)rj[k].z - kz);
                     const float r2 = dx * dx + dy * dy + dz * dz;
                     const bool in = (!CHK || k < valid) && r2 < rc2u;
-                    const float inv = __builtin_amdgcn_rcpf(r2) * lam2inv;  // 1/r^2 in length units
+                    const float inv0 = __builtin_amdgcn_rcpf(r2) * lam2inv;  // 1/r^2 in length units
+                    const float inv = CLAMP ? fmaxf(inv0, irc2) : inv0;
                     const float inv3 = inv * inv * inv;
-                    const float f = in ? (inv3 * inv) * (24.0f - 48.0f * inv3) + c2x8 : 0.0f;
+                    const float fv = (inv3 * inv) * (24.0f - 48.0f * inv3) + c2x8;
+                    const float f = CLAMP && !CHK ? fv : (in || (CLAMP && k < valid) ? fv : 0.0f);
                     bx += f * dx;
                     by += f * dy;
                     bz += f * dz;
                     if (ENERGY) {
-                        pes += in ? 2.0f * (inv3 * inv3 - inv3 + p.c2f * (r2 * lam2) + p.c0f) : 0.0f;
+                        const float i3 = inv0 * inv0 * inv0;
+                        pes += in ? 2.0f * (i3 * i3 - i3 + p.c2f * (r2 * lam2) + p.c0f) : 0.0f;
                         virs += in ? f * r2 : 0.0f;  // units^2: times lam^2 below
                     }
                 }
                 kahan_add(sx, cx, bx);  // compensated across batches
-                kahan_add(sy, cy, by);
-                kahan_add(sz, cz, bz);
+                kahan_add(sy, cy2, by);
+                kahan_add(sz, cz2, bz);
             };
             for (int c = 0; c < nfull; ++c) chunk(c, std::false_type{}, U);
             if (ntail) chunk(nfull, std::true_type{}, ntail);
-        };
-        if (use_tile)
-            pairs(std::true_type{});
-        else
-            pairs(std::false_type{});
-        const double lam = (double)g.lam;  // units back to lengths (a power of two)
-        Fx = ((double)sx - (double)cx) * lam;
-        Fy = ((double)sy - (double)cy) * lam;
-        Fz = ((double)sz - (double)cz) * lam;
-        pe = (double)pes;
-        vir = (double)virs * lam * lam;
+            const double Fx = ((double)sx - (double)cx) * lam;
+            const double Fy = ((double)sy - (double)cy2) * lam;
+            const double Fz = ((double)sz - (double)cz2) * lam;
+            double ke = 0.0, w2 = 0.0, m2 = 0.0;
+            if (active) {
+                if (MODE == kForceOnly) {
+                    d.fx[key] = Fx;
+                    d.fy[key] = Fy;
+                    d.fz[key] = Fz;
+                    if (ENERGY) ke = 0.5 * p.mass * norm2(v0x, v0y, v0z);
+                } else if (MODE == kForceEnd) {
+                    const double vx = kick(v0x, p.h, Fx);
+                    const double vy = kick(v0y, p.h, Fy);
+                    const double vz = kick(v0z, p.h, Fz);
+                    d.vx[sp][key] = vx;
+                    d.vy[sp][key] = vy;
+                    d.vz[sp][key] = vz;
+                    d.fx[key] = Fx;
+                    d.fy[key] = Fy;
+                    d.fz[key] = Fz;
+                    if (ENERGY) ke = 0.5 * p.mass * norm2(vx, vy, vz);
+                } else {  // kForceMid: close step n, open step n+1, drift, re-encode
+                    const double vx = kick(kick(v0x, p.h, Fx), p.h, Fx);
+                    const double vy = kick(kick(v0y, p.h, Fy), p.h, Fy);
+                    const double vz = kick(kick(v0z, p.h, Fz), p.h, Fz);
+                    st_stream(d.vx[sp] + key, vx);
+                    st_stream(d.vy[sp] + key, vy);
+                    st_stream(d.vz[sp] + key, vz);
+                    const Pos xn = make_pos(drift(qi.x, p.dt, vx), drift(qi.y, p.dt, vy), drift(qi.z, p.dt, vz), cc,
+                                            qi.cnt);
+                    d.q[sq ^ 1][key] = xn;
+                    put_u(d.u[sq ^ 1], key, units3(xn, cc, g));
+                    w2 = norm2(vx, vy, vz);
+                    if (d.qb) {
+                        const double4 xbq = d.qb[key];
+                        m2 = norm2(xn.x - xbq.x, xn.y - xbq.y, xn.z - xbq.z);
+                    }
+                }
+            }
+            if (MODE == kForceMid) {
+                const double wm = wave_max(w2);
+                if (l == 0) stripe_put(d.vmax_s, b, t * 4 + wib, wm);
+                if (d.qb) {
+                    const double mm = wave_max(m2);
+                    if (l == 0) stripe_put(d.disp_s, b, t * 4 + wib, mm);
+                }
+            }
+            if (ENERGY && active) {
+                e_ke += ke;
+                e_pe += (double)pes;
+                e_vir += (double)virs * lam * lam;
+            }
+            kb += kRtBlock;
+            if (kb >= k1) break;
+            key = kb + (int)threadIdx.x;
+            active = key < k1;
+            ks = active ? key : k0;
+            qi = d.q[sq][ks];
+            v0x = ld_stream(d.vx[sp] + ks);
+            v0y = ld_stream(d.vy[sp] + ks);
+            v0z = ld_stream(d.vz[sp] + ks);
+            l4 = reinterpret_cast<const uint4*>(d.list) + (size_t)(ks >> 6) * p.rows * 8 + (ks & 63);
+            raw_a = ld_stream(l4);
+            raw_b = p.rows >= 16 ? ld_stream(l4 + kWave) : make_uint4(0u, 0u, 0u, 0u);
+        }
+        if (ENERGY) {  // the tile's partials, summed in a fixed order
+            const double ks = wave_sum(e_ke), ps = wave_sum(e_pe), vs = wave_sum(e_vir);
+            __syncthreads();  // red of the previous tile has been read
+            if (l == 0) {
+                red[0][wib] = ks;
+                red[1][wib] = ps;
+                red[2][wib] = vs;
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                double a0 = red[0][0], a1 = red[1][0], a2 = red[2][0];
+                for (int w = 1; w < NW; ++w) {
+                    a0 += red[0][w];
+                    a1 += red[1][w];
+                    a2 += red[2][w];
+                }
+                d.ke_part[t] = a0;
+                d.pe_part[t] = a1;
+                d.vir_part[t] = a2;
+            }
+        }
+        __syncthreads();  // the next tile's staging reuses the LDS
     }
-    force_finish<MD_PREC_FP32_MIXED, MODE, 1, ENERGY, false>(d, p, g, b, lw, key, active, qi, cc, sq, sp, Fx, Fy, Fz, pe,
-                                                      vir);
 }
 
 // Half-list steps: F is accumulated by atomics, so the integrator runs as its own
@@ -1827,11 +1990,25 @@ __device__ __forceinline__ void block_sum3(double& k, double& e, double& v) {
     __syncthreads();
 }
 
-__global__ __launch_bounds__(kBlock) void k_energy_segments(Dev d, Params p) {
+// Partials of box b: per list wavefront (K = 64 / tpk keys each), or per row tile
+// (tl) when the row-tile force kernel wrote them.
+__device__ __forceinline__ void part_range(const Dev& d, const Params& p, const BoxGeom& g, int b, int tl, int& w0,
+                                           int& w1) {
+    if (tl) {
+        w0 = d.box_t0[b];
+        w1 = d.box_t0[b + 1];
+    } else {
+        const int K = kWave / p.tpk;
+        w0 = g.slot_off / K;
+        w1 = (g.slot_off + g.nslot) / K;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_energy_segments(Dev d, Params p, int tl) {
     const int b = blockIdx.y, j = blockIdx.x;
     const BoxGeom& g = d.geom[b];
-    const int K = kWave / p.tpk;
-    const int w0 = g.slot_off / K, w1 = (g.slot_off + g.nslot) / K;
+    int w0, w1;
+    part_range(d, p, g, b, tl, w0, w1);
     const int a0 = w0 + j * kRedSeg, a1 = min(a0 + kRedSeg, w1);
     if (a0 >= w1) return;  // uniform over the block
     double k = 0.0, e = 0.0, v = 0.0;
@@ -1849,11 +2026,12 @@ __global__ __launch_bounds__(kBlock) void k_energy_segments(Dev d, Params p) {
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_energy_reduce(Dev d, Params p, int record, int thermo) {
+__global__ __launch_bounds__(kBlock) void k_energy_reduce(Dev d, Params p, int record, int thermo, int tl) {
     for (int b = blockIdx.x; b < p.nbox; b += gridDim.x) {
         const BoxGeom& g = d.geom[b];
-        const int K = kWave / p.tpk;
-        const int nseg = (g.nslot / K + kRedSeg - 1) / kRedSeg;
+        int w0, w1;
+        part_range(d, p, g, b, tl, w0, w1);
+        const int nseg = (w1 - w0 + kRedSeg - 1) / kRedSeg;
         double k = 0.0, e = 0.0, v = 0.0;
         for (int j = threadIdx.x; j < nseg; j += kBlock) {
             const double* r = d.red + ((size_t)b * p.redcap + j) * 3;
@@ -1947,6 +2125,8 @@ __global__ __launch_bounds__(kBlock) void k_verify(Dev d, Params p) {
         const Pos* q = d.q[d.st[b].sq];
         const Pos qi = q[s];
         const int n = d.cnt[s];
+        int ps0[27], plen[27];
+        if (p.tile) tile_pieces_of(d, g, qi.cc, ps0, plen);
         unsigned long long missed = 0;
         for (int j = g.slot_off; j < g.slot_off + g.npart; ++j) {
             if (j == s) continue;
@@ -1959,8 +2139,10 @@ __global__ __launch_bounds__(kBlock) void k_verify(Dev d, Params p) {
             }
             if (r2 < p.rc2) {
                 bool found = false;
-                for (int e = 0; e < n && !found; ++e)
-                    found = entry_slot(d, qi.cc, d.list[list_addr(s, e, p.tpk, p.rows)], g) == j;
+                for (int e = 0; e < n && !found; ++e) {
+                    const uint32_t en = d.list[list_addr(s, e, p.tpk, p.rows)];
+                    found = (p.tile ? tile_slot(ps0, plen, en) : entry_slot(d, qi.cc, en, g)) == j;
+                }
                 if (!found) ++missed;
             }
         }
@@ -2038,6 +2220,13 @@ static void launch_list_t(const Dev& d, const Params& p, hipStream_t s) {
         k_list<TPK, false><<<grid_for_waves(p.ntile * kTile, 8192), kBlock, 0, s>>>(d, p);
 }
 
+void launch_row_tiles(const Dev& d, const Params& p, hipStream_t s) {
+    const int gr = grid_for_waves(p.nrows);
+    k_row_tiles<<<gr, kBlock, 0, s>>>(d, p);
+    k_row_scan<<<1, kBlock, 0, s>>>(d, p);
+    k_row_write<<<gr, kBlock, 0, s>>>(d, p);
+}
+
 void launch_rebuild_chain(const Dev& d, const Params& p, bool with_list, hipStream_t s) {
     const int gw = grid_for_waves(p.nwave);
     const int gt = p.ntile < 4096 ? p.ntile : 4096;
@@ -2046,6 +2235,7 @@ void launch_rebuild_chain(const Dev& d, const Params& p, bool with_list, hipStre
     k_scan_tile<<<gt, kBlock, 0, s>>>(d, p);
     k_scan_box<<<p.nbox < 1024 ? p.nbox : 1024, kBlock, 0, s>>>(d, p);
     k_scan_add<<<gt, kBlock, 0, s>>>(d, p);
+    if (p.tile) launch_row_tiles(d, p, s);
     k_scatter<<<gw, kBlock, 0, s>>>(d, p);
     k_rank_permute<<<gw, kBlock, 0, s>>>(d, p);
     k_flip<<<1, kBlock, 0, s>>>(d, p);
@@ -2078,26 +2268,8 @@ static void launch_force_pt(const Dev& d, const Params& p, int mode, bool energy
     }
 }
 
-static void launch_force_tile(const Dev& d, const Params& p, int mode, bool energy, hipStream_t s) {
-    const int nb = (p.nwave + 3) / 4;
-    if (mode == kForceOnly) {
-        if (energy)
-            k_force_tile<kForceOnly, true><<<nb, kBlock, 0, s>>>(d, p);
-        else
-            k_force_tile<kForceOnly, false><<<nb, kBlock, 0, s>>>(d, p);
-    } else if (mode == kForceEnd) {
-        if (energy)
-            k_force_tile<kForceEnd, true><<<nb, kBlock, 0, s>>>(d, p);
-        else
-            k_force_tile<kForceEnd, false><<<nb, kBlock, 0, s>>>(d, p);
-    } else {
-        k_force_tile<kForceMid, false><<<nb, kBlock, 0, s>>>(d, p);
-    }
-}
-
 template <int PREC>
 static void launch_force_p(const Dev& d, const Params& p, int mode, bool energy, hipStream_t s) {
-    if (PREC == MD_PREC_FP32_MIXED && p.tpk == 1 && p.tile) return launch_force_tile(d, p, mode, energy, s);
     switch (p.tpk) {
         case 1: launch_force_pt<PREC, 1>(d, p, mode, energy, s); break;
         case 2: launch_force_pt<PREC, 2>(d, p, mode, energy, s); break;
@@ -2125,7 +2297,45 @@ static void launch_force_half(const Dev& d, const Params& p, int mode, bool ener
     }
 }
 
+template <bool CLAMP>
+static void launch_force_rowtile_c(const Dev& d, const Params& p, int mode, bool energy, hipStream_t s) {
+    const size_t lds = (size_t)p.scap * sizeof(U3);
+    if (mode == kForceOnly) {
+        if (energy)
+            k_force_t<kForceOnly, true, CLAMP><<<p.tgrid, kRtBlock, lds, s>>>(d, p);
+        else
+            k_force_t<kForceOnly, false, CLAMP><<<p.tgrid, kRtBlock, lds, s>>>(d, p);
+    } else if (mode == kForceEnd) {
+        if (energy)
+            k_force_t<kForceEnd, true, CLAMP><<<p.tgrid, kRtBlock, lds, s>>>(d, p);
+        else
+            k_force_t<kForceEnd, false, CLAMP><<<p.tgrid, kRtBlock, lds, s>>>(d, p);
+    } else {
+        k_force_t<kForceMid, false, CLAMP><<<p.tgrid, kRtBlock, lds, s>>>(d, p);
+    }
+}
+
+// Resident blocks per compute unit of the mid-step row-tile kernel with its LDS: the
+// row-tile kernels launch that many blocks per CU, and each loops over the tiles.
+int rowtile_blocks_per_cu(const Params& p) {
+    int nb = 0;
+    const size_t lds = (size_t)p.scap * sizeof(U3);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_force_t<kForceMid, false, true>, kRtBlock, lds) !=
+            hipSuccess ||
+        nb < 1)
+        nb = 1;
+    return nb;
+}
+
+static void launch_force_rowtile(const Dev& d, const Params& p, int mode, bool energy, hipStream_t s) {
+    if (p.clamp)
+        launch_force_rowtile_c<true>(d, p, mode, energy, s);
+    else
+        launch_force_rowtile_c<false>(d, p, mode, energy, s);
+}
+
 void launch_force(const Dev& d, const Params& p, int mode, bool energy, hipStream_t s) {
+    if (p.tile) return launch_force_rowtile(d, p, mode, energy, s);
     if (p.half) {
         if (p.precision == MD_PREC_FP64)
             launch_force_half<MD_PREC_FP64>(d, p, mode, energy, s);
@@ -2145,10 +2355,11 @@ void launch_kick_drift(const Dev& d, const Params& p, hipStream_t s) {
 void launch_dutc(const Dev& d, const Params& p, hipStream_t s) {
     k_dutc<<<p.nbox < 1024 ? p.nbox : 1024, kBlock, 0, s>>>(d, p);
 }
-void launch_energy_reduce(const Dev& d, const Params& p, bool record, int thermo, hipStream_t s) {
-    const int nseg = (p.maxslot / kWave * p.tpk + kRedSeg - 1) / kRedSeg;
-    k_energy_segments<<<dim3(nseg, p.nbox), kBlock, 0, s>>>(d, p);
-    k_energy_reduce<<<p.nbox < 1024 ? p.nbox : 1024, kBlock, 0, s>>>(d, p, record ? 1 : 0, thermo);
+void launch_energy_reduce(const Dev& d, const Params& p, bool record, int thermo, bool tl, hipStream_t s) {
+    const int nparts = tl ? p.maxcell : p.maxslot / kWave * p.tpk;  // a box has at most one row tile per cell
+    const int nseg = (nparts + kRedSeg - 1) / kRedSeg;
+    k_energy_segments<<<dim3(nseg, p.nbox), kBlock, 0, s>>>(d, p, tl ? 1 : 0);
+    k_energy_reduce<<<p.nbox < 1024 ? p.nbox : 1024, kBlock, 0, s>>>(d, p, record ? 1 : 0, thermo, tl ? 1 : 0);
 }
 void launch_ke_partial(const Dev& d, const Params& p, hipStream_t s) {
     k_ke_partial<<<grid_for_waves(p.nwave), kBlock, 0, s>>>(d, p);
