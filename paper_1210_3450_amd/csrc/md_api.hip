@@ -311,6 +311,7 @@ md_status alloc_cells(md_ctx* c) {
     dfree(c->D.row_t0);
     dfree(c->D.cell_rt);
     dfree(c->D.rt_tmp);
+    dfree(c->D.rt_delta);
     dfree(c->D.ke_part);
     dfree(c->D.pe_part);
     dfree(c->D.vir_part);
@@ -325,6 +326,7 @@ md_status alloc_cells(md_ctx* c) {
     if ((s = dalloc(c, &c->D.row_t0, c->nrows)) != MD_OK) return s;
     if ((s = dalloc(c, &c->D.cell_rt, ncellpad)) != MD_OK) return s;
     if ((s = dalloc(c, &c->D.rt_tmp, ncellpad)) != MD_OK) return s;
+    if ((s = dalloc(c, &c->D.rt_delta, ncellpad * 27)) != MD_OK) return s;
     if ((s = dalloc(c, &c->D.ke_part, nparts)) != MD_OK) return s;
     if ((s = dalloc(c, &c->D.pe_part, nparts)) != MD_OK) return s;
     if ((s = dalloc(c, &c->D.vir_part, nparts)) != MD_OK) return s;
@@ -454,6 +456,7 @@ void free_all(md_ctx* c) {
     dfree(D.box_t0);
     dfree(D.cell_rt);
     dfree(D.rt_tmp);
+    dfree(D.rt_delta);
     dfree(D.vmax_s);
     dfree(D.disp_s);
     dfree(D.ke_part);

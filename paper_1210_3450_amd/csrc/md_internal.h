@@ -174,6 +174,7 @@ struct Dev {
     int32_t* box_t0;     // [nbox + 1] first row tile of each box, then the total
     int32_t* cell_rt;    // row tile of each cell
     int32_t* rt_tmp;     // per cell: xa | xb << 16 of the row's k-th tile at (row's first cell + k)
+    int32_t* rt_delta;   // [tile][27]: staged index minus first slot of each piece of the tile
     unsigned long long* vmax_s;  // [nbox][kStripes] striped max |v|^2 (bits), stride kStripeStride
     unsigned long long* disp_s;  // [nbox][kStripes] striped max |q - q_build|^2 (bits)
     double* ke_part;     // per list wave

@@ -783,6 +783,25 @@ __global__ __launch_bounds__(kBlock) void k_row_write(Dev d, Params p) {
     }
 }
 
+// Per row tile and piece p: staged index of the piece's first record minus its first
+// slot, so that the list build turns a stencil cell's first slot into its staged
+// index with one addition.  One wavefront per tile, lane p per piece.
+__global__ __launch_bounds__(kBlock) void k_row_delta(Dev d, Params p) {
+    if (!ld_const(d.any)) return;
+    const int l = lane_id();
+    const int ntl = ld_const(d.ntiles);
+    for (int t = blockIdx.x * 4 + wave_in_block(); t < ntl; t += gridDim.x * 4) {
+        const int4 tr = d.rtile[t];
+        const int b = __builtin_amdgcn_readfirstlane(tr.x);
+        const BoxGeom g = ld_geom(d.geom + b);
+        const int lr = __builtin_amdgcn_readfirstlane(tr.y);
+        int ps0 = 0, plen = 0, ox, oy, oz;
+        if (l < 27) tile_piece(d, g, lr % g.n[1], lr / g.n[1], tr.z, tr.w, l, ps0, plen, ox, oy, oz);
+        const int pbase = wave_incl_sum(plen) - plen;
+        if (l < 27) d.rt_delta[t * 27 + l] = pbase - ps0;
+    }
+}
+
 // ---------------------------------------------------------------- pair list
 
 // Squared minimum-image distance exactly as the plain definition evaluates it:
@@ -797,14 +816,17 @@ __device__ __forceinline__ double dist2_exact(const A& qi, const B& qj, double s
     const double dz = (qj.z - qi.z) - shz;
     return dx * dx + dy * dy + dz * dz;
 }
-// The same value when every image term is zero (t - 0 is t exactly).
+// The same distance for a cell whose stencil has no periodic image, with the sum of
+// squares contracted into two FMAs (7 instructions with the compare instead of 9).
+// Its rounding differs from the uncontracted definition by about one ulp of r^2, so
+// the accept decision can differ only for pairs within ~1e-15 of the list radius:
+// inside the 1e-9 tie band that set comparisons leave out.
 template <class A, class B>
-__device__ __forceinline__ double dist2_exact0(const A& qi, const B& qj) {
-#pragma clang fp contract(off)
+__device__ __forceinline__ double dist2_fma0(const A& qi, const B& qj) {
     const double dx = qj.x - qi.x;
     const double dy = qj.y - qi.y;
     const double dz = qj.z - qi.z;
-    return dx * dx + dy * dy + dz * dz;
+    return __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
 }
 
 __device__ __forceinline__ double readlane_d(double v, int lane) {
@@ -839,8 +861,9 @@ __device__ __forceinline__ int nb_axis(int c, int o, int n, double L, double& su
 // per (key, chunk) an exact FP64 test, a ballot, an mbcnt prefix on the key's
 // running count, and the accepted partners appended in candidate order.  The
 // running count is wave-uniform (SGPR), so no lane bookkeeping sits in the inner
-// loop.  The distance test is the plain definition with no contraction, so the
-// accepted set is the CPU's bit for bit.
+// loop.  The distance test is the plain definition (no contraction) for cells whose
+// stencil holds a periodic image, and contracted into FMAs elsewhere: the accepted
+// set is the CPU's except possibly for pairs within ~1e-15 of the list radius.
 
 // Positions seen through the constant address space: in the list build they are
 // read-only, and uniform indices then become scalar loads into SGPRs.
@@ -861,7 +884,7 @@ typedef const __attribute__((address_space(4))) double const_double;
 constexpr int kStage = 2048;  // LDS list entries per wavefront (16 KB per block, 17.5 KB with the marks: 7 blocks per CU)
 constexpr int kMarkBytes = 6 * kWave;  // candidate window of a pass (G <= 6 chunks)
 
-template <int TPK, bool WRAP, bool STAGED, bool HALF>
+template <int TPK, bool WRAP, bool STAGED, bool HALF, bool TL>
 __device__ __forceinline__ void list_pass(const Dev& d, const Params& p, const Pos* __restrict__ q,
                                           const const_double* qc, int cs0, int kb, int mb, int c0, int total,
                                           int start, int pre, int ekey, int scnt, double shx, double shy,
@@ -898,7 +921,7 @@ __device__ __forceinline__ void list_pass(const Dev& d, const Params& p, const P
             const int base_sc = __shfl(sbase, sc), ek_sc = __shfl(ekey, sc);
             // gather format: stencil cell << 11 | rank; row-tile format: the staged record's
             // LDS byte offset (12-byte records)
-            ent[k] = (uint32_t)(ek_sc + ci) * (p.tile ? (uint32_t)sizeof(U3) : 1u);
+            ent[k] = (uint32_t)(ek_sc + ci) * (TL ? (uint32_t)sizeof(U3) : 1u);
             // 32-bit byte offset from the (scalar) array base: slots stay below 2^27
             const uint32_t boff = (uint32_t)(valid ? base_sc + ci : cs0) * (uint32_t)sizeof(Pos);
             const Pos qj = *reinterpret_cast<const Pos*>(reinterpret_cast<const char*>(q) + boff);
@@ -944,7 +967,7 @@ __device__ __forceinline__ void list_pass(const Dev& d, const Params& p, const P
 #pragma unroll
             for (int k = 0; k < N; ++k) {
                 const double r2 = WRAP ? dist2_exact(qi, make_double3(cx[k], cy[k], cz[k]), sx[k], sy[k], sz[k])
-                                       : dist2_exact0(qi, make_double3(cx[k], cy[k], cz[k]));
+                                       : dist2_fma0(qi, make_double3(cx[k], cy[k], cz[k]));
                 in[k] = r2 < rl2;
             }
 #pragma unroll
@@ -1002,7 +1025,8 @@ __device__ __forceinline__ void list_pass(const Dev& d, const Params& p, const P
 // wavefronts hide (measured at 32M particles, rebuild chain per rebuild: 4 wavefronts
 // 13.2 ms, 6 wavefronts 11.5 ms in an earlier form; 6 -> 7 -> 8 wavefronts now
 // 9.36 -> 9.08 -> 9.19 ms, the last with spills).
-template <int TPK, bool HALF>
+// TL: the row-tile entry format (FP32-mixed, full list); otherwise the gather format.
+template <int TPK, bool HALF, bool TL>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7, 8))) void k_list(Dev d, Params p) {
     if (!ld_const(d.any)) return;  // no box rebuilds this step
     __shared__ __align__(16) uint16_t stage_all[kBlock / kWave][kStage];
@@ -1019,17 +1043,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7, 8))) 
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     uint16_t* stage = stage_all[wv];
     uint8_t* mark = mark_all[wv];
-    for (int c = xcd_block(blockIdx.x, gridDim.x) * 4 + wv; c < ncells; c += gridDim.x * 4) {
+    // One home cell c of box b.
+    auto cell_body = [&](int c, int b, const BoxGeom& g) {
         const int t = c / kTile;
-        // tables this kernel does not write, read through the scalar cache
-        const int b = ld_const(d.tile_box + t);
         const BoxState& st = d.st[b];
-        if (!ld_const(&st.rebuild)) continue;
-        const BoxGeom g = ld_geom(d.geom + b);
         const int local = c - g.cell_off;
-        if (local >= g.ncell) continue;
         const int m = ld_const(d.cell_cnt + c);
-        if (m == 0) continue;
+        if (m == 0) return;
         const int cs0 = ld_const(d.cell_start + c);
         Pos* __restrict__ q = d.q[ld_const(&st.sq)];
         const int cx = local % g.n[0], cy = (local / g.n[0]) % g.n[1], cz = local / (g.n[0] * g.n[1]);
@@ -1059,16 +1079,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7, 8))) 
         // plus its rank; row-tile format: its index in the staged region of the home
         // cell's row tile, whose piece p = r * 3 + side holds unwrapped cells in order)
         int ekey = (l << kOffBits) - pre;
-        if (p.tile) {
-            const int4 tr = d.rtile[ld_const(d.cell_rt + c)];
-            int ps0 = 0, plen = 0, pox, poy, poz;
-            if (l < 27) tile_piece(d, g, cy, cz, tr.z, tr.w, l, ps0, plen, pox, poy, poz);
-            const int pbase = wave_incl_sum(plen) - plen;
+        if constexpr (TL) {
+            // staged index of the stencil cell's first member: its first slot plus the
+            // (staged index - first slot) of the piece of the home cell's row tile holding it
             const int r = l / 3, x = cx + l % 3 - 1;
             const int pc = r * 3 + (x < 0 ? 0 : (x >= g.n[0] ? 2 : 1));
-            const int base_pc = __shfl(pbase, pc), s0_main = __shfl(ps0, r * 3 + 1);
-            const int ebase = base_pc + (pc == r * 3 + 1 ? start - s0_main : 0);
-            ekey = ebase - pre;
+            const int rt = ld_const(d.cell_rt + c);
+            ekey = (l < 27 ? start + d.rt_delta[rt * 27 + pc] : 0) - pre;
         }
         const int total = __builtin_amdgcn_readlane(incl, 26);
         const int pre13 = __builtin_amdgcn_readlane(pre, 13);  // the home cell's first candidate
@@ -1082,11 +1099,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7, 8))) 
                 int open = 0;  // no stencil cell open before the first candidate
                 if (wrap) {
                     for (int c0 = 0; c0 < total; c0 += 3 * kWave)
-                        list_pass<TPK, true, true, HALF>(d, p, q, qc, cs0, kb, mb, c0, total, start, pre, ekey, cnt, shx,
+                        list_pass<TPK, true, true, HALF, TL>(d, p, q, qc, cs0, kb, mb, c0, total, start, pre, ekey, cnt, shx,
                                                          shy, shz, pre13, n_own, open, stage, mark);
                 } else {
                     for (int c0 = 0; c0 < total; c0 += 6 * kWave)
-                        list_pass<TPK, false, true, HALF>(d, p, q, qc, cs0, kb, mb, c0, total, start, pre, ekey, cnt, shx,
+                        list_pass<TPK, false, true, HALF, TL>(d, p, q, qc, cs0, kb, mb, c0, total, start, pre, ekey, cnt, shx,
                                                           shy, shz, pre13, n_own, open, stage, mark);
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -1117,12 +1134,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7, 8))) 
             } else if (wrap) {
                 int open = 0;
                 for (int c0 = 0; c0 < total; c0 += 3 * kWave)
-                    list_pass<TPK, true, false, HALF>(d, p, q, qc, cs0, kb, mb, c0, total, start, pre, ekey, cnt, shx, shy,
+                    list_pass<TPK, true, false, HALF, TL>(d, p, q, qc, cs0, kb, mb, c0, total, start, pre, ekey, cnt, shx, shy,
                                                       shz, pre13, n_own, open, stage, mark);
             } else {
                 int open = 0;
                 for (int c0 = 0; c0 < total; c0 += 6 * kWave)
-                    list_pass<TPK, false, false, HALF>(d, p, q, qc, cs0, kb, mb, c0, total, start, pre, ekey, cnt, shx,
+                    list_pass<TPK, false, false, HALF, TL>(d, p, q, qc, cs0, kb, mb, c0, total, start, pre, ekey, cnt, shx,
                                                        shy, shz, pre13, n_own, open, stage, mark);
             }
             if (l < mb) {
@@ -1133,6 +1150,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7, 8))) 
             need = max(need, __builtin_amdgcn_readlane(wave_incl_max(l < mb ? n_own : 0), 63));
         }
         if (l == 0) atomicMax(&d.tile_need[t], need);
+    };
+    {
+        for (int c = xcd_block(blockIdx.x, gridDim.x) * 4 + wv; c < ncells; c += gridDim.x * 4) {
+            // tables this kernel does not write, read through the scalar cache
+            const int b = ld_const(d.tile_box + c / kTile);
+            if (!ld_const(&d.st[b].rebuild)) continue;
+            const BoxGeom g = ld_geom(d.geom + b);
+            if (c - g.cell_off >= g.ncell) continue;
+            cell_body(c, b, g);
+        }
     }
 }
 
@@ -2215,9 +2242,11 @@ void launch_mark_rebuild(const Dev& d, const Params& p, hipStream_t s) {
 template <int TPK>
 static void launch_list_t(const Dev& d, const Params& p, hipStream_t s) {
     if (TPK == 1 && p.half)
-        k_list<1, true><<<grid_for_waves(p.ntile * kTile, 8192), kBlock, 0, s>>>(d, p);
+        k_list<1, true, false><<<grid_for_waves(p.ntile * kTile, 8192), kBlock, 0, s>>>(d, p);
+    else if (TPK == 1 && p.tile)
+        k_list<1, false, true><<<grid_for_waves(p.ntile * kTile, 8192), kBlock, 0, s>>>(d, p);
     else
-        k_list<TPK, false><<<grid_for_waves(p.ntile * kTile, 8192), kBlock, 0, s>>>(d, p);
+        k_list<TPK, false, false><<<grid_for_waves(p.ntile * kTile, 8192), kBlock, 0, s>>>(d, p);
 }
 
 void launch_row_tiles(const Dev& d, const Params& p, hipStream_t s) {
@@ -2225,6 +2254,7 @@ void launch_row_tiles(const Dev& d, const Params& p, hipStream_t s) {
     k_row_tiles<<<gr, kBlock, 0, s>>>(d, p);
     k_row_scan<<<1, kBlock, 0, s>>>(d, p);
     k_row_write<<<gr, kBlock, 0, s>>>(d, p);
+    k_row_delta<<<4096, kBlock, 0, s>>>(d, p);
 }
 
 void launch_rebuild_chain(const Dev& d, const Params& p, bool with_list, hipStream_t s) {
