@@ -111,7 +111,10 @@ typedef struct {
     int32_t threads_per_key; /* lanes cooperating on one particle's list: 0 = default,
                                 else 1, 2, 4 or 8 */
     int32_t list_cap;     /* list entries per particle: 0 = estimate from density */
-    uint64_t reserved[6]; /* must be zero */
+    double cell_scale;    /* grid cells of side >= cell_scale * r_list (Sec. II.A grid
+                             algorithm: any side >= r_list keeps the 27-cell search exact):
+                             0 = 1, the smallest such cells; else in [1, 2] */
+    uint64_t reserved[5]; /* must be zero */
 } md_params;
 
 typedef struct {
@@ -129,6 +132,10 @@ typedef struct {
     int64_t force_launches;
     double rebuild_ms;    /* with timing on: summed time of list-build chains */
     int64_t rebuild_launches;
+    int32_t row_tiles;    /* 1: the force pass reads partners from row tiles staged in LDS;
+                             0: from global memory (gather format) */
+    int32_t ncell[3];     /* box 0's cells per axis */
+    double cell_scale;    /* cell side lower bound in use, as a multiple of r_list */
 } md_stats;
 
 /* ---- lifetime ---------------------------------------------------------- */
@@ -313,12 +320,19 @@ md_status md_get_stats(md_ctx *ctx, md_stats *out);
  * chains on (1) or off (0); timings accumulate in md_stats. */
 md_status md_set_timing(md_ctx *ctx, int32_t on);
 
-/* Picks threads_per_key by timing the force kernel on the current state for
- * each candidate (1, 2, 4, 8) and keeps the fastest; rebuilds the list in the
- * chosen layout.  cache_path (nullable): a text file of
- * "precision density_bucket n_bucket threads_per_key" lines consulted first
- * and appended to.  With MD_F_HALF_LIST there is one layout and nothing is
- * timed.  Synchronizing. */
+/* Picks the layout of the force pass and the grid by timing them on the current
+ * state: the cell side (cell_scale 1, 1.15 or 1.3 times r_list), the list format
+ * (row tiles or gather format, FP32-mixed only) and threads_per_key (1, 2, 4 or 8,
+ * gather format), for a cost of force-pass time + list-build time / R, where R is
+ * the context's mean rebuild interval so far (10 steps before any step).  Leaves
+ * the state as it was and rebuilds the list in the chosen layout; md_get_stats
+ * reports the choice.  cache_path (nullable): a text file of lines
+ * "precision density_bucket n_bucket ensemble threads_per_key row_tiles
+ * cell_scale_percent", consulted first (a matching line skips the timing) and
+ * appended to.  MD_F_TILE_OFF and MD_F_TILE_ON restrict the format; a
+ * threads_per_key fixed at creation restricts that; a cell_scale given at
+ * creation restricts the cell side.  With MD_F_HALF_LIST nothing is timed.
+ * Synchronizing. */
 md_status md_autotune(md_ctx *ctx, const char *cache_path);
 
 /* ---- errors ------------------------------------------------------------ */

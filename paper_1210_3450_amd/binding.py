@@ -41,7 +41,7 @@ class md_params(C.Structure):
     _fields_ = [("n", C.c_int64), ("box", C.c_double * 3), ("rc", C.c_double), ("skin", C.c_double),
                 ("dt", C.c_double), ("mass", C.c_double), ("precision", C.c_int32), ("cutoff", C.c_int32),
                 ("rebuild", C.c_int32), ("flags", C.c_uint32), ("threads_per_key", C.c_int32),
-                ("list_cap", C.c_int32), ("reserved", C.c_uint64 * 6)]
+                ("list_cap", C.c_int32), ("cell_scale", C.c_double), ("reserved", C.c_uint64 * 5)]
 
 
 class md_stats(C.Structure):
@@ -49,7 +49,8 @@ class md_stats(C.Structure):
                 ("missed_pairs", C.c_int64), ("list_entries", C.c_int64), ("max_list_len", C.c_int32),
                 ("list_cap", C.c_int32), ("threads_per_key", C.c_int32), ("nbox", C.c_int32),
                 ("D", C.c_double), ("force_ms", C.c_double), ("force_launches", C.c_int64),
-                ("rebuild_ms", C.c_double), ("rebuild_launches", C.c_int64)]
+                ("rebuild_ms", C.c_double), ("rebuild_launches", C.c_int64), ("row_tiles", C.c_int32),
+                ("ncell", C.c_int32 * 3), ("cell_scale", C.c_double)]
 
 
 class md_bubble_info(C.Structure):
@@ -111,7 +112,7 @@ class MDError(RuntimeError):
 
 
 def make_params(n, box, rc=2.5, skin=0.3, dt=0.005, mass=1.0, precision=MD_PREC_FP64, cutoff=MD_CUT_EQ1,
-                rebuild=MD_REBUILD_DUTC, flags=0, threads_per_key=0, list_cap=0) -> md_params:
+                rebuild=MD_REBUILD_DUTC, flags=0, threads_per_key=0, list_cap=0, cell_scale=0.0) -> md_params:
     b = np.broadcast_to(np.asarray(box, dtype=np.float64), (3,))
     p = md_params()
     p.n = int(n)
@@ -120,6 +121,7 @@ def make_params(n, box, rc=2.5, skin=0.3, dt=0.005, mass=1.0, precision=MD_PREC_
     p.rc, p.skin, p.dt, p.mass = float(rc), float(skin), float(dt), float(mass)
     p.precision, p.cutoff, p.rebuild = int(precision), int(cutoff), int(rebuild)
     p.flags, p.threads_per_key, p.list_cap = int(flags), int(threads_per_key), int(list_cap)
+    p.cell_scale = float(cell_scale)
     return p
 
 
@@ -332,7 +334,9 @@ class Context:
     def stats(self) -> dict:
         st = md_stats()
         self._chk(md_get_stats(self.ctx, C.byref(st)), "md_get_stats")
-        return {name: getattr(st, name) for name, _ in md_stats._fields_}
+        out = {name: getattr(st, name) for name, _ in md_stats._fields_}
+        out["ncell"] = list(out["ncell"])
+        return out
 
     def set_timing(self, on=True):
         self._chk(md_set_timing(self.ctx, int(bool(on))), "md_set_timing")

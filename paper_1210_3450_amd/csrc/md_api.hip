@@ -45,6 +45,8 @@ struct md_ctx {
     int64_t ntotal = 0;
     int32_t nslot = 0, nwave = 0, ntile = 0, nrows = 0;
     bool tile_fallback = false;    // a row tile overflowed its staging capacity: gather format from then on
+    bool tune_gather = false;      // md_autotune chose the gather format over row tiles
+    double cell_scale = 0.0;       // > 0: cell side bound chosen by md_autotune (else the boxes' own)
     Params P{};
     Dev D{};
     // device allocations not reachable through D
@@ -161,8 +163,10 @@ md_status validate(const md_params* b, int32_t nbox, std::string& why) {
               p.threads_per_key == 4 || p.threads_per_key == 8))
             return bad("threads_per_key must be 0, 1, 2, 4 or 8");
         if (p.list_cap < 0 || p.list_cap > 4096) return bad("list_cap must be in [0, 4096]");
-        for (int k = 0; k < 6; ++k)
+        for (int k = 0; k < 5; ++k)
             if (p.reserved[k]) return bad("reserved fields must be zero");
+        if (!(p.cell_scale == 0.0 || (p.cell_scale >= 1.0 && p.cell_scale <= 2.0)))
+            return bad("cell_scale must be 0 or in [1, 2]");
         const double rl = p.rc + p.skin;
         for (int a = 0; a < 3; ++a) {
             if (!finite_pos(p.box[a])) return bad("box lengths must be finite and > 0");
@@ -173,9 +177,10 @@ md_status validate(const md_params* b, int32_t nbox, std::string& why) {
             const md_params& q = b[0];
             if (p.rc != q.rc || p.skin != q.skin || p.dt != q.dt || p.mass != q.mass ||
                 p.precision != q.precision || p.cutoff != q.cutoff || p.rebuild != q.rebuild ||
-                p.flags != q.flags || p.threads_per_key != q.threads_per_key || p.list_cap != q.list_cap)
-                return bad("rc, skin, dt, mass, precision, cutoff, rebuild, flags, threads_per_key and "
-                           "list_cap must agree across boxes");
+                p.flags != q.flags || p.threads_per_key != q.threads_per_key || p.list_cap != q.list_cap ||
+                p.cell_scale != q.cell_scale)
+                return bad("rc, skin, dt, mass, precision, cutoff, rebuild, flags, threads_per_key, "
+                           "list_cap and cell_scale must agree across boxes");
         }
         slots += (p.n + kWave - 1) / kWave * kWave;
         if (slots > (int64_t)kIdxMask + 1) return bad("more than 2^27 particle slots in total");
@@ -200,8 +205,15 @@ void lj_coeffs(double rc, int mode, double* c2, double* c0) {
 
 // Box geometry: cell grid n = floor(L / r_list) per axis, inv = n / L, cs = L / n,
 // and the placement of each box's cells and slots in the shared arrays.
+// Cell side lower bound as a multiple of r_list: md_autotune's choice, else the
+// parameters' own (0 = 1).
+double cell_scale_of(const md_ctx* c) {
+    if (c->cell_scale > 0.0) return c->cell_scale;
+    return c->prm.cell_scale > 0.0 ? c->prm.cell_scale : 1.0;
+}
+
 void layout(md_ctx* c) {
-    const double rl = c->prm.rc + c->prm.skin;
+    const double rl = c->prm.rc + c->prm.skin, side = rl * cell_scale_of(c);
     c->geom.assign(c->nbox, BoxGeom{});
     int32_t slot = 0, tile = 0, rows = 0;
     int64_t id = 0;
@@ -211,7 +223,9 @@ void layout(md_ctx* c) {
         double csmax = 0.0;
         for (int a = 0; a < 3; ++a) {
             g.L[a] = p.box[a];
-            g.n[a] = (int32_t)std::floor(p.box[a] / rl);
+            // cells of side >= side (>= r_list): at least 3 per axis, which the box
+            // size bound L >= 3 r_list always allows
+            g.n[a] = std::max(3, (int32_t)std::floor(p.box[a] / side));
             g.inv[a] = (double)g.n[a] / p.box[a];
             g.cs[a] = p.box[a] / (double)g.n[a];
             csmax = std::max(csmax, g.cs[a]);
@@ -391,7 +405,7 @@ void params_refresh(md_ctx* c) {
     // partner from LDS; the gather format serves the other layouts and boxes whose
     // cells are too crowded for a tile's staging capacity.
     P.tile = p.precision == MD_PREC_FP32_MIXED && !P.half && P.tpk == 1 && !(p.flags & MD_F_TILE_OFF) &&
-                     !c->tile_fallback
+                     !c->tile_fallback && !c->tune_gather
                  ? 1
                  : 0;
     P.kt = kRtBlock;
@@ -1348,6 +1362,9 @@ md_status md_get_stats(md_ctx* c, md_stats* out) {
     out->force_launches = c->force_n;
     out->rebuild_ms = c->rebuild_ms;
     out->rebuild_launches = c->rebuild_n;
+    out->row_tiles = c->P.tile;
+    for (int a = 0; a < 3; ++a) out->ncell[a] = c->geom[0].n[a];
+    out->cell_scale = cell_scale_of(c);
     if (c->have_list) {
         std::vector<int32_t> cnt(c->nslot);
         HIPCHK(c, hipMemcpy(cnt.data(), c->D.cnt, sizeof(int32_t) * c->nslot, hipMemcpyDeviceToHost));
@@ -1386,56 +1403,109 @@ md_status md_autotune(md_ctx* c, const char* cache_path) {
     char key[96];
     snprintf(key, sizeof key, "%d %d %d %d", c->prm.precision, (int)std::lround(rho * 20.0),
              (int)std::lround(std::log2(nmean)), c->nbox > 1 ? 1 : 0);
-    int best = 0;
+
+    // candidates the parameters allow
+    struct Cand {
+        int tpk;
+        bool tile;
+        int pct;  // cell_scale in percent
+    };
+    const bool mixed = c->prm.precision == MD_PREC_FP32_MIXED;
+    const uint32_t fl = c->prm.flags;
+    std::vector<int> pcts;
+    if (c->prm.cell_scale > 0.0)
+        pcts.push_back((int)std::lround(c->prm.cell_scale * 100.0));
+    else
+        pcts = {100, 115, 130};
+    std::vector<Cand> cands;
+    for (int pct : pcts) {
+        if (mixed && !(fl & MD_F_TILE_OFF)) cands.push_back({1, true, pct});
+        if ((fl & MD_F_TILE_ON) && mixed) continue;  // MD_F_TILE_ON has no effect on FP64
+        for (int t : {1, 2, 4, 8})
+            if (c->prm.threads_per_key == 0 || c->prm.threads_per_key == t) cands.push_back({t, false, pct});
+    }
+    auto valid = [&](const Cand& k) {
+        for (const Cand& q : cands)
+            if (q.tpk == k.tpk && q.tile == k.tile && q.pct == k.pct) return true;
+        return false;
+    };
+
+    Cand best{0, false, 0};
     if (cache_path) {
         std::ifstream in(cache_path);
         std::string line;
         while (std::getline(in, line)) {
             if (line.empty() || line[0] == '#') continue;
             std::istringstream ls(line);
-            int a, b2, c2, d2, t;
-            if (ls >> a >> b2 >> c2 >> d2 >> t) {
+            int a, b2, c2, d2, t, tl, pct;
+            if (ls >> a >> b2 >> c2 >> d2 >> t >> tl >> pct) {
                 char k2[96];
                 snprintf(k2, sizeof k2, "%d %d %d %d", a, b2, c2, d2);
-                if (std::strcmp(k2, key) == 0 && (t == 1 || t == 2 || t == 4 || t == 8)) best = t;
+                const Cand k{t, tl != 0, pct};
+                if (std::strcmp(k2, key) == 0 && valid(k)) best = k;
             }
         }
     }
-    const bool from_cache = best != 0;
+    // the state's own rebuild counts are kept; the builds made here are not steps
+    if ((s = sync_states(c)) != MD_OK) return s;
+    std::vector<int32_t> built(c->nbox);
+    for (int b = 0; b < c->nbox; ++b) built[b] = c->st_h[b].built;
+    const double interval = c->steps > 0 && built[0] > 0 ? (double)c->steps / built[0] : 10.0;
+    const bool fallback0 = c->tile_fallback;
+
+    // re-lay the grid and the list for candidate k and build the list
+    auto apply = [&](const Cand& k) -> md_status {
+        md_status r;
+        c->cell_scale = k.pct / 100.0;
+        c->tune_gather = !k.tile;
+        c->tile_fallback = fallback0;
+        c->P.tpk = k.tpk;
+        layout(c);
+        params_refresh(c);
+        if ((r = alloc_cells(c)) != MD_OK) return r;
+        if ((r = upload_geometry(c)) != MD_OK) return r;
+        if ((r = alloc_list(c, c->P.cap)) != MD_OK) return r;
+        c->have_cells = c->have_list = c->have_F = false;
+        return build_list(c);
+    };
+
+    const bool from_cache = best.tpk != 0;
     if (!from_cache) {
-        float best_ms = 1e30f;
-        hipEvent_t e0, e1;
-        HIPCHK(c, hipEventCreate(&e0));
-        HIPCHK(c, hipEventCreate(&e1));
-        for (int tpk : {1, 2, 4, 8}) {
-            c->P.tpk = tpk;
-            if ((s = alloc_list(c, c->P.cap)) != MD_OK) return s;
-            c->have_list = false;
-            if ((s = build_list(c)) != MD_OK) return s;
+        float best_cost = 1e30f;
+        hipEvent_t ev[3];
+        for (hipEvent_t& e : ev) HIPCHK(c, hipEventCreate(&e));
+        for (const Cand& k : cands) {
+            if ((s = apply(k)) != MD_OK) return s;
+            if (k.tile && !c->P.tile) continue;  // the tiles overflowed: a gather candidate covers it
+            // the chain again on sorted slots (re-sorts identically), then forces
+            HIPCHK(c, hipEventRecord(ev[0], c->stream));
+            launch_mark_rebuild(c->D, c->P, c->stream);
+            launch_rebuild_chain(c->D, c->P, true, c->stream);
+            HIPCHK(c, hipEventRecord(ev[1], c->stream));
             launch_force(c->D, c->P, kForceOnly, false, c->stream);  // warm-up
-            HIPCHK(c, hipEventRecord(e0, c->stream));
             for (int r = 0; r < 5; ++r) launch_force(c->D, c->P, kForceOnly, false, c->stream);
-            HIPCHK(c, hipEventRecord(e1, c->stream));
-            HIPCHK(c, hipEventSynchronize(e1));
+            HIPCHK(c, hipEventRecord(ev[2], c->stream));
+            HIPCHK(c, hipEventSynchronize(ev[2]));
             LAUNCHCHK(c);
-            float ms = 0.f;
-            HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
-            if (ms < best_ms) {
-                best_ms = ms;
-                best = tpk;
+            float mr = 0.f, mf = 0.f;
+            HIPCHK(c, hipEventElapsedTime(&mr, ev[0], ev[1]));
+            HIPCHK(c, hipEventElapsedTime(&mf, ev[1], ev[2]));
+            const float cost = mf / 6.0f + mr / (float)interval;
+            if (cost < best_cost) {
+                best_cost = cost;
+                best = k;
             }
         }
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
+        for (hipEvent_t& e : ev) (void)hipEventDestroy(e);
     }
-    c->P.tpk = best;
-    if ((s = alloc_list(c, c->P.cap)) != MD_OK) return s;
-    c->have_list = false;
-    if ((s = build_list(c)) != MD_OK) return s;
+    if ((s = apply(best)) != MD_OK) return s;
     if ((s = ensure_list_and_forces(c)) != MD_OK) return s;
+    if ((s = sync_states(c)) != MD_OK) return s;
+    for (int b = 0; b < c->nbox; ++b) c->st_h[b].built = built[b];
+    if ((s = push_states(c)) != MD_OK) return s;
     if (cache_path && !from_cache) {
         std::ofstream out(cache_path, std::ios::app);
-        if (out) out << key << " " << best << "\n";
+        if (out) out << key << " " << best.tpk << " " << (best.tile ? 1 : 0) << " " << best.pct << "\n";
     }
     return MD_OK;
 }

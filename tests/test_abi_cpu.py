@@ -27,9 +27,9 @@ def test_every_declared_symbol_is_exported():
 
 
 def test_struct_sizes_match_header_layout():
-    # md_params: int64 + 3 doubles + 4 doubles + 6 int32 + 6 uint64
-    assert C.sizeof(B.md_params) == 8 + 24 + 32 + 24 + 48
-    assert C.sizeof(B.md_stats) == 5 * 8 + 4 * 4 + 8 + 8 + 8 + 8 + 8
+    # md_params: int64 + 3 doubles + 4 doubles + 6 int32 + 1 double + 5 uint64
+    assert C.sizeof(B.md_params) == 8 + 24 + 32 + 24 + 8 + 40
+    assert C.sizeof(B.md_stats) == 5 * 8 + 4 * 4 + 8 + 8 + 8 + 8 + 8 + 4 + 12 + 8
     # md_bubble_info: 4 int32 + 3 doubles + 1 double + 3 int64
     assert C.sizeof(B.md_bubble_info) == 16 + 24 + 8 + 24
 
@@ -53,6 +53,9 @@ def test_null_safety():
 
 BAD = [
     dict(n=1),
+    dict(cell_scale=0.5),
+    dict(cell_scale=2.5),
+    dict(cell_scale=float("nan")),
     dict(rc=0.0),
     dict(rc=float("nan")),
     dict(skin=-0.1),

@@ -97,7 +97,8 @@ def test_autotune_picks_a_layout_and_caches_it(tmp_path):
         assert (np.linalg.norm(F - Fr, axis=1) / A).max() <= 1e-12
         lines = [l for l in open(cache) if l.strip()]
         assert len(lines) == 1  # the second context read the cache instead of timing again
-        assert lines[0].split()[-1] == str(st["threads_per_key"])
+        f = lines[0].split()
+        assert f[4:] == [str(st["threads_per_key"]), str(st["row_tiles"]), str(round(st["cell_scale"] * 100))]
 
 
 def test_fcc1m_full_parity():
