@@ -11,6 +11,12 @@ Prints one JSON line.  Timing: HIP events on the library's stream around
 exactly K steps after W warm-up steps, with torch.cuda.synchronize() on both
 sides.  The force kernel's average launch time comes from the library's own
 HIP events (md_set_timing) over the same timed region.
+
+Beside the headline the default run adds: the same 32M box with the
+displacement rebuild rule, compact figures of the 4000-particle FP64 box
+(100 steps), the 1M box in both precisions (100 steps) and the 256-box
+ensemble (autotuned, captured graphs) with a one-box-at-a-time baseline on a
+subset, and the FP64 CPU oracle on a bounded sample of the 32M run.
 """
 from __future__ import annotations
 
@@ -48,7 +54,8 @@ def pairs_within_rc_per_particle(rho, rc):
 REBUILD_BYTES_PER_PARTICLE = 260.0  # binning 32, permute 104, list build 124 (per particle per rebuild)
 MIXED_NOTE = ("pair forces in FP32 on exact fixed-point cell-relative separations; positions, velocities, "
               "integration and energy totals in FP64")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_force_mixed_fcc32m_hbm_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_force_t_fcc32m_hbm_traffic.txt")
+FLOPS_FILE = os.path.join(ROOT, "profiles", "k_force_t_fcc32m_valu_flops.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1210_3450_amd", "csrc", f) for f in ("md_kernels.hip", "md_internal.h")]
 
 
@@ -61,27 +68,43 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per force launch from the committed counter summary, or None when
-    the kernel sources changed since the counters were taken."""
+def summary_value(path, key):
+    """A "key: value" figure of a committed counter summary, or None when the
+    kernel sources changed since the counters were taken (or it is absent)."""
     try:
         kv = {}
-        with open(TRAFFIC_FILE) as fh:
+        with open(path) as fh:
             for line in fh:
                 parts = line.split()
                 if len(parts) == 2 and parts[0].endswith(":"):
                     kv[parts[0][:-1]] = parts[1]
         if kv.get("kernel_sources_sha256") != kernel_source_hash():
             return None
-        return float(kv["hbm_bytes_per_launch"])
+        return float(kv[key])
     except (OSError, KeyError, ValueError):
         return None
 
 
-def run_gpu(B, torch, w, precision, steps, warmup, tpk=0, flags=0):
+def measured_traffic():
+    """HBM bytes per force launch (TCC-to-memory read and write requests by size)."""
+    return summary_value(TRAFFIC_FILE, "hbm_bytes_per_launch")
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def run_gpu(B, torch, w, precision, steps, warmup, tpk=0, flags=0, rebuild=0):
     stream = torch.cuda.Stream()
     p = B.make_params(w.n, w.box, rc=w.rc, skin=w.skin, dt=w.dt, precision=precision, threads_per_key=tpk,
-                      flags=flags)
+                      flags=flags, rebuild=rebuild)
     with torch.cuda.stream(stream):
         ctx = B.Context(p, stream=stream)
         ctx.set_state(w.pos, w.vel)
@@ -111,6 +134,7 @@ def run_gpu(B, torch, w, precision, steps, warmup, tpk=0, flags=0):
         "list_cap": st["list_cap"],
         "max_list_len": st["max_list_len"],
         "threads_per_key": st["threads_per_key"],
+        "row_tiles": st["row_tiles"],
         "E_per_particle_end": (ke + pe) / w.n,
         "warmup_s": warm_s,
     }
@@ -138,16 +162,18 @@ def copy_bandwidth(torch, nbytes=1 << 30, reps=5):
 
 def cpu_baseline(w, sample_steps):
     """The FP64 oracle, as it stands, on the same 32M state: its initial list
-    build plus sample_steps velocity-Verlet steps (DUTC rebuilds included)."""
+    build plus sample_steps velocity-Verlet steps (DUTC rebuilds included), so
+    that the sample holds list builds in about the share the GPU run has."""
     import oracle
     t0 = time.time()
     r = oracle.run(w.pos, w.vel, w.box, sample_steps, rc=w.rc, skin=w.skin, dt=w.dt)
     t = time.time() - t0
     return {"value": w.n * sample_steps / t, "unit": "particle-steps/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
+            "kind": "oracle", "steps": int(r.steps), "rebuilds": int(r.rebuilds), "wall_s": t,
+            "cpu_model": cpu_model(),
             "sample": "FP64 CPU oracle on the same %d-particle state: initial cell list + pair list, then %d "
-                      "velocity-Verlet steps with DUTC rebuilds (%d builds), %.1f s wall" %
-                      (w.n, sample_steps, r.rebuilds, t)}
+                      "velocity-Verlet steps with DUTC rebuilds (%d list builds in all), %.1f s wall on %d "
+                      "threads of %s" % (w.n, sample_steps, r.rebuilds, t, oracle.num_threads(), cpu_model())}
 
 
 def drift_stats(ke, pe, n, dt, every):
@@ -383,6 +409,84 @@ def workload_batch(B, torch, args):
             "rebuilds": st["rebuilds"], "max_rel_energy_dev_over_boxes": float(max(drift))}
 
 
+def extra_keys(B, torch, args):
+    """Compact figures of the other workloads for the one-line record: the
+    4000-particle FP64 box (100 graph steps), the 1M box in both precisions
+    (100 steps each) and the 256-box ensemble (autotuned, captured graphs) with
+    a one-box-at-a-time baseline on a subset of its boxes."""
+    import tempfile
+    from paper_1210_3450_amd import inputs
+    out = {}
+    stream = torch.cuda.Stream()
+    # 4000 particles, FP64 and FP32-mixed, captured graphs
+    w = inputs.small_nve()
+    for name, prec in (("fp64", B.MD_PREC_FP64), ("fp32_mixed", B.MD_PREC_FP32_MIXED)):
+        with torch.cuda.stream(stream):
+            ctx = B.Context(B.make_params(w.n, w.box, precision=prec, flags=B.MD_F_GRAPH), stream=stream)
+            ctx.set_state(w.pos, w.vel)
+            ctx.step(20)
+            ms = timed_steps(ctx, torch, stream, 100)
+            ctx.close()
+        out["c1_fcc4000_%s_us_per_step" % name] = ms * 1e3 / 100
+    # 1,048,576 particles, both precisions, default layout
+    w = inputs.medium_1m()
+    for name, prec in (("fp64", B.MD_PREC_FP64), ("fp32_mixed", B.MD_PREC_FP32_MIXED)):
+        with torch.cuda.stream(stream):
+            ctx = B.Context(B.make_params(w.n, w.box, precision=prec, flags=B.MD_F_GRAPH), stream=stream)
+            ctx.set_state(w.pos, w.vel)
+            ctx.step(20)
+            st0 = ctx.stats()
+            ms = timed_steps(ctx, torch, stream, 100)
+            st = ctx.stats()
+            ctx.close()
+        out["c2_fcc1m_%s_ms_per_step" % name] = ms / 100
+        out["c2_fcc1m_%s_rebuilds_per_100" % name] = st["rebuilds"] - st0["rebuilds"]
+    # 256 boxes of uneven size and density, one context, autotuned
+    spec = inputs.batch_spec(256)
+    boxes = [inputs.batch_box(spec, b) for b in range(256)]
+    ntot = int(sum(p.shape[0] for p, _, _ in boxes))
+    pos = np.concatenate([p for p, _, _ in boxes])
+    vel = np.concatenate([v for _, v, _ in boxes])
+    cache = os.path.join(tempfile.gettempdir(), "mdgpu_bench_tune_%d.txt" % os.getpid())
+    with torch.cuda.stream(stream):
+        params = [B.make_params(p.shape[0], L, precision=B.MD_PREC_FP32_MIXED, flags=B.MD_F_GRAPH)
+                  for p, _, L in boxes]
+        ctx = B.Context(params, stream=stream)
+        ctx.set_state(pos, vel)
+        ke0, pe0 = ctx.batch_energy()
+        ctx.autotune(cache)
+        ctx.step(20)
+        ms = timed_steps(ctx, torch, stream, args.extra_batch_steps)
+        st = ctx.stats()
+        ctx.close()
+        # one box at a time through the single-box path: every 16th box by size
+        order = np.argsort(spec.n)
+        sub = order[:: max(1, 256 // args.extra_baseline_boxes)][: args.extra_baseline_boxes]
+        t_one, n_one = 0.0, 0
+        for k in sub:
+            p, v, L = boxes[int(k)]
+            c1 = B.Context(B.make_params(p.shape[0], L, precision=B.MD_PREC_FP32_MIXED, flags=B.MD_F_GRAPH),
+                           stream=stream)
+            c1.set_state(p, v)
+            c1.step(5)
+            t_one += timed_steps(c1, torch, stream, 20)
+            n_one += p.shape[0] * 20
+            c1.close()
+    try:
+        os.remove(cache)
+    except OSError:
+        pass
+    E0 = (np.asarray(ke0) + np.asarray(pe0)) / spec.n
+    out["c5_ensemble256_ms_per_step"] = ms / args.extra_batch_steps
+    out["c5_ensemble256_particle_steps_per_s"] = ntot * args.extra_batch_steps / (ms / 1e3)
+    out["c5_one_box_at_a_time_particle_steps_per_s"] = n_one / (t_one / 1e3)
+    out["c5_one_box_at_a_time_boxes"] = int(len(sub))
+    out["c5_autotuned"] = {"threads_per_key": st["threads_per_key"], "row_tiles": st["row_tiles"],
+                           "cell_scale": st["cell_scale"]}
+    out["c5_E0_per_particle_min_max"] = [float(E0.min()), float(E0.max())]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -393,12 +497,17 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-fast-rcp", action="store_true",
                     help="skip the FP64 run with the hardware reciprocal and its correction")
-    ap.add_argument("--no-half", action="store_true",
-                    help="skip the half-list (Newton's third law) runs of both precisions")
+    ap.add_argument("--half", action="store_true",
+                    help="add the half-list (Newton's third law) runs of both precisions")
     ap.add_argument("--half-steps", type=int, default=100,
                     help="timed steps of each half-list run (about 48 ms per step at 32M)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--cpu-steps", type=int, default=20,
+                    help="oracle steps of the CPU sample (20 at 32M hold 4-5 list builds)")
+    ap.add_argument("--no-extra", action="store_true", help="skip the compact figures of the other workloads")
+    ap.add_argument("--no-displacement", action="store_true", help="skip the displacement-rule run")
+    ap.add_argument("--extra-batch-steps", type=int, default=100)
+    ap.add_argument("--extra-baseline-boxes", type=int, default=16)
     ap.add_argument("--workload", default="fcc32m",
                     choices=["fcc32m", "fcc4000", "fcc1m", "cavitation", "batch256"])
     ap.add_argument("--drift-steps", type=int, default=10000)
@@ -455,8 +564,15 @@ def main():
         print("bench: FP64 with the corrected hardware reciprocal %.3f ms/step" % fp64_fast["ms_per_step"],
               file=sys.stderr, flush=True)
 
+    disp = None
+    if not args.no_displacement:
+        disp = run_gpu(B, torch, w, B.MD_PREC_FP32_MIXED, args.steps, args.warmup, args.tpk, tile_flag,
+                       B.MD_REBUILD_DISPLACEMENT)
+        print("bench: FP32-mixed, displacement rule %.3f ms/step" % disp["ms_per_step"], file=sys.stderr,
+              flush=True)
+
     half = {}
-    if not args.no_half:
+    if args.half:
         for name, prec in (("fp32_mixed", B.MD_PREC_FP32_MIXED), ("fp64", B.MD_PREC_FP64)):
             if prec == B.MD_PREC_FP64 and args.no_fp64:
                 continue
@@ -476,6 +592,12 @@ def main():
     step_achieved = step_bpp * w.n / (mixed["ms_per_step"] / 1e3) / 1e9
     traffic = measured_traffic() if args.ncell == 200 else None
     copy_gbs = copy_bandwidth(torch)
+    # vector roofline of the force pass: the method's flops (25 per unordered pair within
+    # rc) and the FP32 flops the kernel issues (SQ_INSTS_VALU_FLOPS_FP32 + _TRANS per launch,
+    # from the committed counter summary) per launch time, against the FP32 vector peak
+    alg_tflops = FLOP_PER_PAIR * pairs / (mixed["force_ms_avg"] / 1e3) / 1e12
+    issued = summary_value(FLOPS_FILE, "fp32_flops_per_launch") if args.ncell == 200 else None
+    issued_tflops = issued / (mixed["force_ms_avg"] / 1e3) / 1e12 if issued else None
 
     out = {
         "metric": "particle-steps/s + Gflop/s, 32M LJ, FP32-mixed vs FP64 on 1 MI355X",
@@ -499,17 +621,32 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_unit": "HBM bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, copy-calibrated)",
-                     "kernel": "k_force<FP32_MIXED> (pair forces + kicks + drift)",
+                     "kernel": "k_force_t<kForceMid> (row tiles staged in LDS: pair forces + kicks + drift)",
                      "bytes_per_particle": bpp, "launch_ms_avg": mixed["force_ms_avg"],
                      "copy_gbs_measured": copy_gbs, "frac_of_copy": achieved / copy_gbs},
         "step_roofline": {"bound": "hbm", "achieved": step_achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                           "frac": step_achieved / HBM_PEAK_GBS, "frac_of_copy": step_achieved / copy_gbs,
                           "bytes_per_particle_step": step_bpp,
                           "rebuild_interval_steps": interval},
+        "vector_roofline": {"bound": "alu", "kernel": "k_force_t<kForceMid>", "unit": "TFLOP/s",
+                            "peak": FP32_VEC_PEAK_TFLOPS, "algorithmic": alg_tflops,
+                            "frac": alg_tflops / FP32_VEC_PEAK_TFLOPS, "issued": issued_tflops,
+                            "issued_frac": issued_tflops / FP32_VEC_PEAK_TFLOPS if issued_tflops else None,
+                            "convention": "algorithmic: 25 flop per unordered pair within rc; issued: FP32 "
+                                          "lane flops counted by SQ_INSTS_VALU_FLOPS_FP32(+_TRANS)"},
     }
     if fp64 is not None:
+        f64_tflops = FLOP_PER_PAIR * pairs / (fp64["force_ms_avg"] / 1e3) / 1e12
         out["fp64"] = dict(fp64, gflops=FLOP_PER_PAIR * pairs / (fp64["ms_per_step"] / 1e3) / 1e9,
-                           force_achieved_gbs=force_bytes / (fp64["force_ms_avg"] / 1e3) / 1e9)
+                           force_achieved_gbs=force_bytes / (fp64["force_ms_avg"] / 1e3) / 1e9,
+                           force_hbm_frac=force_bytes / (fp64["force_ms_avg"] / 1e3) / 1e9 / HBM_PEAK_GBS,
+                           force_vector_frac=f64_tflops / FP64_VEC_PEAK_TFLOPS,
+                           force_algorithmic_tflops=f64_tflops)
+    if disp is not None:
+        out["mixed_displacement_rule"] = dict(
+            disp, rebuild_interval_steps=args.steps / disp["rebuilds"] if disp["rebuilds"] else None,
+            note="MD_REBUILD_DISPLACEMENT: rebuild when the largest displacement since the last build "
+                 "exceeds skin/2")
     if fp64_fast is not None:
         out["fp64_fast_rcp"] = dict(fp64_fast, gflops=FLOP_PER_PAIR * pairs / (fp64_fast["ms_per_step"] / 1e3) / 1e9,
                                     note="FP64 with 1/r^2 from the hardware reciprocal and the Sec. III.C "
@@ -520,8 +657,11 @@ def main():
                                            "flushed with atomic adds, integration "
                                            "as a separate pass; force_ms_avg covers clearing F, the force pass "
                                            "and the integration pass")
+    if not args.no_extra and args.ncell == 200:
+        print("bench: other workloads ...", file=sys.stderr, flush=True)
+        out.update(extra_keys(B, torch, args))
     if not args.no_cpu:
-        print("bench: CPU oracle sample ...", file=sys.stderr, flush=True)
+        print("bench: CPU oracle sample (%d steps) ..." % args.cpu_steps, file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
     print(json.dumps(out), flush=True)
 

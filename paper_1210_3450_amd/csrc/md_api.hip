@@ -1453,9 +1453,24 @@ md_status md_autotune(md_ctx* c, const char* cache_path) {
     const double interval = c->steps > 0 && built[0] > 0 ? (double)c->steps / built[0] : 10.0;
     const bool fallback0 = c->tile_fallback;
 
-    // re-lay the grid and the list for candidate k and build the list
+    // re-lay the grid and the list for candidate k and build the list.  The slots go
+    // back to caller order first (as md_set_state leaves them), so that the order
+    // within cells after the last build does not depend on the candidates timed
+    // before it: a tuned context and one that reads the choice from the cache step
+    // identically.
     auto apply = [&](const Cand& k) -> md_status {
         md_status r;
+        if ((r = sync_states(c)) != MD_OK) return r;
+        launch_get_state(c->D, c->P, c->bk_pos, c->bk_vel, c->nwave, c->stream);
+        for (int b = 0; b < c->nbox; ++b) {
+            BoxState& st = c->st_h[b];
+            st.sq = st.sp = 0;
+            st.need = 0;
+            st.rebuild = 0;
+        }
+        if ((r = push_states(c)) != MD_OK) return r;
+        launch_set_state(c->D, c->P, c->bk_pos, c->bk_vel, c->nwave, c->stream);
+        LAUNCHCHK(c);
         c->cell_scale = k.pct / 100.0;
         c->tune_gather = !k.tile;
         c->tile_fallback = fallback0;

@@ -168,6 +168,20 @@ def batch_box(spec: BatchSpec, b: int):
     return pos, vel, L
 
 
+def free_gas(vmax: float, seed: int = 3):
+    """8 particles 10 apart in a box of side 20, so that no pair comes within a
+    list radius for hundreds of steps: the first moves at exactly vmax along x,
+    the others more slowly in random directions.  Returns (positions,
+    velocities, L)."""
+    g = np.array([[i, j, k] for i in (0, 1) for j in (0, 1) for k in (0, 1)], dtype=np.float64)
+    q = 5.0 + 10.0 * g
+    rng = np.random.Generator(np.random.PCG64(seed))
+    v = rng.normal(size=(8, 3))
+    v *= (0.9 * vmax * rng.uniform(0.1, 1.0, 8) / np.linalg.norm(v, axis=1))[:, None]
+    v[0] = (vmax, 0.0, 0.0)
+    return q, v, 20.0
+
+
 def random_box(n: int, L, seed: int, min_sep: float = 0.0) -> np.ndarray:
     """Uniform random positions in [0, L) (no overlap control unless min_sep > 0,
     in which case a jittered cubic lattice with spacing >= min_sep is used)."""

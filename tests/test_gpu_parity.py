@@ -691,3 +691,21 @@ def test_thermostat_ensemble_reaches_each_box_temperature(precision):
     np.testing.assert_allclose(T[T.shape[0] // 2:].mean(axis=0), T0, rtol=0.06)
     H = ke + pe + th
     assert (np.abs(H - H[0]).max(axis=0) / ke[0]).max() < 5e-3
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("dt,vmax,skin", [(2.0 ** -7, 0.5, 0.3), (2.0 ** -6, 0.25, 0.5)])
+def test_dutc_cadence_of_free_particles(precision, dt, vmax, skin):
+    """Free particles whose fastest one moves at vmax: the DUTC rule (Sec. II.A)
+    rebuilds every K = floor(skin / (2 vmax dt)) + 1 steps, as the oracle does."""
+    b = B()
+    K = int(np.floor(skin / (2.0 * vmax * dt))) + 1
+    q, v, L = inputs.free_gas(vmax)
+    for n in (K - 1, K, 2 * K, 3 * K + 1):
+        with b.Context(b.make_params(8, L, dt=dt, skin=skin, precision=precision)) as c:
+            c.set_state(q, v)
+            c.step(n)
+            st = c.stats()
+            _, vg = c.get_state()
+        assert st["rebuilds"] == 1 + n // K == oracle.run(q, v, L, n, dt=dt, skin=skin).rebuilds, n
+        np.testing.assert_array_equal(vg.cpu().numpy(), v)

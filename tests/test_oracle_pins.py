@@ -304,6 +304,26 @@ def test_dutc_list_stays_valid_and_never_fails():
     assert bad.missed_pairs > 0
 
 
+# (dt, vmax, skin): dt * vmax is a power of two times a small integer, so the DUTC
+# sum D = k * dt * vmax is exact; in the last case skin / (2 vmax dt) = 64 exactly and
+# 2 D = skin at step 64 must not rebuild (the rule is a strict inequality)
+DUTC_CADENCE = [(2.0 ** -7, 0.5, 0.3), (2.0 ** -8, 0.75, 0.3), (2.0 ** -6, 0.25, 0.5)]
+
+
+@pytest.mark.parametrize("dt,vmax,skin", DUTC_CADENCE)
+def test_dutc_cadence_of_free_particles(dt, vmax, skin):
+    """Sec. II.A's DUTC bound grows by dt * max|v| per step and the list is rebuilt
+    once 2 D exceeds the skin: free particles whose fastest one moves at vmax are
+    rebuilt every K = floor(skin / (2 vmax dt)) + 1 steps exactly."""
+    K = int(math.floor(skin / (2.0 * vmax * dt))) + 1
+    q, v, L = inputs.free_gas(vmax)
+    for n in (K - 1, K, 2 * K - 1, 2 * K, 5 * K + 3):
+        r = oracle.run(q, v, L, n, dt=dt, skin=skin)
+        assert r.rebuilds == 1 + n // K, (n, K, r.rebuilds)  # the initial build counts
+        np.testing.assert_array_equal(r.v, v)  # no forces: velocities unchanged
+        assert r.D == pytest.approx((n % K) * dt * vmax, abs=1e-15)
+
+
 def test_momentum_and_energy_conservation():
     """Total momentum stays ~0; total energy stays bounded with Eq. (1) at dt = 0.005."""
     w = inputs.small_nve()
