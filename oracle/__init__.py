@@ -29,6 +29,15 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _CFLAGS = ["-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-shared", "-fPIC", "-std=c11"]
 
 
+def build_sanitized(out: str) -> str:
+    """Compile md_oracle.c with AddressSanitizer and UndefinedBehaviorSanitizer into
+    out (load it by setting MD_ORACLE_LIB, with gcc's libasan preloaded)."""
+    flags = [f for f in _CFLAGS if not f.startswith("-O")]
+    subprocess.check_call(["gcc", "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                           "-fno-sanitize-recover=all", *flags, "-o", out, _SRC, "-lm"])
+    return out
+
+
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (no FMA contraction, no fast-math)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
@@ -62,9 +71,12 @@ class OrcStats(C.Structure):
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build(force=True)
-        L = C.CDLL(_LIB)
+        path = os.environ.get("MD_ORACLE_LIB")  # another build of md_oracle.c (sanitizer runs)
+        if not path:
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build(force=True)
+            path = _LIB
+        L = C.CDLL(path)
         L.orc_num_threads.restype = C.c_int
         L.orc_coeffs.argtypes = [C.c_double, C.c_int, P_D, P_D]
         L.orc_pair_v.argtypes = [C.c_double, C.c_double, C.c_double]

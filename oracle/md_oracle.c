@@ -250,7 +250,7 @@ static int64_t scan_partners(const cell_list *cl, const double *q, const double 
                     }
                 }
             }
-    if (cnt <= cap) qsort(out, (size_t)cnt, sizeof(int32_t), cmp_i32);
+    if (cnt > 1 && cnt <= cap) qsort(out, (size_t)cnt, sizeof(int32_t), cmp_i32);  /* out may be NULL when cap = 0 */
     return cnt;
 }
 

@@ -1526,7 +1526,11 @@ md_status md_autotune(md_ctx* c, const char* cache_path) {
 }
 
 const char* md_status_str(md_status s) {
-    const int k = -(int)s;
+    // a C caller may pass any int; its bits are read as an int, since reading an
+    // out-of-range value through the C++ enum type is undefined
+    int v;
+    std::memcpy(&v, &s, sizeof v);
+    const int k = -v;
     if (k < 0 || k >= (int)(sizeof(kStatusStr) / sizeof(kStatusStr[0]))) return "MD_UNKNOWN";
     return kStatusStr[k];
 }
