@@ -620,7 +620,9 @@ def main():
         "mixed": mixed,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "traffic_unit": "HBM bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, copy-calibrated)",
+                     "traffic_unit": "HBM bytes per launch from the TCC-to-memory read and write request counters by "
+                                     "request size (a plain 1 GiB copy reads exactly 1 GiB and writes 1 GiB by the same "
+                                     "rule)",
                      "kernel": "k_force_t<kForceMid> (row tiles staged in LDS: pair forces + kicks + drift)",
                      "bytes_per_particle": bpp, "launch_ms_avg": mixed["force_ms_avg"],
                      "copy_gbs_measured": copy_gbs, "frac_of_copy": achieved / copy_gbs},
