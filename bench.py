@@ -60,11 +60,18 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_1210_3450_amd", "csrc", f) for f in 
 
 
 def kernel_source_hash():
+    """SHA-256 of the kernel sources with comments and blank lines removed, so that a
+    change of wording in a comment does not disown the counters of an unchanged kernel."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(f, "rb") as fh:
-            h.update(fh.read())
+        with open(f) as fh:
+            text = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
+        for line in text.splitlines():
+            line = re.sub(r"//.*", "", line).rstrip()
+            if line.strip():
+                h.update(line.encode() + b"\n")
     return h.hexdigest()
 
 

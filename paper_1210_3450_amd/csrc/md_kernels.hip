@@ -1,19 +1,22 @@
 // md_kernels.hip -- gfx950 kernels of the short-range LJ hot path.
 //
 // Per step (velocity Verlet, Sec. III.B; list validity by DUTC, Sec. II.A):
-//   k_force<kForceMid>  close step n (v += hF), open step n+1 (v += hF, q += dt v),
-//                       per-box max |v|^2 for the DUTC bound
-//   k_dutc              D += dt * max|v|; flag a rebuild when 2D > skin
-//   rebuild chain       (early exit unless flagged) wrap + cell id, counting sort
-//                       by cell, permute into coalesced arrays, build the pair list
-// and at chunk ends k_force<kForceEnd> (closing half kick, F stored) followed by
-// k_kick_drift at the start of the next chunk.
+//   force pass (kForceMid)  close step n (v += hF), open step n+1 (v += hF, q += dt v),
+//                           per-box max |v|^2 for the DUTC bound: k_force_t (FP32-mixed,
+//                           partners from a row tile staged in LDS) or k_force (gather
+//                           format: FP64, and FP32-mixed when tiles do not fit)
+//   k_dutc                  D += dt * max|v|; flag a rebuild when 2D > skin
+//   rebuild chain           (early exit unless flagged) wrap + cell id, counting sort
+//                           by cell, permute into coalesced arrays, row tiles, pair list
+// and at chunk ends the force pass in kForceEnd mode (closing half kick, F stored)
+// followed by k_kick_drift at the start of the next chunk.
 //
-// The force kernel follows Algorithm 1 (Sec. III.C): a full list, each key's
-// force summed by its own lane(s) and never scattered, the momentum update fused
-// into the force pass.  The truncation mask of Algorithm 1 becomes a branch
-// (lanes of a wavefront are masked by hardware).  Parallel work is one lane (or
-// tpk lanes) per key over a wave-blocked ELL list, so list reads are coalesced.
+// The force passes follow Algorithm 1 (Sec. III.C): a full list, each key's force
+// summed by its own lane(s) and never scattered, the momentum update fused into
+// the force pass.  The truncation mask of Algorithm 1 becomes a select, or for the
+// Eq. (1) cutoff on the FP32-mixed passes a clamp of 1/r^2 at 1/rc^2 (f(rc) = 0);
+// no lane branches on it.  Parallel work is one lane (or tpk lanes) per key over a
+// wave-blocked ELL list, so list reads are coalesced.
 #include <math.h>
 
 #include <type_traits>
@@ -28,8 +31,6 @@ __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 // Index of the calling wavefront within its block, in a scalar register.
 __device__ __forceinline__ int wave_in_block() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
 
-// A wave-uniform read of a value the running kernel does not write, through the
-// constant address space, so it becomes a scalar load (scalar cache).
 // Streaming accesses of the force pass (list chunks, velocities): each byte is used
 // once per pass, so they carry the non-temporal hint and leave the L2 to the partner
 // records that neighbouring wavefronts gather again.
@@ -41,6 +42,8 @@ __device__ __forceinline__ uint4 ld_stream(const uint4* p) {
 __device__ __forceinline__ double ld_stream(const double* p) { return __builtin_nontemporal_load(p); }
 __device__ __forceinline__ void st_stream(double* p, double v) { __builtin_nontemporal_store(v, p); }
 
+// A wave-uniform read of a value the running kernel does not write, through the
+// constant address space, so it becomes a scalar load (scalar cache).
 __device__ __forceinline__ int ld_const(const int32_t* p) {
     return *reinterpret_cast<const __attribute__((address_space(4))) int32_t*>(
         reinterpret_cast<uintptr_t>(p));
