@@ -25,6 +25,7 @@ using namespace mdg;
 namespace {
 
 constexpr int kChunk = 200;      // steps enqueued between status checks
+constexpr int64_t kTileMinN = 1 << 23;  // FP32-mixed boxes from this size take row tiles by default
 constexpr int kGraphSteps = 8;   // continuing steps per captured graph
 
 // Message of the last failed md_create / md_batch_create (no context exists then).
@@ -45,7 +46,7 @@ struct md_ctx {
     int64_t ntotal = 0;
     int32_t nslot = 0, nwave = 0, ntile = 0, nrows = 0;
     bool tile_fallback = false;    // a row tile overflowed its staging capacity: gather format from then on
-    bool tune_gather = false;      // md_autotune chose the gather format over row tiles
+    bool prefer_gather = false;    // gather format over row tiles: by size at creation, or md_autotune's choice
     double cell_scale = 0.0;       // > 0: cell side bound chosen by md_autotune (else the boxes' own)
     Params P{};
     Dev D{};
@@ -405,7 +406,7 @@ void params_refresh(md_ctx* c) {
     // partner from LDS; the gather format serves the other layouts and boxes whose
     // cells are too crowded for a tile's staging capacity.
     P.tile = p.precision == MD_PREC_FP32_MIXED && !P.half && P.tpk == 1 && !(p.flags & MD_F_TILE_OFF) &&
-                     !c->tile_fallback && !c->tune_gather
+                     !c->tile_fallback && !c->prefer_gather
                  ? 1
                  : 0;
     P.kt = kRtBlock;
@@ -800,9 +801,18 @@ md_status create_impl(const md_params* boxes, int32_t nbox, void* stream, md_ctx
     // per key to fill the chip; large ones are bound by partner gathers, where the
     // FP64 path's 32-byte records gain from two lanes reading adjacent entries
     if (tpk == 0) tpk = c->ntotal < 262144 ? 4 : (c->prm.precision == MD_PREC_FP64 ? 2 : 1);
-    // the FP32-mixed row-tile path takes one lane per key at every size
-    if (c->prm.threads_per_key == 0 && c->prm.precision == MD_PREC_FP32_MIXED && !(c->prm.flags & MD_F_TILE_OFF))
-        tpk = 1;
+    // Row tiles pay off on large boxes only: at 13.8M particles (FCC, density 0.5) their
+    // force pass is 11% and the step 3.5% faster than the gather format's, at 4M particles
+    // and below the gather format is 7-25% faster per step (the tile cuts cost rebuild time
+    // and the gather pass's partners still hit in L2).  So the FP32-mixed default takes
+    // them for a largest box of kTileMinN particles or more (md_autotune measures instead).
+    int64_t nmax = 0;
+    for (const md_params& bp : c->boxes) nmax = std::max(nmax, bp.n);
+    const bool mixed = c->prm.precision == MD_PREC_FP32_MIXED;
+    const bool tiles = mixed && !(c->prm.flags & (MD_F_TILE_OFF | MD_F_HALF_LIST)) &&
+                       ((c->prm.flags & MD_F_TILE_ON) || nmax >= kTileMinN);
+    if (c->prm.threads_per_key == 0 && tiles) tpk = 1;
+    c->prefer_gather = mixed && !tiles;
     if (c->prm.flags & MD_F_HALF_LIST) tpk = 1;
     c->P.tpk = tpk;
     params_refresh(c);
@@ -1472,7 +1482,7 @@ md_status md_autotune(md_ctx* c, const char* cache_path) {
         launch_set_state(c->D, c->P, c->bk_pos, c->bk_vel, c->nwave, c->stream);
         LAUNCHCHK(c);
         c->cell_scale = k.pct / 100.0;
-        c->tune_gather = !k.tile;
+        c->prefer_gather = !k.tile;
         c->tile_fallback = fallback0;
         c->P.tpk = k.tpk;
         layout(c);

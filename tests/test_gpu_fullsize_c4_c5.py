@@ -3,8 +3,8 @@
 Cavitation (Sec. IV.A protocol): 128^3 simple-cubic sites at density 0.7
 (2,097,152 particles, rc = 3.0, skin 0.3) held at T = 0.9 by the Nose-Hoover
 thermostat for 200 steps, every length scaled by 1.1, then 200 NVE steps on the
-FP32-mixed path.  Lists are uneven after the expansion; all cell ids must be
-bit-exact, 2000 sampled neighbour sets bit-exact (a random sample plus the
+FP32-mixed path (default format, and row tiles).  Lists are uneven after the
+expansion; all cell ids must be bit-exact, 2000 sampled neighbour sets bit-exact (a random sample plus the
 longest and shortest lists) and the sampled forces within 1e-5 of the FP64
 oracle.
 
@@ -37,14 +37,17 @@ def B():
     return binding
 
 
-def test_cavitation_2m_after_expansion_sampled_parity():
+@pytest.mark.parametrize("tiles", [False, True], ids=["default", "row-tiles"])
+def test_cavitation_2m_after_expansion_sampled_parity(tiles):
     b = B()
     w = inputs.cavitation_liquid()
     assert w.n == 2097152
     alpha = 1.1
     L1 = w.box[0] * alpha
     rl = w.rc + w.skin
-    with b.Context(b.make_params(w.n, w.box, rc=w.rc, skin=w.skin, dt=w.dt, precision=b.MD_PREC_FP32_MIXED)) as c:
+    flags = b.MD_F_TILE_ON if tiles else 0
+    with b.Context(b.make_params(w.n, w.box, rc=w.rc, skin=w.skin, dt=w.dt, precision=b.MD_PREC_FP32_MIXED,
+                                 flags=flags)) as c:
         c.set_state(w.pos, w.vel)
         c.set_thermostat(w.T, 0.5)
         c.step(200)

@@ -272,23 +272,28 @@ def test_row_tile_overflow_falls_back_to_gathers():
     idx = np.indices((m, m, m)).reshape(3, -1).T.astype(np.float64)
     q = np.mod((idx + 0.5) * sp + rng(21).uniform(-0.1, 0.1, size=idx.shape) * sp, L)
     v = inputs.maxwell_boltzmann(q.shape[0], 0.5, 1.0, rng(22))
-    F, traj = {}, {}
+    F, traj, sets, tiles = {}, {}, {}, {}
     # one lane per key in both (the gather format's default for small boxes is four);
     # a tiny step: at this density the forces are large.  Were the row tiles kept,
     # the force pass would skip every (overflowing) tile and the forces would differ.
-    for flag in (0, b.MD_F_TILE_OFF):
+    on, off = b.MD_F_TILE_ON, b.MD_F_TILE_OFF
+    for flag in (on, off):
         with make_ctx(q, v, L, precision=1, flags=flag, dt=1e-6, threads_per_key=1) as c:
             F[flag] = c.compute_forces().cpu().numpy()
             kp, pl = c.get_neighbors()
+            sets[flag] = (kp.cpu().numpy(), pl.cpu().numpy())
             c.step(5)
             traj[flag] = c.get_state()[0].cpu().numpy()
-    np.testing.assert_array_equal(F[0], F[b.MD_F_TILE_OFF])
-    np.testing.assert_array_equal(traj[0], traj[b.MD_F_TILE_OFF])
+            tiles[flag] = c.stats()["row_tiles"]
+    assert tiles[on] == 0 and tiles[off] == 0  # the row-tile context switched formats
+    np.testing.assert_array_equal(F[on], F[off])
+    np.testing.assert_array_equal(traj[on], traj[off])
     kpr, plr = oracle.neighbors(q, L, 2.8)
-    np.testing.assert_array_equal(kp.cpu().numpy(), kpr)
-    np.testing.assert_array_equal(pl.cpu().numpy(), plr)
+    for flag in (on, off):
+        np.testing.assert_array_equal(sets[flag][0], kpr)
+        np.testing.assert_array_equal(sets[flag][1], plr)
     Fr, _, A = oracle.forces(q, L, 2.5, 0.3)
-    assert norm_err(F[0], Fr, A) <= 1e-5
+    assert norm_err(F[on], Fr, A) <= 1e-5
 
 
 @pytest.mark.parametrize("name", CASES)
