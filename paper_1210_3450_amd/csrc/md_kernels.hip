@@ -434,20 +434,11 @@ __global__ __launch_bounds__(kBlock) void k_dutc(Dev d, Params p) {
     }
 }
 
-__global__ void k_flip(Dev d, Params p) {
-    if (!*d.any) return;
-    for (int b = threadIdx.x; b < p.nbox; b += blockDim.x) {
-        BoxState& st = d.st[b];
-        if (st.rebuild) {
-            st.sq ^= 1;
-            st.sp ^= 1;
-        }
-    }
-}
-
-// After a build: longest list over each box's cell tiles, DUTC bound reset, and
-// the "some box rebuilds" gate cleared.  A single block walks every box, so the
-// gate is cleared only after all of them are done.
+// After a build: the permuted buffers become the current ones, longest list over
+// each box's cell tiles, DUTC bound reset, and the "some box rebuilds" gate cleared.
+// A single block walks every box, so the gate is cleared only after all of them are
+// done.  (Between the permutation and this kernel, a rebuilding box's current
+// positions are in buffer sq ^ 1: the list build reads them there.)
 __global__ __launch_bounds__(kBlock) void k_post_build(Dev d, Params p, int with_list) {
     __shared__ int red[kBlock];
     if (!*d.any) return;
@@ -470,6 +461,8 @@ __global__ __launch_bounds__(kBlock) void k_post_build(Dev d, Params p, int with
                 st.built += 1;
                 st.need = max(st.need, red[0]);
             }
+            st.sq ^= 1;
+            st.sp ^= 1;
             st.rebuild = 0;
         }
         __syncthreads();
@@ -481,7 +474,6 @@ __global__ __launch_bounds__(kBlock) void k_post_build(Dev d, Params p, int with
 
 __global__ __launch_bounds__(kBlock) void k_cell_clear(Dev d, Params p) {
     if (!ld_const(d.any)) return;  // no box rebuilds this step
-    if (p.tile && blockIdx.x == 0 && threadIdx.x == 0) d.ntiles[1] = 0;  // longest staged region, rebuilt below
     for (int t = blockIdx.x; t < p.ntile; t += gridDim.x) {
         if (!d.st[d.tile_box[t]].rebuild) continue;
         int4* c = reinterpret_cast<int4*>(d.cell_cnt + (size_t)t * kTile);
@@ -677,93 +669,144 @@ __device__ __forceinline__ void tile_piece(const Dev& d, const BoxGeom& g, int c
 
 // Cuts every row of cells into row tiles, greedily from x = 0: a tile grows by the
 // next cell while its keys stay within kt, its staged region within scap records and
-// its width within kTileWMax cells.  One wavefront per row; the column sums of the
-// 3 x 3 rows around it (cells x = -1 .. n, unwrapped) go to LDS first.  A one-cell
-// tile whose region exceeds scap sets error bit 2 of its box (the context then
-// falls back to the gather format).
+// its width within kTileWMax cells.  One wavefront per row.  The column sums of the
+// 3 x 3 rows around it (cells x = -1 .. n, unwrapped) and the row's own counts go to
+// LDS as prefix sums; every lane then finds, for the cells x it holds, where a tile
+// starting at x would end (a binary search: both sums grow with the tile), and lane 0
+// follows those ends from x = 0, a handful of steps per row.  A one-cell tile whose
+// region exceeds scap sets error bit 2 of its box (the context then falls back to the
+// gather format).
 __global__ __launch_bounds__(kBlock) void k_row_tiles(Dev d, Params p) {
     if (!ld_const(d.any)) return;  // no box rebuilds this step
-    __shared__ int col_all[kBlock / kWave][kMaxCellsPerAxis + 3];  // unwrapped x -> index x + 1
-    __shared__ int hom_all[kBlock / kWave][kMaxCellsPerAxis + 1];
+    constexpr int NWb = kBlock / kWave;
+    __shared__ int col_all[NWb][kMaxCellsPerAxis + 3];  // C[k]: staged counts of unwrapped x < k - 1
+    __shared__ int hom_all[NWb][kMaxCellsPerAxis + 1];  // H[k]: keys of cells x < k
+    __shared__ int nxt_all[NWb][kMaxCellsPerAxis];      // end of the tile that starts at x
     const int wv = wave_in_block(), l = lane_id();
-    int* col = col_all[wv];
-    int* hom = hom_all[wv];
+    int* C = col_all[wv];
+    int* H = hom_all[wv];
+    int* nxt = nxt_all[wv];
+    auto wave_sync = [] {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+    // in-place exclusive prefix sum of a[0 .. len), and a[len] = the total
+    auto prefix = [&](int* a, int len) {
+        int carry = 0;
+        for (int j0 = 0; j0 < len; j0 += kWave) {
+            const int j = j0 + l;
+            const int v = j < len ? a[j] : 0;
+            const int incl = wave_incl_sum(v);
+            if (j < len) a[j] = carry + incl - v;
+            carry += __builtin_amdgcn_readlane(incl, kWave - 1);
+        }
+        if (l == 0) a[len] = carry;
+        wave_sync();
+    };
     for (int row = blockIdx.x * 4 + wv; row < p.nrows; row += gridDim.x * 4) {
         const int b = ld_const(d.row_box + row);
         const BoxGeom g = ld_geom(d.geom + b);
         const int lr = row - g.row_off, nx = g.n[0], ny = g.n[1], nz = g.n[2];
         const int cy = lr % ny, cz = lr / ny;
-        for (int x = l - 1; x <= nx; x += kWave) {
-            const int xw = wrap_idx(x, nx);
-            int sum = 0;
+        // the 9 row starts, then the counts of 4 x positions per lane in flight at once
+        int rs[9];
 #pragma unroll
-            for (int r = 0; r < 9; ++r) {
-                const int yw = wrap_idx(cy + r % 3 - 1, ny), zw = wrap_idx(cz + r / 3 - 1, nz);
-                sum += d.cell_cnt[g.cell_off + (zw * ny + yw) * nx + xw];
+        for (int r = 0; r < 9; ++r)
+            rs[r] = g.cell_off + (wrap_idx(cz + r / 3 - 1, nz) * ny + wrap_idx(cy + r % 3 - 1, ny)) * nx;
+        constexpr int kXu = 4;
+        for (int x0 = l - 1; x0 <= nx; x0 += kWave * kXu) {
+            int sum[kXu], own[kXu];
+#pragma unroll
+            for (int u = 0; u < kXu; ++u) {
+                const int x = x0 + u * kWave, xw = wrap_idx(min(x, nx), nx);
+                sum[u] = 0;
+                if (x <= nx) {
+#pragma unroll
+                    for (int r = 0; r < 9; ++r) sum[u] += d.cell_cnt[rs[r] + xw];
+                }
+                own[u] = x >= 0 && x < nx ? d.cell_cnt[rs[4] + x] : 0;  // r = 4: the row itself
             }
-            col[x + 1] = sum;
-            if (x >= 0 && x < nx) hom[x] = d.cell_cnt[g.cell_off + (cz * ny + cy) * nx + x];
+#pragma unroll
+            for (int u = 0; u < kXu; ++u) {
+                const int x = x0 + u * kWave;
+                if (x <= nx) C[x + 1] = sum[u];
+                if (x >= 0 && x < nx) H[x] = own[u];
+            }
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        wave_sync();
+        prefix(C, nx + 2);
+        prefix(H, nx);
+        // the tile [xa, xb) holds H[xb] - H[xa] keys and stages C[xb + 2] - C[xa] records;
+        // a tile takes at least one cell
+        for (int xa = l; xa < nx; xa += kWave) {
+            int lo = xa + 1, hi = min(nx, xa + kTileWMax);
+            const int h0 = H[xa], c0 = C[xa];
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (H[mid] - h0 <= p.kt && C[mid + 2] - c0 <= p.scap)
+                    lo = mid;
+                else
+                    hi = mid - 1;
+            }
+            nxt[xa] = lo;
+        }
+        wave_sync();
         if (l == 0) {
             const int base = g.cell_off + lr * nx;  // the row's cells hold its tiles in rt_tmp
             int nt = 0, xa = 0, big = 0;
-            bool over = false;
             while (xa < nx) {
-                int keys = hom[xa], stg = col[xa] + col[xa + 1] + col[xa + 2];
-                int xb = xa + 1;
-                while (xb < nx && xb - xa < kTileWMax && keys + hom[xb] <= p.kt && stg + col[xb + 2] <= p.scap) {
-                    keys += hom[xb];
-                    stg += col[xb + 2];
-                    ++xb;
-                }
-                over = over || stg > p.scap;
-                big = max(big, stg);
+                const int xb = nxt[xa];
+                big = max(big, C[xb + 2] - C[xa]);
                 d.rt_tmp[base + nt] = xa | (xb << 16);
                 ++nt;
                 xa = xb;
             }
             d.row_nt[row] = nt;
-            if (over) atomicOr(&d.st[b].err, 4);
-            atomicMax(d.ntiles + 1, big);
+            if (big > p.scap) atomicOr(&d.st[b].err, 4);  // only a one-cell tile can exceed it
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        wave_sync();
     }
 }
 
 // One block: exclusive scan of the tiles per row (global row order), the tile
-// total, and each box's first tile.
+// total, and each box's first tile.  The rows go through in coalesced passes of
+// kBlock; each pass is a block-wide scan (wavefront sums, then their prefix).
 __global__ __launch_bounds__(kBlock) void k_row_scan(Dev d, Params p) {
     if (!ld_const(d.any)) return;
-    __shared__ int part[kBlock];
-    const int n = p.nrows;
-    const int per = (n + kBlock - 1) / kBlock;
-    const int a = min((int)threadIdx.x * per, n), e = min(a + per, n);
-    int sum = 0;
-    for (int i = a; i < e; ++i) sum += d.row_nt[i];
-    part[threadIdx.x] = sum;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int run = 0;
-        for (int t = 0; t < kBlock; ++t) {
-            const int x = part[t];
-            part[t] = run;
-            run += x;
+    constexpr int NWb = kBlock / kWave;
+    __shared__ int wsum[NWb];
+    const int n = p.nrows, tid = threadIdx.x, l = lane_id(), wv = wave_in_block();
+    int carry = 0;
+    int nt = tid < n ? d.row_nt[tid] : 0, rb = tid < n ? d.row_box[tid] : 0;
+    int rprev = tid >= 1 && tid - 1 < n ? d.row_box[tid - 1] : -1;
+    for (int i0 = 0; i0 < n; i0 += kBlock) {
+        const int i = i0 + tid;
+        // the next pass's values, loaded ahead
+        const int j = i + kBlock;
+        const int nt_n = j < n ? d.row_nt[j] : 0, rb_n = j < n ? d.row_box[j] : 0;
+        const int rprev_n = j - 1 < n ? d.row_box[j - 1] : -1;
+        const int incl = wave_incl_sum(nt);
+        if (l == kWave - 1) wsum[wv] = incl;
+        __syncthreads();
+        int before = carry;
+        for (int w = 0; w < wv; ++w) before += wsum[w];
+        int total = 0;
+        for (int w = 0; w < NWb; ++w) total += wsum[w];
+        if (i < n) {
+            const int t0 = before + incl - nt;
+            d.row_t0[i] = t0;
+            if (i == 0 || rprev != rb) d.box_t0[rb] = t0;  // a box's rows are consecutive
         }
-        d.ntiles[0] = run;
-        d.box_t0[p.nbox] = run;
+        carry += total;
+        __syncthreads();  // wsum is rewritten by the next pass
+        nt = nt_n;
+        rb = rb_n;
+        rprev = rprev_n;
     }
-    __syncthreads();
-    int run = part[threadIdx.x];
-    for (int i = a; i < e; ++i) {
-        const int b = d.row_box[i];
-        if (i == 0 || d.row_box[i - 1] != b) d.box_t0[b] = run;  // a box's rows are consecutive
-        d.row_t0[i] = run;
-        run += d.row_nt[i];
+    if (tid == 0) {
+        d.ntiles[0] = carry;
+        d.box_t0[p.nbox] = carry;
     }
 }
 
@@ -1054,7 +1097,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7, 8))) 
         const int m = ld_const(d.cell_cnt + c);
         if (m == 0) return;
         const int cs0 = ld_const(d.cell_start + c);
-        Pos* __restrict__ q = d.q[ld_const(&st.sq)];
+        Pos* __restrict__ q = d.q[ld_const(&st.sq) ^ 1];  // permuted, made current after the build
         const int cx = local % g.n[0], cy = (local / g.n[0]) % g.n[1], cz = local / (g.n[0] * g.n[1]);
         // stencil cell s = lane s < 27: start, count and image term
         int start = 0, cnt = 0;
@@ -2271,7 +2314,6 @@ void launch_rebuild_chain(const Dev& d, const Params& p, bool with_list, hipStre
     if (p.tile) launch_row_tiles(d, p, s);
     k_scatter<<<gw, kBlock, 0, s>>>(d, p);
     k_rank_permute<<<gw, kBlock, 0, s>>>(d, p);
-    k_flip<<<1, kBlock, 0, s>>>(d, p);
     if (with_list) {
         switch (p.tpk) {
             case 1: launch_list_t<1>(d, p, s); break;
