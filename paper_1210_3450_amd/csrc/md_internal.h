@@ -170,7 +170,7 @@ struct Dev {
     int32_t* row_box;    // box of each global row
     int32_t* row_nt;     // row tiles per row
     int32_t* row_t0;     // first row tile of each row (exclusive scan of row_nt)
-    int32_t* ntiles;     // [0] row tiles in all, [1] unused
+    int32_t* ntiles;     // [0] row tiles in all, [1] blocks of the post-build kernel done (the last resets it)
     int32_t* box_t0;     // [nbox + 1] first row tile of each box, then the total
     int32_t* cell_rt;    // row tile of each cell
     int32_t* rt_tmp;     // per cell: xa | xb << 16 of the row's k-th tile at (row's first cell + k)

@@ -435,31 +435,30 @@ __global__ __launch_bounds__(kBlock) void k_dutc(Dev d, Params p) {
 }
 
 // After a build: the permuted buffers become the current ones, longest list over
-// each box's cell tiles, DUTC bound reset, and the "some box rebuilds" gate cleared.
-// A single block walks every box, so the gate is cleared only after all of them are
-// done.  (Between the permutation and this kernel, a rebuilding box's current
+// each box's cell tiles, DUTC bound reset, and the "some box rebuilds" gate cleared by
+// the last block to finish.  (Between the permutation and this kernel, a rebuilding box's current
 // positions are in buffer sq ^ 1: the list build reads them there.)
 __global__ __launch_bounds__(kBlock) void k_post_build(Dev d, Params p, int with_list) {
-    __shared__ int red[kBlock];
+    __shared__ int red[kBlock / kWave];
+    __shared__ int last;
     if (!*d.any) return;
-    for (int b = 0; b < p.nbox; ++b) {
+    const int l = lane_id(), wv = wave_in_block();
+    for (int b = blockIdx.x; b < p.nbox; b += gridDim.x) {  // one block per box
         BoxState& st = d.st[b];
         if (!st.rebuild) continue;  // uniform over the block
         const BoxGeom& g = d.geom[b];
         int m = 0;
         if (with_list)
             for (int t = threadIdx.x; t < g.ntile; t += kBlock) m = max(m, d.tile_need[g.tile_off + t]);
-        red[threadIdx.x] = m;
+        m = __builtin_amdgcn_readlane(wave_incl_max(m), kWave - 1);
+        if (l == 0) red[wv] = m;
         __syncthreads();
-        for (int o = kBlock / 2; o > 0; o >>= 1) {
-            if (threadIdx.x < o) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + o]);
-            __syncthreads();
-        }
         if (threadIdx.x == 0) {
+            for (int w = 1; w < kBlock / kWave; ++w) m = max(m, red[w]);
             if (with_list) {
                 st.D = 0.0;
                 st.built += 1;
-                st.need = max(st.need, red[0]);
+                st.need = max(st.need, m);
             }
             st.sq ^= 1;
             st.sp ^= 1;
@@ -467,7 +466,15 @@ __global__ __launch_bounds__(kBlock) void k_post_build(Dev d, Params p, int with
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) *d.any = 0;
+    // the last block to finish clears the gate (every block has read it by then)
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) last = atomicAdd(d.ntiles + 1, 1) == (int)gridDim.x - 1;
+    __syncthreads();
+    if (last && threadIdx.x == 0) {
+        d.ntiles[1] = 0;
+        *d.any = 0;
+    }
 }
 
 // ---------------------------------------------------------------- binning
@@ -2322,7 +2329,7 @@ void launch_rebuild_chain(const Dev& d, const Params& p, bool with_list, hipStre
             default: launch_list_t<8>(d, p, s); break;
         }
     }
-    k_post_build<<<1, kBlock, 0, s>>>(d, p, with_list ? 1 : 0);
+    k_post_build<<<p.nbox < 1024 ? p.nbox : 1024, kBlock, 0, s>>>(d, p, with_list ? 1 : 0);
 }
 
 template <int PREC, int TPK>
