@@ -74,17 +74,18 @@ typedef enum {
 #define MD_F_VERIFY_LIST 1u        /* debug: after every force evaluation count pairs within
                                       rc missing from the list (O(n^2) per box) */
 #define MD_F_GRAPH 2u              /* replay md_step chunks as captured HIP graphs */
-#define MD_F_TILE_ON 4u            /* FP32-mixed: row tiles (the default for a largest box of 2^23
-                                      particles or more; threads_per_key 0 or 1):
-                                      each row of cells is cut into runs of cells whose partners (the
-                                      9 neighbouring rows, one cell wider each side) a block stages in
-                                      LDS once; list entries name staged records and the force pass
-                                      reads every partner from LDS.  A context whose cells are too
-                                      crowded for the staging capacity (about 2400 particles around
-                                      one cell) switches to the gather format by itself. */
-#define MD_F_TILE_OFF 8u           /* FP32-mixed: the gather format instead of row tiles (every partner
-                                      read from global memory by cell and rank; the default for
-                                      smaller boxes) */
+#define MD_F_TILE_ON 4u            /* row tiles (threads_per_key 0 or 1; the FP32-mixed default for a
+                                      largest box of 2^23 particles or more): each row of cells is
+                                      cut into runs of cells whose partners (the 9 neighbouring rows,
+                                      one cell wider each side) a block stages in LDS once (fixed-point
+                                      records for FP32-mixed, FP64 positions for FP64); list entries
+                                      name staged records and the force pass reads every partner from
+                                      LDS.  A context whose cells are too crowded for the staging
+                                      capacity (about 2400 particles around one cell) switches to the
+                                      gather format by itself. */
+#define MD_F_TILE_OFF 8u           /* the gather format instead of row tiles (every partner read from
+                                      global memory by cell and rank; the default for FP64 and for
+                                      smaller FP32-mixed boxes) */
 #define MD_F_FAST_RCP 16u          /* FP64 path: 1/r^2 from the hardware reciprocal, with the
                                       correction of Sec. III.C applied to r^-6, r^-8, r^-12 and
                                       r^-14 (r^-2n ~ xt^n ((n + 1) - n xt r^2)) instead of a division */

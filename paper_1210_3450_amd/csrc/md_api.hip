@@ -402,13 +402,11 @@ void params_refresh(md_ctx* c) {
     P.ntile = c->ntile;
     P.precision = p.precision;
     P.half = (p.flags & MD_F_HALF_LIST) ? 1 : 0;
-    // Row tiles (FP32-mixed, full list, one lane per key): the force pass reads every
-    // partner from LDS; the gather format serves the other layouts and boxes whose
-    // cells are too crowded for a tile's staging capacity.
-    P.tile = p.precision == MD_PREC_FP32_MIXED && !P.half && P.tpk == 1 && !(p.flags & MD_F_TILE_OFF) &&
-                     !c->tile_fallback && !c->prefer_gather
-                 ? 1
-                 : 0;
+    // Row tiles (full list, one lane per key): the force pass reads every partner from
+    // LDS; the gather format serves the other layouts, the sizes where it is faster, and
+    // boxes whose cells are too crowded for a tile's staging capacity.
+    P.tile = !P.half && P.tpk == 1 && !(p.flags & MD_F_TILE_OFF) && !c->tile_fallback && !c->prefer_gather ? 1 : 0;
+    P.recb = p.precision == MD_PREC_FP64 ? 24 : 12;  // FP64 x, y, z or three fixed-point ints
     P.kt = kRtBlock;
     P.scap = kStageCap;
     P.nrows = c->nrows;
@@ -809,10 +807,10 @@ md_status create_impl(const md_params* boxes, int32_t nbox, void* stream, md_ctx
     int64_t nmax = 0;
     for (const md_params& bp : c->boxes) nmax = std::max(nmax, bp.n);
     const bool mixed = c->prm.precision == MD_PREC_FP32_MIXED;
-    const bool tiles = mixed && !(c->prm.flags & (MD_F_TILE_OFF | MD_F_HALF_LIST)) &&
-                       ((c->prm.flags & MD_F_TILE_ON) || nmax >= kTileMinN);
+    const bool tiles = !(c->prm.flags & (MD_F_TILE_OFF | MD_F_HALF_LIST)) &&
+                       ((c->prm.flags & MD_F_TILE_ON) || (mixed && nmax >= kTileMinN));
     if (c->prm.threads_per_key == 0 && tiles) tpk = 1;
-    c->prefer_gather = mixed && !tiles;
+    c->prefer_gather = !tiles;
     if (c->prm.flags & MD_F_HALF_LIST) tpk = 1;
     c->P.tpk = tpk;
     params_refresh(c);
@@ -1420,7 +1418,6 @@ md_status md_autotune(md_ctx* c, const char* cache_path) {
         bool tile;
         int pct;  // cell_scale in percent
     };
-    const bool mixed = c->prm.precision == MD_PREC_FP32_MIXED;
     const uint32_t fl = c->prm.flags;
     std::vector<int> pcts;
     if (c->prm.cell_scale > 0.0)
@@ -1429,8 +1426,9 @@ md_status md_autotune(md_ctx* c, const char* cache_path) {
         pcts = {100, 115, 130};
     std::vector<Cand> cands;
     for (int pct : pcts) {
-        if (mixed && !(fl & MD_F_TILE_OFF)) cands.push_back({1, true, pct});
-        if ((fl & MD_F_TILE_ON) && mixed) continue;  // MD_F_TILE_ON has no effect on FP64
+        if (!(fl & MD_F_TILE_OFF) && (c->prm.threads_per_key == 0 || c->prm.threads_per_key == 1))
+            cands.push_back({1, true, pct});
+        if (fl & MD_F_TILE_ON) continue;
         for (int t : {1, 2, 4, 8})
             if (c->prm.threads_per_key == 0 || c->prm.threads_per_key == t) cands.push_back({t, false, pct});
     }

@@ -127,9 +127,10 @@ struct Params {
     int32_t ntile;      // cell tiles over all boxes
     int32_t precision;  // MD_PREC_*
     int32_t record;     // energy reduction appends to the series
-    int32_t tile;       // row-tile list format and forces from LDS-staged tiles (FP32-mixed, one lane per key)
+    int32_t tile;       // row-tile list format and forces from LDS-staged tiles (one lane per key)
     int32_t kt;         // keys per row tile at most (a single cell may hold more)
-    int32_t scap;       // staged partner records per row tile at most (LDS: 16 bytes each)
+    int32_t scap;       // staged partner records per row tile at most (LDS: recb bytes each)
+    int32_t recb;       // bytes per staged record: 12 (FP32-mixed fixed point), 24 (FP64 x, y, z)
     int32_t tgrid;      // blocks of the row-tile force kernel: one resident round (each loops over tiles)
     int32_t clamp;      // Eq. 1 cutoff (f(rc) = 0): FP32-mixed forces clamp 1/r^2 at 1/rc^2 instead of masking
     int32_t nrows;      // rows of cells over all boxes

@@ -337,9 +337,9 @@ __device__ void tile_pieces_of(const Dev& d, const BoxGeom& g, uint32_t cc, int*
     }
 }
 
-// Slot behind a row-tile entry (12 * staged index), given the tile's pieces.
-__device__ int tile_slot(const int* ps0, const int* plen, uint32_t e) {
-    int idx = (int)(e / (uint32_t)sizeof(U3));
+// Slot behind a row-tile entry (recb * staged index), given the tile's pieces.
+__device__ int tile_slot(const int* ps0, const int* plen, uint32_t e, int recb) {
+    int idx = (int)(e / (uint32_t)recb);
     for (int pc = 0; pc < 27; ++pc) {
         if (idx < plen[pc]) return ps0[pc] + idx;
         idx -= plen[pc];
@@ -364,7 +364,7 @@ __global__ __launch_bounds__(kBlock) void k_list_export(Dev d, Params p, const i
             int ps0[27], plen[27];
             tile_pieces_of(d, g, cc, ps0, plen);
             for (int e = 0; e < n; ++e)
-                partners[base + e] = id[tile_slot(ps0, plen, d.list[list_addr(s, e, p.tpk, p.rows)])];
+                partners[base + e] = id[tile_slot(ps0, plen, d.list[list_addr(s, e, p.tpk, p.rows)], p.recb)];
         } else {
             for (int e = 0; e < n; ++e)
                 partners[base + e] = id[entry_slot(d, cc, d.list[list_addr(s, e, p.tpk, p.rows)], g)];
@@ -674,6 +674,18 @@ __device__ __forceinline__ void tile_piece(const Dev& d, const BoxGeom& g, int c
     len = d.cell_start[rowc + x1] + d.cell_cnt[rowc + x1] - s0;
 }
 
+// Periodic image of piece p of a row tile's staged region, per axis in {-1, 0, 1}:
+// -1 where the piece's cells wrapped below 0 (their positions are taken minus L),
+// +1 above n - 1 (plus L).  The same cases as tile_piece's fixed-point terms.
+__device__ __forceinline__ void tile_piece_img(const BoxGeom& g, int cy, int cz, int p, int& rx, int& ry, int& rz) {
+    const int r = (p * 11) >> 5, side = p - 3 * r;
+    const int rzz = (r * 11) >> 5, ryy = r - 3 * rzz;
+    const int y = cy + ryy - 1, z = cz + rzz - 1;
+    rx = side == 0 ? -1 : (side == 2 ? 1 : 0);
+    ry = y < 0 ? -1 : (y >= g.n[1] ? 1 : 0);
+    rz = z < 0 ? -1 : (z >= g.n[2] ? 1 : 0);
+}
+
 // Cuts every row of cells into row tiles, greedily from x = 0: a tile grows by the
 // next cell while its keys stay within kt, its staged region within scap records and
 // its width within kTileWMax cells.  One wavefront per row.  The column sums of the
@@ -974,7 +986,7 @@ __device__ __forceinline__ void list_pass(const Dev& d, const Params& p, const P
             const int base_sc = __shfl(sbase, sc), ek_sc = __shfl(ekey, sc);
             // gather format: stencil cell << 11 | rank; row-tile format: the staged record's
             // LDS byte offset (12-byte records)
-            ent[k] = (uint32_t)(ek_sc + ci) * (TL ? (uint32_t)sizeof(U3) : 1u);
+            ent[k] = (uint32_t)(ek_sc + ci) * (TL ? (uint32_t)p.recb : 1u);
             // 32-bit byte offset from the (scalar) array base: slots stay below 2^27
             const uint32_t boff = (uint32_t)(valid ? base_sc + ci : cs0) * (uint32_t)sizeof(Pos);
             const Pos qj = *reinterpret_cast<const Pos*>(reinterpret_cast<const char*>(q) + boff);
@@ -1961,6 +1973,230 @@ __global__ __launch_bounds__(kRtBlock) void k_force_t(Dev d, Params p) {
     }
 }
 
+// FP64 pair forces from a row tile staged in LDS (row-tile list format, one lane per
+// key): the tiles, pieces and list entries of k_force_t, with FP64 position records
+// (x, y, z; an entry is 24 times the staged index) staged with each piece's periodic
+// image added (x - L where the piece wrapped below 0, x + L above), so a separation is
+// three FP64 subtractions.  For pairs that do not cross a periodic face that is the
+// gather pass's separation bit for bit; across a face the image is added before the
+// subtraction instead of after (one rounding of a different sum).  The pair scalar,
+// the summation order and the integration are the gather pass's (IEEE division, or
+// the hardware reciprocal with the correction of Sec. III.C).
+struct D3 {
+    double x, y, z;
+};
+template <int MODE, bool ENERGY>
+__global__ __launch_bounds__(kRtBlock) void k_force_t64(Dev d, Params p) {
+    constexpr int NW = kRtBlock / kWave;
+    constexpr int U = 8, kPc = 27, kCopy = 4;
+    extern __shared__ D3 stg64[];  // p.scap records of 24 bytes
+    __shared__ double red[3][NW];
+    const int l = lane_id(), wib = wave_in_block();
+    const int ntl = ld_const(d.ntiles);
+    for (int t = xcd_block(blockIdx.x, gridDim.x); t < ntl; t += gridDim.x) {
+        const int4 tr = d.rtile[t];
+        const int b = __builtin_amdgcn_readfirstlane(tr.x);
+        const BoxGeom g = ld_geom(d.geom + b);
+        const int lr = __builtin_amdgcn_readfirstlane(tr.y), xa = __builtin_amdgcn_readfirstlane(tr.z),
+                  xb = __builtin_amdgcn_readfirstlane(tr.w);
+        const int cy = lr % g.n[1], cz = lr / g.n[1];
+        const int sq = ld_const(&d.st[b].sq), sp = ld_const(&d.st[b].sp);
+        int ps0 = 0, plen = 0, rx = 0, ry = 0, rz = 0;
+        if (l < kPc) {
+            int ox, oy, oz;
+            tile_piece(d, g, cy, cz, xa, xb, l, ps0, plen, ox, oy, oz);
+            tile_piece_img(g, cy, cz, l, rx, ry, rz);
+        }
+        const int pincl = wave_incl_sum(plen);
+        const int S = __builtin_amdgcn_readlane(pincl, kPc - 1);
+        const int rowc = g.cell_off + (cz * g.n[1] + cy) * g.n[0];
+        const int k0 = ld_const(d.cell_start + rowc + xa);
+        const int k1 = ld_const(d.cell_start + rowc + xb - 1) + ld_const(d.cell_cnt + rowc + xb - 1);
+        if (S > p.scap) continue;  // uniform over the block; nothing staged yet
+        int kb = k0;
+        int key = kb + (int)threadIdx.x;
+        bool active = key < k1;
+        int ks = active ? key : k0;
+        Pos qi = d.q[sq][ks];
+        double v0x = ld_stream(d.vx[sp] + ks), v0y = ld_stream(d.vy[sp] + ks), v0z = ld_stream(d.vz[sp] + ks);
+        const uint4* __restrict__ l4 = reinterpret_cast<const uint4*>(d.list) + (size_t)(ks >> 6) * p.rows * 8 + (ks & 63);
+        uint4 raw_a = ld_stream(l4);
+        uint4 raw_b = p.rows >= 16 ? ld_stream(l4 + kWave) : make_uint4(0u, 0u, 0u, 0u);
+        {  // staging, as in k_force_t: 64-record chunks dealt round-robin to the wavefronts
+            const int pch = (plen + kWave - 1) >> 6;
+            const int chincl = wave_incl_sum(pch);
+            const int NC = __builtin_amdgcn_readlane(chincl, kPc - 1);
+            const int cs = chincl - pch;
+            const int src = ps0 - kWave * cs, dst = (pincl - plen) - kWave * cs, end = plen + kWave * cs;
+            const Pos* __restrict__ q = d.q[sq];
+            for (int c0 = wib; c0 < NC; c0 += NW * kCopy) {
+                D3 v[kCopy];
+                int at[kCopy];
+#pragma unroll
+                for (int k = 0; k < kCopy; ++k) {
+                    const int c = c0 + NW * k;
+                    at[k] = -1;
+                    if (c < NC) {  // uniform
+                        const int pc = __popcll(__ballot(l < kPc && chincl <= c));
+                        const int i = c * kWave + l;
+                        const double sx = (double)__builtin_amdgcn_readlane(rx, pc) * g.L[0];
+                        const double sy = (double)__builtin_amdgcn_readlane(ry, pc) * g.L[1];
+                        const double sz = (double)__builtin_amdgcn_readlane(rz, pc) * g.L[2];
+                        if (i < __builtin_amdgcn_readlane(end, pc)) {
+                            const Pos x = q[__builtin_amdgcn_readlane(src, pc) + i];
+                            v[k] = D3{x.x + sx, x.y + sy, x.z + sz};
+                            at[k] = __builtin_amdgcn_readlane(dst, pc) + i;
+                        }
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < kCopy; ++k)
+                    if (at[k] >= 0) stg64[at[k]] = v[k];
+            }
+        }
+        __syncthreads();
+        const double rc2 = p.rc2, c2x8 = 8.0 * p.c2;
+        const bool fast = p.fastrcp != 0;  // uniform
+        const char* __restrict__ sb = reinterpret_cast<const char*>(stg64);
+        double e_ke = 0.0, e_pe = 0.0, e_vir = 0.0;
+        for (;;) {  // rounds of kRtBlock keys: a one-cell tile may hold more (uniform)
+            const uint32_t cc = qi.cc;
+            const int nl = active ? qi.cnt : 0;
+            const int nfull = nl >> 3, ntail = nl & 7;
+            double Fx = 0.0, Fy = 0.0, Fz = 0.0, pe = 0.0, vir = 0.0;
+            auto chunk = [&](int c, auto chk_c, int valid) {
+                constexpr bool CHK = decltype(chk_c)::value;
+                const uint4 raw = raw_a;
+                D3 rj[U];
+#pragma unroll
+                for (int k = 0; k < U; ++k) {
+                    const uint32_t w = k < 2 ? raw.x : k < 4 ? raw.y : k < 6 ? raw.z : raw.w;
+                    uint32_t off = (k & 1) ? w >> 16 : w & 0xffffu;
+                    if (CHK && k >= valid) off = 0u;  // padding entries: any record, masked below
+                    rj[k] = *reinterpret_cast<const D3*>(sb + off);
+                }
+                if (!CHK) {
+                    raw_a = raw_b;
+                    if (8 * (c + 2) < nl) raw_b = ld_stream(l4 + (size_t)(c + 2) * kWave);
+                }
+#pragma unroll
+                for (int k = 0; k < U; ++k) {
+                    const double dx = rj[k].x - qi.x;
+                    const double dy = rj[k].y - qi.y;
+                    const double dz = rj[k].z - qi.z;
+                    const double r2 = dx * dx + dy * dy + dz * dz;
+                    const bool in = (!CHK || k < valid) && r2 < rc2;
+                    double f, e = 0.0;
+                    if (fast) {
+                        const double xt = __builtin_amdgcn_rcp(r2);
+                        const double tt = xt * r2;
+                        const double x2 = xt * xt, x3 = x2 * xt, x4 = x2 * x2;
+                        const double r8 = x4 * (5.0 - 4.0 * tt), r14 = x4 * x3 * (8.0 - 7.0 * tt);
+                        f = in ? 24.0 * r8 - 48.0 * r14 + c2x8 : 0.0;
+                        if (ENERGY) e = x3 * x3 * (7.0 - 6.0 * tt) - x3 * (4.0 - 3.0 * tt);
+                    } else {
+                        const double inv = 1.0 / r2;
+                        const double inv3 = inv * inv * inv;
+                        f = in ? (24.0 * inv3 - 48.0 * inv3 * inv3) * inv + c2x8 : 0.0;
+                        if (ENERGY) e = inv3 * inv3 - inv3;
+                    }
+                    Fx += f * dx;
+                    Fy += f * dy;
+                    Fz += f * dz;
+                    if (ENERGY) {
+                        pe += in ? 2.0 * (e + p.c2 * r2 + p.c0) : 0.0;
+                        vir += in ? f * r2 : 0.0;
+                    }
+                }
+            };
+            for (int c = 0; c < nfull; ++c) chunk(c, std::false_type{}, U);
+            if (ntail) chunk(nfull, std::true_type{}, ntail);
+            double ke = 0.0, w2 = 0.0, m2 = 0.0;
+            if (active) {
+                if (MODE == kForceOnly) {
+                    d.fx[key] = Fx;
+                    d.fy[key] = Fy;
+                    d.fz[key] = Fz;
+                    if (ENERGY) ke = 0.5 * p.mass * norm2(v0x, v0y, v0z);
+                } else if (MODE == kForceEnd) {
+                    const double vx = kick(v0x, p.h, Fx);
+                    const double vy = kick(v0y, p.h, Fy);
+                    const double vz = kick(v0z, p.h, Fz);
+                    d.vx[sp][key] = vx;
+                    d.vy[sp][key] = vy;
+                    d.vz[sp][key] = vz;
+                    d.fx[key] = Fx;
+                    d.fy[key] = Fy;
+                    d.fz[key] = Fz;
+                    if (ENERGY) ke = 0.5 * p.mass * norm2(vx, vy, vz);
+                } else {  // kForceMid: close step n, open step n+1, drift
+                    const double vx = kick(kick(v0x, p.h, Fx), p.h, Fx);
+                    const double vy = kick(kick(v0y, p.h, Fy), p.h, Fy);
+                    const double vz = kick(kick(v0z, p.h, Fz), p.h, Fz);
+                    st_stream(d.vx[sp] + key, vx);
+                    st_stream(d.vy[sp] + key, vy);
+                    st_stream(d.vz[sp] + key, vz);
+                    const Pos xn = make_pos(drift(qi.x, p.dt, vx), drift(qi.y, p.dt, vy), drift(qi.z, p.dt, vz), cc,
+                                            qi.cnt);
+                    d.q[sq ^ 1][key] = xn;
+                    w2 = norm2(vx, vy, vz);
+                    if (d.qb) {
+                        const double4 xbq = d.qb[key];
+                        m2 = norm2(xn.x - xbq.x, xn.y - xbq.y, xn.z - xbq.z);
+                    }
+                }
+            }
+            if (MODE == kForceMid) {
+                const double wm = wave_max(w2);
+                if (l == 0) stripe_put(d.vmax_s, b, t * 4 + wib, wm);
+                if (d.qb) {
+                    const double mm = wave_max(m2);
+                    if (l == 0) stripe_put(d.disp_s, b, t * 4 + wib, mm);
+                }
+            }
+            if (ENERGY && active) {
+                e_ke += ke;
+                e_pe += pe;
+                e_vir += vir;
+            }
+            kb += kRtBlock;
+            if (kb >= k1) break;
+            key = kb + (int)threadIdx.x;
+            active = key < k1;
+            ks = active ? key : k0;
+            qi = d.q[sq][ks];
+            v0x = ld_stream(d.vx[sp] + ks);
+            v0y = ld_stream(d.vy[sp] + ks);
+            v0z = ld_stream(d.vz[sp] + ks);
+            l4 = reinterpret_cast<const uint4*>(d.list) + (size_t)(ks >> 6) * p.rows * 8 + (ks & 63);
+            raw_a = ld_stream(l4);
+            raw_b = p.rows >= 16 ? ld_stream(l4 + kWave) : make_uint4(0u, 0u, 0u, 0u);
+        }
+        if (ENERGY) {  // the tile's partials, summed in a fixed order
+            const double ks2 = wave_sum(e_ke), ps = wave_sum(e_pe), vs = wave_sum(e_vir);
+            __syncthreads();
+            if (l == 0) {
+                red[0][wib] = ks2;
+                red[1][wib] = ps;
+                red[2][wib] = vs;
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                double a0 = red[0][0], a1 = red[1][0], a2 = red[2][0];
+                for (int w = 1; w < NW; ++w) {
+                    a0 += red[0][w];
+                    a1 += red[1][w];
+                    a2 += red[2][w];
+                }
+                d.ke_part[t] = a0;
+                d.pe_part[t] = a1;
+                d.vir_part[t] = a2;
+            }
+        }
+        __syncthreads();  // the next tile's staging reuses the LDS
+    }
+}
+
 // Half-list steps: F is accumulated by atomics, so the integrator runs as its own
 // pass after the force pass.  k_zero_f clears F before the force pass.
 __global__ __launch_bounds__(kBlock) void k_zero_f(Dev d, Params p) {
@@ -2221,7 +2457,7 @@ __global__ __launch_bounds__(kBlock) void k_verify(Dev d, Params p) {
                 bool found = false;
                 for (int e = 0; e < n && !found; ++e) {
                     const uint32_t en = d.list[list_addr(s, e, p.tpk, p.rows)];
-                    found = (p.tile ? tile_slot(ps0, plen, en) : entry_slot(d, qi.cc, en, g)) == j;
+                    found = (p.tile ? tile_slot(ps0, plen, en, p.recb) : entry_slot(d, qi.cc, en, g)) == j;
                 }
                 if (!found) ++missed;
             }
@@ -2401,16 +2637,38 @@ static void launch_force_rowtile_c(const Dev& d, const Params& p, int mode, bool
 // row-tile kernels launch that many blocks per CU, and each loops over the tiles.
 int rowtile_blocks_per_cu(const Params& p) {
     int nb = 0;
-    const size_t lds = (size_t)p.scap * sizeof(U3);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_force_t<kForceMid, false, true>, kRtBlock, lds) !=
-            hipSuccess ||
-        nb < 1)
-        nb = 1;
+    hipError_t e;
+    if (p.precision == MD_PREC_FP64)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_force_t64<kForceMid, false>, kRtBlock,
+                                                         (size_t)p.scap * sizeof(D3));
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_force_t<kForceMid, false, true>, kRtBlock,
+                                                         (size_t)p.scap * sizeof(U3));
+    if (e != hipSuccess || nb < 1) nb = 1;
     return nb;
 }
 
+static void launch_force_rowtile64(const Dev& d, const Params& p, int mode, bool energy, hipStream_t s) {
+    const size_t lds = (size_t)p.scap * sizeof(D3);
+    if (mode == kForceOnly) {
+        if (energy)
+            k_force_t64<kForceOnly, true><<<p.tgrid, kRtBlock, lds, s>>>(d, p);
+        else
+            k_force_t64<kForceOnly, false><<<p.tgrid, kRtBlock, lds, s>>>(d, p);
+    } else if (mode == kForceEnd) {
+        if (energy)
+            k_force_t64<kForceEnd, true><<<p.tgrid, kRtBlock, lds, s>>>(d, p);
+        else
+            k_force_t64<kForceEnd, false><<<p.tgrid, kRtBlock, lds, s>>>(d, p);
+    } else {
+        k_force_t64<kForceMid, false><<<p.tgrid, kRtBlock, lds, s>>>(d, p);
+    }
+}
+
 static void launch_force_rowtile(const Dev& d, const Params& p, int mode, bool energy, hipStream_t s) {
-    if (p.clamp)
+    if (p.precision == MD_PREC_FP64)
+        launch_force_rowtile64(d, p, mode, energy, s);
+    else if (p.clamp)
         launch_force_rowtile_c<true>(d, p, mode, energy, s);
     else
         launch_force_rowtile_c<false>(d, p, mode, energy, s);

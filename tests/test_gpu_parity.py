@@ -259,6 +259,46 @@ def test_steps_mixed_tiles_equal_global_gathers():
     assert a[4] == t[4] and a[4] > 0
 
 
+@pytest.mark.parametrize("fast", [False, True], ids=["div", "fastrcp"])
+@pytest.mark.parametrize("name", ["rows26", "dilute", "small"])
+def test_forces_fp64_tiles_match_gathers_and_oracle(name, fast):
+    """The FP64 row-tile pass: the same pair arithmetic as the gather pass, with each
+    staged piece's periodic image added to the positions before the subtraction (one
+    rounding of a different sum for pairs across a face, which the steep potential of
+    close pairs amplifies to ~1e-13): forces agree with the gather pass and with the
+    oracle to the FP64 bar, energies to 1e-13."""
+    b = B()
+    q, L = tile_case(name)
+    v = inputs.maxwell_boltzmann(q.shape[0], 1.0, 1.0, rng(7))
+    F, E = {}, {}
+    for flag in (b.MD_F_TILE_ON, b.MD_F_TILE_OFF):
+        fl = flag | (b.MD_F_FAST_RCP if fast else 0)
+        with make_ctx(q, v, L, precision=0, threads_per_key=1, flags=fl) as c:
+            F[flag] = c.compute_forces().cpu().numpy()
+            E[flag] = c.energy()
+            assert c.stats()["row_tiles"] == (1 if flag == b.MD_F_TILE_ON else 0)
+    Fr, per, A = oracle.forces(q, L, 2.5, 0.3)
+    assert norm_err(F[b.MD_F_TILE_ON], F[b.MD_F_TILE_OFF], A) <= 1e-12
+    assert norm_err(F[b.MD_F_TILE_ON], Fr, A) <= 1e-12
+    assert E[b.MD_F_TILE_ON][1] == pytest.approx(E[b.MD_F_TILE_OFF][1], rel=1e-13)
+    assert E[b.MD_F_TILE_ON][1] == pytest.approx(per, rel=1e-12)
+
+
+def test_steps_fp64_tiles_track_the_oracle():
+    """100 FP64 steps with row tiles (kicks, drift, rebuilds): positions within 1e-9
+    of the oracle's trajectory, as the gather pass."""
+    b = B()
+    q, L = tile_case("rows26")
+    v = inputs.maxwell_boltzmann(q.shape[0], 1.0, 1.0, rng(8))
+    with make_ctx(q, v, L, precision=0, threads_per_key=1, flags=b.MD_F_TILE_ON) as c:
+        c.step(100)
+        pos = c.get_state()[0].cpu().numpy()
+        reb = c.stats()["rebuilds"]
+    r = oracle.run(q, v, L, 100)
+    assert np.abs(_wrapdiff(pos, r.q, L)).max() < 1e-9
+    assert reb == r.rebuilds
+
+
 def test_row_tile_overflow_falls_back_to_gathers():
     """A box whose one-cell row tiles stage more partners than the LDS capacity (a
     jittered 14^3 lattice in 3 x 3 x 3 cells: every cell sees all 2744 particles)
