@@ -55,6 +55,47 @@ def test_small_nve_energy_drift_matches_oracle():
         assert dev[k] < 3.0 * dev["oracle"] + 1e-5
 
 
+def _drift_slope(ke, pe, dt_sample):
+    """Least-squares slope of (E(t) - E(0)) / |E(0)| per unit time."""
+    E = np.asarray(ke) + np.asarray(pe)
+    y = (E - E[0]) / abs(E[0])
+    t = np.arange(len(E)) * dt_sample
+    return float(np.polyfit(t, y, 1)[0])
+
+
+def test_nve_drift_10k_steps_beside_oracle():
+    """The energy-conservation comparison of Sec. III.C (Fig. 3) over 10^4 steps
+    (t = 50 tau) at N = 4000: the FP64 oracle, the GPU FP64 path and the GPU
+    FP32-mixed path each run the same initial state for 10^4 steps; the mixed
+    path's energy deviation and drift slope stay at the level of double
+    precision, and the GPU FP64 series follows the oracle's while the
+    trajectories agree."""
+    b = B()
+    w = inputs.small_nve()
+    steps, every, dt = 10000, 100, 0.005
+    r = oracle.run(w.pos, w.vel, w.box, steps, energy_every=every)
+    dev = {"oracle": _maxdev(r.ke, r.pe)}
+    slope = {"oracle": _drift_slope(r.ke, r.pe, every * dt)}
+    E = {"oracle": r.ke + r.pe}
+    for name, prec in (("fp64", 0), ("fp32_mixed", 1)):
+        with b.Context(b.make_params(w.n, w.box, precision=prec, flags=b.MD_F_GRAPH)) as c:
+            c.set_state(w.pos, w.vel)
+            c.step(steps, every)
+            ke, pe = c.energy_series()
+        assert len(ke) == len(r.ke)
+        dev[name] = _maxdev(ke[:, 0], pe[:, 0])
+        slope[name] = _drift_slope(ke[:, 0], pe[:, 0], every * dt)
+        E[name] = ke[:, 0] + pe[:, 0]
+    print("10^4 steps, max |E(t)-E(0)|/|E(0)|:", dev)
+    print("10^4 steps, drift slope of (E-E0)/|E0| per tau:", slope)
+    # the first sample after 100 steps: GPU FP64 and oracle on the same trajectory
+    np.testing.assert_allclose(E["fp64"][:2], E["oracle"][:2], rtol=1e-9)
+    for k in ("fp64", "fp32_mixed"):
+        assert dev[k] < 5e-3
+        assert dev[k] < 3.0 * dev["oracle"] + 1e-5
+        assert abs(slope[k]) < 3.0 * abs(slope["oracle"]) + 2e-6
+
+
 def test_small_nve_drift_fast_reciprocal():
     """The energy-conservation comparison of Sec. III.C on the GPU: 2000 steps at
     N = 4000 with the hardware reciprocal and the correction keep the energy at
