@@ -208,9 +208,13 @@ md_status md_compute_forces(md_ctx *ctx, double *force);
  * drift, DUTC check (Sec. II.A), list rebuild when needed, forces, half kick.
  * energy_every > 0 records KE and PE every energy_every steps (read back with
  * md_energy_series).  With MD_F_VERIFY_LIST returns MD_ELIST if the verifier
- * found a missed pair.  Synchronizes once at the end of the call to check
- * list overflow and numeric errors (overflowed chunks are replayed with a
- * larger list). */
+ * found a missed pair.  Synchronizes every 200 steps and at the end of the call
+ * to check list overflow and numeric errors.  A list build that overflows (the
+ * list's capacity, or a row tile's staging capacity) stops the kernels of its
+ * step; the library then grows the list (or switches to the gather format) and
+ * goes on from that build, so the run equals one that had room from the start.
+ * If growing the list fails (MD_ENOMEM) the state is left drifted within that
+ * step and the next call rebuilds the list. */
 md_status md_step(md_ctx *ctx, int32_t nsteps, int32_t energy_every);
 
 /* Kinetic and potential energy at the current (synchronized) state, summed

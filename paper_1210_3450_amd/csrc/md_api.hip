@@ -51,8 +51,8 @@ struct md_ctx {
     Params P{};
     Dev D{};
     // device allocations not reachable through D
-    double* bk_pos = nullptr;
-    double* bk_vel = nullptr;
+    double* bk_pos = nullptr;    // caller-order copy of the state while md_autotune re-lays
+    double* bk_vel = nullptr;    // the grid (allocated on its first call)
     double* dscratch = nullptr;  // nbox doubles (scale factors)
     BoxState* st_h = nullptr;    // pinned mirror of the box states
     int64_t list_alloc = 0;      // entries allocated in D.list
@@ -437,6 +437,7 @@ void free_all(md_ctx* c) {
     dfree(D.geom);
     dfree(D.st);
     dfree(D.any);
+    dfree(D.halt);
     dfree(D.wave_box);
     dfree(D.tile_box);
     for (int k = 0; k < 2; ++k) {
@@ -510,6 +511,7 @@ md_status alloc_all(md_ctx* c) {
     A(D.geom, c->nbox);
     A(D.st, c->nbox);
     A(D.any, 1);
+    A(D.halt, 1);
     A(D.wave_box, c->nwave);
     for (int k = 0; k < 2; ++k) {
         A(D.q[k], ns);
@@ -536,12 +538,11 @@ md_status alloc_all(md_ctx* c) {
     A(D.series_pe, (size_t)kMaxSeries * c->nbox);
     A(D.series_vir, (size_t)kMaxSeries * c->nbox);
     A(D.series_th, (size_t)kMaxSeries * c->nbox);
-    A(c->bk_pos, (size_t)c->ntotal * 3);
-    A(c->bk_vel, (size_t)c->ntotal * 3);
     A(c->dscratch, (size_t)c->nbox);
 #undef A
     if ((s = alloc_cells(c)) != MD_OK) return s;
     HIPCHK(c, hipMemsetAsync(D.any, 0, sizeof(int32_t), c->stream));
+    HIPCHK(c, hipMemsetAsync(D.halt, 0, sizeof(int32_t), c->stream));
     HIPCHK(c, hipMemsetAsync(D.ntiles, 0, 2 * sizeof(int32_t), c->stream));
     HIPCHK(c, hipMemsetAsync(D.vmax_s, 0, sizeof(unsigned long long) * c->nbox * kStripes * kStripeStride, c->stream));
     HIPCHK(c, hipMemsetAsync(D.disp_s, 0, sizeof(unsigned long long) * c->nbox * kStripes * kStripeStride, c->stream));
@@ -695,10 +696,15 @@ md_status switch_to_gather(md_ctx* c) {
 }
 
 
+// Lets the kernels of a step run again after an overflow stopped them (a fill
+// kernel, not a memset node, so the call is safe wherever it is enqueued).
+void clear_halt(md_ctx* c) { launch_fill_i32(c->D.halt, 0, 1, c->stream); }
+
 // Full list build for every box, growing the list until it fits.
 md_status build_list(md_ctx* c) {
     md_status s;
     for (int attempt = 0; attempt < 8; ++attempt) {
+        clear_halt(c);
         launch_mark_rebuild(c->D, c->P, c->stream);
         if ((s = enqueue_rebuild(c, true)) != MD_OK) return s;
         LAUNCHCHK(c);
@@ -716,7 +722,8 @@ md_status build_list(md_ctx* c) {
             c->have_F = false;
             return MD_OK;
         }
-        // grow and rebuild (slots are already sorted; the rebuild re-sorts identically)
+        // grow and rebuild (the overflow stopped the chain before the permuted buffers
+        // became current; the rebuild sorts the same slots by cell again)
         if ((s = alloc_list(c, need + need / 4 + 8)) != MD_OK) return s;
         c->regrows += 1;
         for (int b = 0; b < c->nbox; ++b) c->st_h[b].need = 0;
@@ -739,6 +746,7 @@ md_status ensure_list_and_forces(md_ctx* c) {
 
 md_status reset_states_for_new_state(md_ctx* c, bool keep_series) {
     md_status s;
+    clear_halt(c);
     if ((s = sync_states(c)) != MD_OK) return s;
     for (int b = 0; b < c->nbox; ++b) {
         BoxState& st = c->st_h[b];
@@ -928,11 +936,19 @@ md_status md_build_cells(md_ctx* c) {
     md_status s;
     if ((s = check_ctx(c)) != MD_OK) return s;
     if (!c->have_state) return fail(c, MD_ESTATE, "no state: call md_set_state first");
-    launch_mark_rebuild(c->D, c->P, c->stream);
-    if ((s = enqueue_rebuild(c, false)) != MD_OK) return s;
-    LAUNCHCHK(c);
-    if ((s = sync_states(c)) != MD_OK) return s;
-    if ((s = status_from_states(c)) != MD_OK) return s;
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        clear_halt(c);
+        launch_mark_rebuild(c->D, c->P, c->stream);
+        if ((s = enqueue_rebuild(c, false)) != MD_OK) return s;
+        LAUNCHCHK(c);
+        if ((s = sync_states(c)) != MD_OK) return s;
+        if ((s = status_from_states(c)) != MD_OK) return s;
+        if (!tile_overflow(c)) break;
+        // a row tile's staging capacity overflowed and stopped the chain: the
+        // gather format from now on, and the cells again
+        switch_to_gather(c);
+        if ((s = push_states(c)) != MD_OK) return s;
+    }
     c->have_cells = true;
     c->have_list = c->have_F = false;
     return MD_OK;
@@ -972,18 +988,18 @@ md_status md_step(md_ctx* c, int32_t nsteps, int32_t energy_every) {
     bool thermo = false;
     for (int b = 0; b < c->nbox; ++b) thermo = thermo || c->st_h[b].thQ > 0.0;
     int32_t done = 0;
+    // after an overflow: step done + 1 is already opened (kicked, drifted, DUTC checked)
+    bool opened = false;
     while (done < nsteps) {
         const int32_t chunk = std::min(kChunk, nsteps - done);
-        // checkpoint for a replay if the list overflows inside the chunk
-        std::vector<BoxState> before(c->st_h, c->st_h + c->nbox);
-        launch_get_state(c->D, c->P, c->bk_pos, c->bk_vel, c->nwave, c->stream);
+        const int32_t nstep0 = c->st_h[0].nstep;
         for (int32_t k = 1; k <= chunk && thermo; ++k) {
             // Nose-Hoover: every step is kick/drift, forces with the closing kick and the
             // energy partials, then the thermostat half steps (end of this step and start
             // of the next) folded into the next kick; the run ends with the velocities
             // scaled by the closing half step's factor
             const int32_t gk = done + k;
-            if (k == 1) {
+            if (k == 1 && !opened) {
                 launch_ke_partial(c->D, c->P, c->stream);
                 launch_energy_reduce(c->D, c->P, false, 2, false, c->stream);
                 launch_kick_drift(c->D, c->P, c->stream);
@@ -1003,7 +1019,7 @@ md_status md_step(md_ctx* c, int32_t nsteps, int32_t energy_every) {
         }
         for (int32_t k = 1; k <= chunk && !thermo; ++k) {
             const int32_t gk = done + k;
-            if (k == 1) {
+            if (k == 1 && !opened) {
                 launch_kick_drift(c->D, c->P, c->stream);
                 launch_dutc(c->D, c->P, c->stream);
             }
@@ -1028,38 +1044,36 @@ md_status md_step(md_ctx* c, int32_t nsteps, int32_t energy_every) {
         LAUNCHCHK(c);
         if ((s = sync_states(c)) != MD_OK) return s;
         if ((s = status_from_states(c)) != MD_OK) return s;
+        const int32_t need = max_need(c);
+        const bool tover = tile_overflow(c);
+        if (need > c->P.cap || tover) {
+            // A list build overflowed (list capacity, or a row tile's staging capacity)
+            // and every kernel after it returned at once: the state is the one that
+            // build found, in step `open` of this chunk (kicked, drifted, DUTC checked,
+            // list pending).  Grow the list or change its format and go on from there.
+            const int32_t open = (opened ? 1 : 0) + (c->st_h[0].nstep - nstep0);
+            clear_halt(c);
+            if (tover) switch_to_gather(c);
+            if (need > c->P.cap) {
+                if ((s = alloc_list(c, need + need / 4 + 8)) != MD_OK) {
+                    c->have_list = c->have_F = false;  // the state is step `open`, drifted
+                    return s;
+                }
+                c->regrows += 1;
+            }
+            if ((s = push_states(c)) != MD_OK) return s;
+            done += open - 1;
+            c->steps += open - 1;
+            opened = true;
+            continue;
+        }
         if (thermo) {  // k_vscale applied the pending factor: the next kick starts from 1
             for (int b = 0; b < c->nbox; ++b) c->st_h[b].vscale = 1.0;
             if ((s = push_states(c)) != MD_OK) return s;
         }
-        const int32_t need = max_need(c);
-        const bool tover = tile_overflow(c);
-        if (need > c->P.cap || tover) {
-            // overflowed (list capacity, or a row tile's staging capacity): restore the
-            // chunk's starting state, grow or change the list format, rebuild, replay
-            if (tover) switch_to_gather(c);
-            if (need > c->P.cap) {
-                if ((s = alloc_list(c, need + need / 4 + 8)) != MD_OK) return s;
-                c->regrows += 1;
-            }
-            for (int b = 0; b < c->nbox; ++b) {
-                BoxState st = before[b];
-                st.sq = st.sp = 0;
-                st.need = 0;
-                st.rebuild = 0;
-                st.built = c->st_h[b].built;
-                c->st_h[b] = st;
-            }
-            if ((s = push_states(c)) != MD_OK) return s;
-            launch_set_state(c->D, c->P, c->bk_pos, c->bk_vel, c->nwave, c->stream);
-            LAUNCHCHK(c);
-            c->have_list = c->have_F = false;
-            if ((s = ensure_list_and_forces(c)) != MD_OK) return s;
-            if ((s = sync_states(c)) != MD_OK) return s;
-            continue;
-        }
         done += chunk;
         c->steps += chunk;
+        opened = false;
     }
     c->have_F = true;
     if (c->prm.flags & MD_F_VERIFY_LIST)
@@ -1454,6 +1468,8 @@ md_status md_autotune(md_ctx* c, const char* cache_path) {
             }
         }
     }
+    if (!c->bk_pos && (s = dalloc(c, &c->bk_pos, (size_t)c->ntotal * 3)) != MD_OK) return s;
+    if (!c->bk_vel && (s = dalloc(c, &c->bk_vel, (size_t)c->ntotal * 3)) != MD_OK) return s;
     // the state's own rebuild counts are kept; the builds made here are not steps
     if ((s = sync_states(c)) != MD_OK) return s;
     std::vector<int32_t> built(c->nbox);

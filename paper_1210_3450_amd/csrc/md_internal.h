@@ -108,7 +108,7 @@ struct BoxState {
     unsigned long long missed; // verifier: pairs within rc absent from the list
     double ke, pe;             // last reduced energies
     int32_t nseries;           // energy samples recorded
-    int32_t pad;
+    int32_t nstep;             // steps opened (drift done, DUTC check run) since the state was set
     double vir;                // last reduced pair virial sum_{i<j} f r^2
     double xi, eta;            // Nose-Hoover thermostat variable and its time integral
     double vscale;             // velocity factor the next kick applies (thermostat; 1 otherwise)
@@ -145,6 +145,9 @@ struct Dev {
     BoxGeom* geom;
     BoxState* st;
     int32_t* any;        // nonzero while some box has a list build pending this step
+    int32_t* halt;       // nonzero after a list build overflowed (list capacity or a row tile's
+                         // staging capacity): the kernels of a step return at once until the
+                         // host has grown the list or changed its format and cleared it
     int32_t* wave_box;   // box of each 64-slot wavefront
     int32_t* tile_box;   // box of each cell tile
     Pos* q[2];

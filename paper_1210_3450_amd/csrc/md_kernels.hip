@@ -49,6 +49,11 @@ __device__ __forceinline__ int ld_const(const int32_t* p) {
         reinterpret_cast<uintptr_t>(p));
 }
 
+// A list build of this step overflowed (the list's capacity, or a row tile's
+// staging capacity): every kernel of a step returns at once, leaving the state as
+// that build found it, until the host has grown the list or changed its format.
+__device__ __forceinline__ bool halted(const Dev& d) { return ld_const(d.halt) != 0; }
+
 // A box's geometry, read through the scalar cache: no kernel writes it, so the
 // wavefront-uniform reads become scalar loads instead of a chain of vector loads
 // that every store in a loop would force to repeat.
@@ -413,6 +418,7 @@ __device__ double stripe_max(unsigned long long* stripes) {
 // whether the list must be rebuilt (Sec. II.A).  One block per box.
 __global__ __launch_bounds__(kBlock) void k_dutc(Dev d, Params p) {
 #pragma clang fp contract(off)
+    if (halted(d)) return;
     for (int b = blockIdx.x; b < p.nbox; b += gridDim.x) {
         const double vmax2 = stripe_max(d.vmax_s + (size_t)b * kStripes * kStripeStride);
         double m2 = 0.0;
@@ -420,6 +426,7 @@ __global__ __launch_bounds__(kBlock) void k_dutc(Dev d, Params p) {
         if (threadIdx.x == 0) {
             BoxState& st = d.st[b];
             st.sq ^= 1;
+            st.nstep += 1;
             st.D = st.D + p.dt * sqrt(vmax2);
             int rb = 0;
             if (p.policy == MD_REBUILD_DUTC)
@@ -441,7 +448,7 @@ __global__ __launch_bounds__(kBlock) void k_dutc(Dev d, Params p) {
 __global__ __launch_bounds__(kBlock) void k_post_build(Dev d, Params p, int with_list) {
     __shared__ int red[kBlock / kWave];
     __shared__ int last;
-    if (!*d.any) return;
+    if (!*d.any || halted(d)) return;
     const int l = lane_id(), wv = wave_in_block();
     for (int b = blockIdx.x; b < p.nbox; b += gridDim.x) {  // one block per box
         BoxState& st = d.st[b];
@@ -480,7 +487,7 @@ __global__ __launch_bounds__(kBlock) void k_post_build(Dev d, Params p, int with
 // ---------------------------------------------------------------- binning
 
 __global__ __launch_bounds__(kBlock) void k_cell_clear(Dev d, Params p) {
-    if (!ld_const(d.any)) return;  // no box rebuilds this step
+    if (!ld_const(d.any) || halted(d)) return;  // no box rebuilds this step, or a build overflowed
     for (int t = blockIdx.x; t < p.ntile; t += gridDim.x) {
         if (!d.st[d.tile_box[t]].rebuild) continue;
         int4* c = reinterpret_cast<int4*>(d.cell_cnt + (size_t)t * kTile);
@@ -493,7 +500,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_clear(Dev d, Params p) {
 // Slots arrive sorted by cell from the previous build, so a wavefront issues one
 // atomic per run of equal cells and hands out tickets within the run.
 __global__ __launch_bounds__(kBlock) void k_bin(Dev d, Params p) {
-    if (!ld_const(d.any)) return;  // no box rebuilds this step
+    if (!ld_const(d.any) || halted(d)) return;  // no box rebuilds this step, or a build overflowed
     const int l = lane_id();
     for (int w = blockIdx.x * 4 + wave_in_block(); w < p.nwave; w += gridDim.x * 4) {
         const int b = ld_const(d.wave_box + w);
@@ -537,7 +544,7 @@ __global__ __launch_bounds__(kBlock) void k_bin(Dev d, Params p) {
 
 // Tile-local exclusive scan of cell counts; tile totals to tile_sum.
 __global__ __launch_bounds__(kBlock) void k_scan_tile(Dev d, Params p) {
-    if (!ld_const(d.any)) return;  // no box rebuilds this step
+    if (!ld_const(d.any) || halted(d)) return;  // no box rebuilds this step, or a build overflowed
     for (int t = blockIdx.x; t < p.ntile; t += gridDim.x) {
         if (!d.st[d.tile_box[t]].rebuild) continue;  // uniform over the block
         const size_t base = (size_t)t * kTile + threadIdx.x * 4;
@@ -552,7 +559,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_tile(Dev d, Params p) {
 
 // Per box: exclusive scan over its tiles' totals, offset by the box's first slot.
 __global__ __launch_bounds__(kBlock) void k_scan_box(Dev d, Params p) {
-    if (!ld_const(d.any)) return;  // no box rebuilds this step
+    if (!ld_const(d.any) || halted(d)) return;  // no box rebuilds this step, or a build overflowed
     for (int b = blockIdx.x; b < p.nbox; b += gridDim.x) {
         if (!d.st[b].rebuild) continue;
         const BoxGeom& g = d.geom[b];
@@ -569,7 +576,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_box(Dev d, Params p) {
 }
 
 __global__ __launch_bounds__(kBlock) void k_scan_add(Dev d, Params p) {
-    if (!ld_const(d.any)) return;  // no box rebuilds this step
+    if (!ld_const(d.any) || halted(d)) return;  // no box rebuilds this step, or a build overflowed
     for (int t = blockIdx.x; t < p.ntile; t += gridDim.x) {
         if (!d.st[d.tile_box[t]].rebuild) continue;
         const int add = d.tile_pref[t];
@@ -581,7 +588,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_add(Dev d, Params p) {
 }
 
 __global__ __launch_bounds__(kBlock) void k_scatter(Dev d, Params p) {
-    if (!ld_const(d.any)) return;  // no box rebuilds this step
+    if (!ld_const(d.any) || halted(d)) return;  // no box rebuilds this step, or a build overflowed
     const int l = lane_id();
     for (int w = blockIdx.x * 4 + wave_in_block(); w < p.nwave; w += gridDim.x * 4) {
         const int b = ld_const(d.wave_box + w);
@@ -600,7 +607,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(Dev d, Params p) {
 // cell's members is its new slot, and its state is copied there (position record
 // with the new cell, fixed-point record, velocities, caller id).
 __global__ __launch_bounds__(kBlock) void k_rank_permute(Dev d, Params p) {
-    if (!ld_const(d.any)) return;  // no box rebuilds this step
+    if (!ld_const(d.any) || halted(d)) return;  // no box rebuilds this step, or a build overflowed
     const int l = lane_id();
     for (int w = xcd_block(blockIdx.x, gridDim.x) * 4 + wave_in_block(); w < p.nwave; w += gridDim.x * 4) {
         const int b = ld_const(d.wave_box + w);
@@ -696,7 +703,7 @@ __device__ __forceinline__ void tile_piece_img(const BoxGeom& g, int cy, int cz,
 // region exceeds scap sets error bit 2 of its box (the context then falls back to the
 // gather format).
 __global__ __launch_bounds__(kBlock) void k_row_tiles(Dev d, Params p) {
-    if (!ld_const(d.any)) return;  // no box rebuilds this step
+    if (!ld_const(d.any) || halted(d)) return;  // no box rebuilds this step, or a build overflowed
     constexpr int NWb = kBlock / kWave;
     __shared__ int col_all[NWb][kMaxCellsPerAxis + 3];  // C[k]: staged counts of unwrapped x < k - 1
     __shared__ int hom_all[NWb][kMaxCellsPerAxis + 1];  // H[k]: keys of cells x < k
@@ -782,7 +789,10 @@ __global__ __launch_bounds__(kBlock) void k_row_tiles(Dev d, Params p) {
                 xa = xb;
             }
             d.row_nt[row] = nt;
-            if (big > p.scap) atomicOr(&d.st[b].err, 4);  // only a one-cell tile can exceed it
+            if (big > p.scap) {  // only a one-cell tile can exceed it; the step stops here
+                atomicOr(&d.st[b].err, 4);
+                atomicOr(d.halt, 1);
+            }
         }
         wave_sync();
     }
@@ -792,7 +802,7 @@ __global__ __launch_bounds__(kBlock) void k_row_tiles(Dev d, Params p) {
 // total, and each box's first tile.  The rows go through in coalesced passes of
 // kBlock; each pass is a block-wide scan (wavefront sums, then their prefix).
 __global__ __launch_bounds__(kBlock) void k_row_scan(Dev d, Params p) {
-    if (!ld_const(d.any)) return;
+    if (!ld_const(d.any) || halted(d)) return;
     constexpr int NWb = kBlock / kWave;
     __shared__ int wsum[NWb];
     const int n = p.nrows, tid = threadIdx.x, l = lane_id(), wv = wave_in_block();
@@ -832,7 +842,7 @@ __global__ __launch_bounds__(kBlock) void k_row_scan(Dev d, Params p) {
 // Row tiles into their global slots, and the tile of every cell.  One wavefront
 // per row, one lane per tile.
 __global__ __launch_bounds__(kBlock) void k_row_write(Dev d, Params p) {
-    if (!ld_const(d.any)) return;
+    if (!ld_const(d.any) || halted(d)) return;
     const int l = lane_id();
     for (int row = blockIdx.x * 4 + wave_in_block(); row < p.nrows; row += gridDim.x * 4) {
         const int b = ld_const(d.row_box + row);
@@ -852,7 +862,7 @@ __global__ __launch_bounds__(kBlock) void k_row_write(Dev d, Params p) {
 // slot, so that the list build turns a stencil cell's first slot into its staged
 // index with one addition.  One wavefront per tile, lane p per piece.
 __global__ __launch_bounds__(kBlock) void k_row_delta(Dev d, Params p) {
-    if (!ld_const(d.any)) return;
+    if (!ld_const(d.any) || halted(d)) return;
     const int l = lane_id();
     const int ntl = ld_const(d.ntiles);
     for (int t = blockIdx.x * 4 + wave_in_block(); t < ntl; t += gridDim.x * 4) {
@@ -1093,7 +1103,7 @@ __device__ __forceinline__ void list_pass(const Dev& d, const Params& p, const P
 // TL: the row-tile entry format (FP32-mixed, full list); otherwise the gather format.
 template <int TPK, bool HALF, bool TL>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7, 8))) void k_list(Dev d, Params p) {
-    if (!ld_const(d.any)) return;  // no box rebuilds this step
+    if (!ld_const(d.any) || halted(d)) return;  // no box rebuilds this step, or a build overflowed
     __shared__ __align__(16) uint16_t stage_all[kBlock / kWave][kStage];
     __shared__ __align__(16) uint8_t mark_all[kBlock / kWave][kMarkBytes];
     const int l = lane_id();
@@ -1214,7 +1224,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7, 8))) 
             }
             need = max(need, __builtin_amdgcn_readlane(wave_incl_max(l < mb ? n_own : 0), 63));
         }
-        if (l == 0) atomicMax(&d.tile_need[t], need);
+        if (l == 0) {
+            atomicMax(&d.tile_need[t], need);
+            if (need > cap) {  // entries were dropped: the step stops here (see halted)
+                atomicMax(&d.st[b].need, need);
+                atomicOr(d.halt, 1);
+            }
+        }
     };
     {
         for (int c = xcd_block(blockIdx.x, gridDim.x) * 4 + wv; c < ncells; c += gridDim.x * 4) {
@@ -1391,6 +1407,7 @@ __device__ __forceinline__ uint32_t force_rec(const Dev& d, uint32_t cc, int s, 
 // F must be zero before the pass.
 template <int PREC, int MODE, int TPK, bool ENERGY, bool HALF = false>
 __global__ __launch_bounds__(kBlock) void k_force(Dev d, Params p) {
+    if (halted(d)) return;
     static_assert(!HALF || (MODE == kForceOnly && TPK == 1), "half lists: forces only, one lane per key");
     constexpr int K = kWave / TPK;
     constexpr int U = 8;  // entries per iteration (one 16-byte chunk)
@@ -1751,6 +1768,7 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Params p) {
 // compare and a select); f(rc) rounds to a few 1e-9 in FP32.
 template <int MODE, bool ENERGY, bool CLAMP>
 __global__ __launch_bounds__(kRtBlock) void k_force_t(Dev d, Params p) {
+    if (halted(d)) return;
     constexpr int NW = kRtBlock / kWave;  // wavefronts per block
     constexpr int U = 8;       // entries per 16-byte list chunk
     constexpr int kPc = 27;    // pieces of a staged region
@@ -1987,6 +2005,7 @@ struct D3 {
 };
 template <int MODE, bool ENERGY>
 __global__ __launch_bounds__(kRtBlock) void k_force_t64(Dev d, Params p) {
+    if (halted(d)) return;
     constexpr int NW = kRtBlock / kWave;
     constexpr int U = 8, kPc = 27, kCopy = 4;
     extern __shared__ D3 stg64[];  // p.scap records of 24 bytes
@@ -2200,6 +2219,7 @@ __global__ __launch_bounds__(kRtBlock) void k_force_t64(Dev d, Params p) {
 // Half-list steps: F is accumulated by atomics, so the integrator runs as its own
 // pass after the force pass.  k_zero_f clears F before the force pass.
 __global__ __launch_bounds__(kBlock) void k_zero_f(Dev d, Params p) {
+    if (halted(d)) return;
     const int n = p.nwave * kWave;
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
         d.fx[i] = 0.0;
@@ -2212,6 +2232,7 @@ __global__ __launch_bounds__(kBlock) void k_zero_f(Dev d, Params p) {
 // of the kicked velocities (one lane per key, so list waves are slot waves).
 template <bool ENERGY>
 __global__ __launch_bounds__(kBlock) void k_kick_close(Dev d, Params p) {
+    if (halted(d)) return;
     const int l = lane_id();
     for (int w = blockIdx.x * 4 + wave_in_block(); w < p.nwave; w += gridDim.x * 4) {
         const int b = ld_const(d.wave_box + w);
@@ -2240,6 +2261,7 @@ __global__ __launch_bounds__(kBlock) void k_kick_close(Dev d, Params p) {
 // first, with the same forces, as the fused full-list pass does.
 template <bool CLOSE>
 __global__ __launch_bounds__(kBlock) void k_kick_drift(Dev d, Params p) {
+    if (halted(d)) return;
     const int l = lane_id();
     for (int w = blockIdx.x * 4 + wave_in_block(); w < p.nwave; w += gridDim.x * 4) {
         const int b = ld_const(d.wave_box + w);
@@ -2321,6 +2343,7 @@ __device__ __forceinline__ void part_range(const Dev& d, const Params& p, const 
 }
 
 __global__ __launch_bounds__(kBlock) void k_energy_segments(Dev d, Params p, int tl) {
+    if (halted(d)) return;
     const int b = blockIdx.y, j = blockIdx.x;
     const BoxGeom& g = d.geom[b];
     int w0, w1;
@@ -2343,6 +2366,7 @@ __global__ __launch_bounds__(kBlock) void k_energy_segments(Dev d, Params p, int
 }
 
 __global__ __launch_bounds__(kBlock) void k_energy_reduce(Dev d, Params p, int record, int thermo, int tl) {
+    if (halted(d)) return;
     for (int b = blockIdx.x; b < p.nbox; b += gridDim.x) {
         const BoxGeom& g = d.geom[b];
         int w0, w1;
@@ -2398,6 +2422,7 @@ __global__ __launch_bounds__(kBlock) void k_energy_reduce(Dev d, Params p, int r
 // KE partials of the current velocities, in the per-list-wave layout the
 // reduction reads (a slot wave's sum in its first list wave, zeros in the others).
 __global__ __launch_bounds__(kBlock) void k_ke_partial(Dev d, Params p) {
+    if (halted(d)) return;
     const int l = lane_id();
     for (int w = blockIdx.x * 4 + wave_in_block(); w < p.nwave; w += gridDim.x * 4) {
         const int b = ld_const(d.wave_box + w);
@@ -2416,6 +2441,7 @@ __global__ __launch_bounds__(kBlock) void k_ke_partial(Dev d, Params p) {
 
 // Apply the pending thermostat factor to the velocities (end of a run of steps).
 __global__ __launch_bounds__(kBlock) void k_vscale(Dev d, Params p) {
+    if (halted(d)) return;
     const int l = lane_id();
     for (int w = blockIdx.x * 4 + wave_in_block(); w < p.nwave; w += gridDim.x * 4) {
         const int b = ld_const(d.wave_box + w);
@@ -2432,6 +2458,7 @@ __global__ __launch_bounds__(kBlock) void k_vscale(Dev d, Params p) {
 // Debug verifier: pairs within rc (minimum image, current positions) that the
 // key's list lacks.  O(n^2) per box.
 __global__ __launch_bounds__(kBlock) void k_verify(Dev d, Params p) {
+    if (halted(d)) return;
     const int l = lane_id();
     for (int w = blockIdx.x * 4 + wave_in_block(); w < p.nwave; w += gridDim.x * 4) {
         const int b = ld_const(d.wave_box + w);

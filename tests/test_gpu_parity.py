@@ -334,6 +334,18 @@ def test_row_tile_overflow_falls_back_to_gathers():
         np.testing.assert_array_equal(sets[flag][1], plr)
     Fr, _, A = oracle.forces(q, L, 2.5, 0.3)
     assert norm_err(F[on], Fr, A) <= 1e-5
+    # the same overflow met by a cells-only build: it switches formats and bins again
+    with make_ctx(q, v, L, precision=1, flags=on, threads_per_key=1) as c:
+        c.build_cells()
+        cells, nc = c.get_cells()
+        pos, _ = c.get_state()
+        assert c.stats()["row_tiles"] == 0
+        F2 = c.compute_forces().cpu().numpy()
+    qw, cref, ncref = oracle_state(q, L)
+    assert tuple(ncref) == nc
+    np.testing.assert_array_equal(cells.cpu().numpy(), cref)
+    np.testing.assert_array_equal(pos.cpu().numpy(), qw)
+    np.testing.assert_array_equal(F2, F[off])
 
 
 @pytest.mark.parametrize("name", CASES)
@@ -572,6 +584,41 @@ def test_list_overflow_regrows_at_build_and_during_steps():
         st = c.stats()
     assert st["list_regrows"] >= 1
     assert np.abs(_wrapdiff(pos.cpu().numpy(), r.q, 10.0)).max() < 1e-9
+
+
+@pytest.mark.parametrize("mode", ["fp64", "fp64-graphs", "fp64-thermostat", "mixed-rowtiles"])
+def test_overflow_during_steps_resumes_at_that_build(mode):
+    """A list that overflows at a build during stepping stops the step's kernels
+    there; the library grows the list and goes on from that build, so the run
+    equals one with room from the start bit for bit: positions, velocities and the
+    energy series (with captured graphs, under the thermostat, with row tiles)."""
+    b = B()
+    q0, v0 = inputs.fcc_positions(5, 2.0), inputs.maxwell_boltzmann(500, 3.0, 1.0, rng(11))
+    kw = dict(threads_per_key=1)
+    if mode == "fp64-graphs":
+        kw["flags"] = b.MD_F_GRAPH
+    if mode == "mixed-rowtiles":
+        kw.update(precision=1, flags=b.MD_F_TILE_ON)
+    out = {}
+    for cap in (48, 256):  # the lattice's lists hold 42 entries; heating makes them longer
+        with make_ctx(q0, v0, 10.0, list_cap=cap, **kw) as c:
+            if mode == "fp64-thermostat":
+                c.set_thermostat(2.0, 0.5)
+            c.step(70, 10)
+            c.step(50, 10)  # a second call: the overflow handling left nothing pending
+            pos, vel = c.get_state()
+            ke, pe = c.energy_series()
+            out[cap] = (pos.cpu().numpy(), vel.cpu().numpy(), ke, pe, c.stats())
+    st48, st256 = out[48][4], out[256][4]
+    assert st48["list_regrows"] >= 1 and st256["list_regrows"] == 0
+    assert st48["list_cap"] > 48
+    if mode == "mixed-rowtiles":
+        assert st48["row_tiles"] == 1 and st256["row_tiles"] == 1
+    assert st48["steps"] == st256["steps"] == 120
+    assert st48["rebuilds"] == st256["rebuilds"]
+    assert len(out[48][2]) == 12
+    for i in range(4):
+        np.testing.assert_array_equal(out[48][i], out[256][i])
 
 
 def test_rescale_box_and_velocity_scaling():
