@@ -377,6 +377,24 @@ md_status alloc_list(md_ctx* c, int32_t cap) {
     return MD_OK;
 }
 
+// A larger list during stepping: the entries move to the new layout, so the boxes
+// that do not rebuild at the step the overflow stopped keep their lists.
+md_status grow_list_keeping(md_ctx* c, int32_t cap) {
+    uint16_t* old = c->D.list;
+    const int32_t old_rows = c->P.rows;
+    c->D.list = nullptr;
+    md_status s = alloc_list(c, cap);  // frees nothing now: the old buffer is held here
+    if (s != MD_OK) {
+        c->D.list = old;
+        return s;
+    }
+    launch_list_relayout(c->D, c->P, old, old_rows, c->stream);
+    LAUNCHCHK(c);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    dfree(old);
+    return MD_OK;
+}
+
 void params_refresh(md_ctx* c) {
     Params& P = c->P;
     const md_params& p = c->prm;
@@ -1053,15 +1071,20 @@ md_status md_step(md_ctx* c, int32_t nsteps, int32_t energy_every) {
             // list pending).  Grow the list or change its format and go on from there.
             const int32_t open = (opened ? 1 : 0) + (c->st_h[0].nstep - nstep0);
             clear_halt(c);
-            if (tover) switch_to_gather(c);
             if (need > c->P.cap) {
-                if ((s = alloc_list(c, need + need / 4 + 8)) != MD_OK) {
+                if ((s = grow_list_keeping(c, need + need / 4 + 8)) != MD_OK) {
                     c->have_list = c->have_F = false;  // the state is step `open`, drifted
                     return s;
                 }
                 c->regrows += 1;
             }
+            if (tover) {
+                // the gather format reads no row-tile entries: every box builds again
+                switch_to_gather(c);
+                for (int b = 0; b < c->nbox; ++b) c->st_h[b].rebuild = 1;
+            }
             if ((s = push_states(c)) != MD_OK) return s;
+            if (tover) launch_mark_rebuild(c->D, c->P, c->stream);
             done += open - 1;
             c->steps += open - 1;
             opened = true;

@@ -292,6 +292,7 @@ void launch_vscale(const Dev& d, const Params& p, hipStream_t s);
 void launch_verify(const Dev& d, const Params& p, hipStream_t s);
 void launch_scale(const Dev& d, const Params& p, const double* alpha_q, const double* scale_v,
                   hipStream_t s);
+void launch_list_relayout(const Dev& d, const Params& p, const uint16_t* old, int32_t old_rows, hipStream_t s);
 void launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 
 }  // namespace mdg

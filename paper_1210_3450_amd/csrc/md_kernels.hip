@@ -1761,8 +1761,9 @@ __global__ __launch_bounds__(kBlock) void k_force(Dev d, Params p) {
 // arithmetic after that, and the summation order, are those of the gather kernel,
 // so both give the same forces bit for bit.  The integration (kicks, drift,
 // fixed-point re-encoding, DUTC maximum) follows in the same pass; energy partials
-// are summed per tile in a fixed order.  A tile whose region exceeds scap (the
-// host then falls back to the gather format and replays) is skipped.
+// are summed per tile in a fixed order.  A tile whose region exceeds scap is
+// skipped (its build has stopped the step; the host switches to the gather format
+// and goes on from that build).
 // CLAMP (the Eq. 1 cutoff, whose f(rc) is 0): a list entry beyond rc is evaluated at
 // rc instead of being masked, 1/r^2 = max(1/r^2, 1/rc^2) (one instruction for a
 // compare and a select); f(rc) rounds to a few 1e-9 in FP32.
@@ -2519,6 +2520,20 @@ __global__ __launch_bounds__(kBlock) void k_scale(Dev d, Params p, const double*
     }
 }
 
+// A larger list buffer: every slot's entries moved from the old layout (old_rows
+// chunks of 8 per list lane) to the current one (p.rows), so the boxes that do not
+// rebuild at the step an overflow stopped keep their lists.  One thread per slot;
+// entry e < min(cnt, old capacity) exists in both layouts.
+__global__ __launch_bounds__(kBlock) void k_list_relayout(Dev d, Params p, const uint16_t* __restrict__ old,
+                                                          int old_rows) {
+    const int nslot = p.nwave * kWave;
+    const int old_cap = old_rows * p.tpk;
+    for (int s = blockIdx.x * kBlock + threadIdx.x; s < nslot; s += gridDim.x * kBlock) {
+        const int n = min(max(d.cnt[s], 0), old_cap);
+        for (int e = 0; e < n; ++e) d.list[list_addr(s, e, p.tpk, p.rows)] = old[list_addr(s, e, p.tpk, old_rows)];
+    }
+}
+
 __global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = v;
@@ -2739,6 +2754,9 @@ void launch_verify(const Dev& d, const Params& p, hipStream_t s) {
 }
 void launch_scale(const Dev& d, const Params& p, const double* alpha_q, const double* scale_v, hipStream_t s) {
     k_scale<<<grid_for_waves(p.nwave), kBlock, 0, s>>>(d, p, alpha_q, scale_v);
+}
+void launch_list_relayout(const Dev& d, const Params& p, const uint16_t* old, int32_t old_rows, hipStream_t s) {
+    k_list_relayout<<<grid_for_waves(p.nwave), kBlock, 0, s>>>(d, p, old, old_rows);
 }
 void launch_fill_i32(int32_t* ptr, int32_t v, int64_t n, hipStream_t s) {
     int64_t g = (n + kBlock - 1) / kBlock;

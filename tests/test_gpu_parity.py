@@ -698,6 +698,41 @@ def test_batch_trajectory_matches_per_box_runs():
     assert st["rebuilds"] == reb
 
 
+@pytest.mark.parametrize("mode", ["fp64", "mixed-rowtiles"])
+def test_batch_overflow_during_steps_resumes_at_that_build(mode):
+    """An ensemble whose lists outgrow their capacity during stepping (every box
+    stops at that build, whichever box overflowed; the boxes that do not rebuild
+    then keep their lists in the larger layout) equals the same ensemble with room
+    from the start, bit for bit, box by box."""
+    b = B()
+    q0 = inputs.fcc_positions(5, 2.0)
+    vs = [inputs.maxwell_boltzmann(500, T, 1.0, rng(30 + k)) for k, T in enumerate((3.0, 1.0, 2.0))]
+    kw = dict(threads_per_key=1)
+    if mode == "mixed-rowtiles":
+        kw.update(precision=1, flags=b.MD_F_TILE_ON)
+    out = {}
+    for cap in (48, 256):
+        params = [b.make_params(500, 10.0, list_cap=cap, **kw) for _ in vs]
+        with b.Context(params) as c:
+            c.set_state(np.concatenate([q0] * len(vs)), np.concatenate(vs))
+            c.step(120, 10)
+            pos, vel = c.get_state()
+            ke, pe = c.energy_series()
+            out[cap] = (pos.cpu().numpy(), vel.cpu().numpy(), ke, pe, c.stats())
+    assert out[48][4]["list_regrows"] >= 1 and out[256][4]["list_regrows"] == 0
+    assert out[48][4]["rebuilds"] == out[256][4]["rebuilds"]
+    if mode == "mixed-rowtiles":
+        assert out[48][4]["row_tiles"] == 1
+    for i in range(4):
+        np.testing.assert_array_equal(out[48][i], out[256][i])
+    # and each box against its own oracle run (FP64)
+    if mode == "fp64":
+        pos = out[48][0]
+        for k, v in enumerate(vs):
+            r = oracle.run(q0, v, 10.0, 120)
+            assert np.abs(_wrapdiff(pos[500 * k:500 * (k + 1)], r.q, 10.0)).max() < 1e-9
+
+
 # ------------------------------------------------------------------ pressure and thermostat
 
 @pytest.mark.parametrize("name", ["fcc4000", "jitter_ragged", "clustered"])
