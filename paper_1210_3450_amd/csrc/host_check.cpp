@@ -279,6 +279,30 @@ void gpu_checks() {
             CHECK(ke[0] == ke[1] && ke[1] == ke[2] && pe[0] == pe[1] && pe[1] == pe[2]);
             OK(md_destroy(c));
         }
+        // the same ensemble with a small list capacity and one box three times as
+        // fast: its lists outgrow the capacity during stepping, the step stops at
+        // that build, and the other boxes' lists move to the larger layout
+        for (size_t i = 0; i < v.size(); ++i) v3[i] *= 3.0;
+        (void)hipMemcpy(dv3, v3.data(), v3.size() * sizeof(double), hipMemcpyHostToDevice);
+        for (auto& p : b3) {
+            p.precision = MD_PREC_FP64;
+            p.flags = 0;
+            p.list_cap = 48;
+            p.threads_per_key = 1;
+        }
+        c = nullptr;
+        OK(md_batch_create(b3, 3, stream, &c));
+        if (c) {
+            OK(md_set_state(c, dq3, dv3));
+            OK(md_step(c, 60, 20));
+            md_stats st;
+            OK(md_get_stats(c, &st));
+            CHECK(st.list_regrows >= 1 && st.list_cap > 48 && st.steps == 60);
+            double ke[3], pe[3];
+            OK(md_batch_energy(c, ke, pe));
+            CHECK(std::isfinite(ke[0]) && std::isfinite(pe[0]) && pe[1] == pe[2]);
+            OK(md_destroy(c));
+        }
         (void)hipStreamDestroy(stream);
         (void)hipFree(dq3);
         (void)hipFree(dv3);
