@@ -294,6 +294,12 @@ def test_steps_fp64_tiles_track_the_oracle():
         c.step(100)
         pos = c.get_state()[0].cpu().numpy()
         reb = c.stats()["rebuilds"]
+        assert c.stats()["row_tiles"] == 1
+        c.build_neighbors()
+        kp, pl = c.get_neighbors()
+    kpr, plr = oracle.neighbors(pos, L, 2.8)  # the sets the row-tile entries name
+    np.testing.assert_array_equal(kp.cpu().numpy(), kpr)
+    np.testing.assert_array_equal(pl.cpu().numpy(), plr)
     r = oracle.run(q, v, L, 100)
     assert np.abs(_wrapdiff(pos, r.q, L)).max() < 1e-9
     assert reb == r.rebuilds
