@@ -171,3 +171,46 @@ def test_fcc32m_sampled_parity_in_bench_configuration(name, precision, flags, to
             np.testing.assert_array_equal(s_, r)
     Fr, A, _ = oracle.forces_sample(qw, w.box, 2.5, ids)
     assert (np.linalg.norm(F - Fr, axis=1) / A).max() <= tol
+
+
+@pytest.mark.parametrize("name,precision,tol", [("fp32_mixed", 1, 1e-5), ("fp64", 0, 1e-12)])
+def test_fcc32m_force_error_at_steps_0_and_500(name, precision, tol):
+    """The 32M benchmark box in its default layout: sampled forces against the
+    oracle on the lattice (step 0) and on the path's own state after 500 steps
+    (about 100 rebuilds at one every 5 steps), where the 2000 sampled neighbour sets
+    are bit-exact too."""
+    b = B()
+    w = inputs.large_32m()
+    rng = np.random.Generator(np.random.PCG64(78))
+    ids = np.sort(rng.choice(w.n, 2000, replace=False))
+    errs = {}
+    with b.Context(b.make_params(w.n, w.box, precision=precision)) as c:
+        c.set_state(w.pos, w.vel)
+        for k in (0, 500):
+            if k:
+                c.step(k)
+            q, _ = c.get_state()
+            if k:
+                c.build_neighbors()  # the sets at these positions
+            F = c.compute_forces()
+            F = F[torch.as_tensor(ids, device=F.device)].cpu().numpy()
+            sets = None
+            if k:
+                kp, pl = c.get_neighbors()
+                idt = torch.as_tensor(ids, device=kp.device)
+                starts, ends = kp[idt].cpu().numpy(), kp[idt + 1].cpu().numpy()
+                sets = [pl[s:e].cpu().numpy() for s, e in zip(starts, ends)]
+                del kp, pl
+            q = q.cpu().numpy()
+            Fr, A, _ = oracle.forces_sample(q, w.box, 2.5, ids)
+            errs[k] = float((np.linalg.norm(F - Fr, axis=1) / A).max())
+            if sets is not None:
+                ref = oracle.neighbors_sample(q, w.box, 2.8, ids)
+                for s_, r in zip(sets, ref):
+                    np.testing.assert_array_equal(s_, r)
+            del q
+        st = c.stats()
+    print("%s: max normalised force error at step 0 %.3e, at step 500 %.3e; %d builds" %
+          (name, errs[0], errs[500], st["rebuilds"]))
+    assert st["rebuilds"] >= 90
+    assert errs[0] <= tol and errs[500] <= tol
