@@ -27,8 +27,10 @@
  *   - The caller owns every pointer it passes.  The library copies what it needs
  *     on the context's stream and keeps no caller pointer after returning.
  *   - The context owns all internal device memory; it is allocated in
- *     md_create / md_batch_create and only grows inside a list rebuild whose
- *     capacity overflowed.  No allocation happens per step otherwise.
+ *     md_create / md_batch_create.  Afterwards only a list build whose capacity
+ *     overflowed grows the list, and md_autotune re-allocates the cell and list
+ *     arrays for the layout it picks (plus a caller-order copy of the state on
+ *     its first call).  No allocation happens per step otherwise.
  *   - Calls are asynchronous on the context stream unless marked
  *     "synchronizing".  A context is not thread-safe; distinct contexts are
  *     independent.
