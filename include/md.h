@@ -28,9 +28,10 @@
  *     on the context's stream and keeps no caller pointer after returning.
  *   - The context owns all internal device memory; it is allocated in
  *     md_create / md_batch_create.  Afterwards only a list build whose capacity
- *     overflowed grows the list, and md_autotune re-allocates the cell and list
- *     arrays for the layout it picks (plus a caller-order copy of the state on
- *     its first call).  No allocation happens per step otherwise.
+ *     overflowed grows the list, md_rescale_box re-allocates the cell arrays
+ *     when the number of cells changes, and md_autotune re-allocates the cell
+ *     and list arrays for the layout it picks (plus a caller-order copy of the
+ *     state on its first call).  No allocation happens per step otherwise.
  *   - Calls are asynchronous on the context stream unless marked
  *     "synchronizing".  A context is not thread-safe; distinct contexts are
  *     independent.
