@@ -243,6 +243,13 @@ void layout(md_ctx* c) {
         g.lam2inv = (float)(g.ucs * g.ucs);
         g.rc2u = (float)(p.rc * p.rc * g.ucs * g.ucs);
         g.ncell = g.n[0] * g.n[1] * g.n[2];
+        const int64_t divs[3] = {g.n[0], g.n[1], (int64_t)g.n[0] * g.n[1]};
+        for (int k = 0; k < 3; ++k) {
+            int l = 0;
+            while (((int64_t)1 << l) < divs[k]) ++l;  // n >= 3: l >= 2
+            g.dmul[k] = (uint32_t)((((uint64_t)1) << (30 + l)) / (uint64_t)divs[k] + 1);
+            g.dshr[k] = l - 2;
+        }
         g.ntile = (g.ncell + kTile - 1) / kTile;
         g.tile_off = tile;
         g.cell_off = tile * kTile;

@@ -94,6 +94,12 @@ struct BoxGeom {
     int32_t nslot;
     int32_t id_off;    // first caller index of this box
     int32_t row_off;   // first global row of cells (row = cz * ny + cy within the box)
+    // division by d = n[0], n[1], n[0] * n[1] (k = 0, 1, 2) for 0 <= x < 2^30 as
+    // (x * dmul[k]) >> (32 + dshr[k]), with dmul = floor(2^(30 + l) / d) + 1 and
+    // dshr = l - 2, l = ceil(log2 d): exact over that range, since the multiplier's
+    // excess m d - 2^(30 + l) lies in (0, d]
+    uint32_t dmul[3];
+    int32_t dshr[3];
 };
 
 struct BoxState {

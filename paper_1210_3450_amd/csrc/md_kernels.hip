@@ -68,6 +68,12 @@ __device__ __forceinline__ BoxGeom ld_geom(const BoxGeom* p) {
     return g;
 }
 
+// x / n[0] (k = 0), x / n[1] (k = 1) or x / (n[0] * n[1]) (k = 2) for 0 <= x < 2^30,
+// with the box's precomputed multiplier and shift instead of an integer division.
+__device__ __forceinline__ int gdiv(const BoxGeom& g, int x, int k) {
+    return (int)(__umulhi((uint32_t)x, g.dmul[k]) >> g.dshr[k]);
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs (block b runs on XCD
 // b % 8).  Give XCD x a contiguous run of logical blocks so that neighbouring
 // keys, whose partners overlap, share that XCD's L2.  Bijective on [0, nb).
@@ -631,8 +637,8 @@ __global__ __launch_bounds__(kBlock) void k_rank_permute(Dev d, Params p) {
         d.vy[np][dst] = d.vy[sp][o];
         d.vz[np][dst] = d.vz[sp][o];
         d.id[np][dst] = key;
-        const int cx = cid % g.n[0], tq = cid / g.n[0];
-        const int cy = tq % g.n[1], cz = tq / g.n[1];
+        const int tq = gdiv(g, cid, 0), cx = cid - tq * g.n[0];
+        const int cz = gdiv(g, tq, 1), cy = tq - cz * g.n[1];
         const uint32_t cc = (uint32_t)cx | ((uint32_t)cy << 10) | ((uint32_t)cz << 20);
         x.cc = cc;
         x.cnt = 0;
@@ -871,7 +877,8 @@ __global__ __launch_bounds__(kBlock) void k_row_delta(Dev d, Params p) {
         const BoxGeom g = ld_geom(d.geom + b);
         const int lr = __builtin_amdgcn_readfirstlane(tr.y);
         int ps0 = 0, plen = 0, ox, oy, oz;
-        if (l < 27) tile_piece(d, g, lr % g.n[1], lr / g.n[1], tr.z, tr.w, l, ps0, plen, ox, oy, oz);
+        const int lz = gdiv(g, lr, 1);
+        if (l < 27) tile_piece(d, g, lr - lz * g.n[1], lz, tr.z, tr.w, l, ps0, plen, ox, oy, oz);
         const int pbase = wave_incl_sum(plen) - plen;
         if (l < 27) d.rt_delta[t * 27 + l] = pbase - ps0;
     }
@@ -1127,7 +1134,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7, 8))) 
         if (m == 0) return;
         const int cs0 = ld_const(d.cell_start + c);
         Pos* __restrict__ q = d.q[ld_const(&st.sq) ^ 1];  // permuted, made current after the build
-        const int cx = local % g.n[0], cy = (local / g.n[0]) % g.n[1], cz = local / (g.n[0] * g.n[1]);
+        const int ly = gdiv(g, local, 0), cz = gdiv(g, local, 2);
+        const int cx = local - ly * g.n[0], cy = ly - cz * g.n[1];
         // stencil cell s = lane s < 27: start, count and image term
         int start = 0, cnt = 0;
         double shx = 0.0, shy = 0.0, shz = 0.0;
@@ -1784,7 +1792,7 @@ __global__ __launch_bounds__(kRtBlock) void k_force_t(Dev d, Params p) {
         const BoxGeom g = ld_geom(d.geom + b);
         const int lr = __builtin_amdgcn_readfirstlane(tr.y), xa = __builtin_amdgcn_readfirstlane(tr.z),
                   xb = __builtin_amdgcn_readfirstlane(tr.w);
-        const int cy = lr % g.n[1], cz = lr / g.n[1];
+        const int cz = gdiv(g, lr, 1), cy = lr - cz * g.n[1];
         const int sq = ld_const(&d.st[b].sq), sp = ld_const(&d.st[b].sp);
         // every wavefront works out the pieces itself (lane p holds piece p): no barrier
         int ps0 = 0, plen = 0, pox = 0, poy = 0, poz = 0;
@@ -2019,7 +2027,7 @@ __global__ __launch_bounds__(kRtBlock) void k_force_t64(Dev d, Params p) {
         const BoxGeom g = ld_geom(d.geom + b);
         const int lr = __builtin_amdgcn_readfirstlane(tr.y), xa = __builtin_amdgcn_readfirstlane(tr.z),
                   xb = __builtin_amdgcn_readfirstlane(tr.w);
-        const int cy = lr % g.n[1], cz = lr / g.n[1];
+        const int cz = gdiv(g, lr, 1), cy = lr - cz * g.n[1];
         const int sq = ld_const(&d.st[b].sq), sp = ld_const(&d.st[b].sp);
         int ps0 = 0, plen = 0, rx = 0, ry = 0, rz = 0;
         if (l < kPc) {
