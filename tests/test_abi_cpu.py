@@ -4,6 +4,7 @@ import ctypes as C
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_1210_3450_amd import binding as B
@@ -106,3 +107,23 @@ def test_batch_rejects_mismatched_shared_fields():
     out = C.c_void_p()
     assert B.md_batch_create(arr, 2, None, C.byref(out)) == B.MD_EINVAL
     assert B.md_batch_create(arr, 0, None, C.byref(out)) == B.MD_EINVAL
+
+
+def test_cell_division_multipliers_are_exact():
+    """The box geometry divides cell indices by n[0], n[1] and n[0] * n[1] with a
+    multiplier floor(2^(30 + l) / d) + 1 and a shift of 32 + l - 2 (l = ceil(log2 d)),
+    which is exact for every 0 <= x < 2^30 (the multiplier's excess m d - 2^(30 + l)
+    lies in (0, d]); checked here for every divisor the cell grid can have on one axis
+    and for products of two, at the edges of every quotient class and at random."""
+    rng = np.random.Generator(np.random.PCG64(5))
+    X = (1 << 30) - 1
+    divisors = list(range(3, 1024)) + [a * b for a in (3, 7, 45, 142, 1000, 1023) for b in (3, 64, 142, 999, 1023)]
+    for d in divisors:
+        l = (d - 1).bit_length()  # ceil(log2 d)
+        m = (1 << (30 + l)) // d + 1
+        assert m < (1 << 32)
+        ks = np.unique(np.concatenate([[0, 1, 2], rng.integers(0, X // d + 1, 64), [X // d - 1, X // d]]))
+        xs = np.concatenate([ks * d, ks * d + d - 1, rng.integers(0, X + 1, 256)])
+        xs = xs[(xs >= 0) & (xs <= X)].astype(object)
+        q = [((int(x) * m) >> 32) >> (l - 2) for x in xs]
+        assert q == [int(x) // d for x in xs], d
