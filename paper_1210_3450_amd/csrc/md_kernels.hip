@@ -148,13 +148,16 @@ __device__ int block_excl_scan(int v, int* total) {
     return off + inc - v;
 }
 
-// Cell-relative anchor of cell c on an axis: the cell centre (c + 1/2) * cs.
-__device__ __forceinline__ double anchor(int c, double cs) { return ((double)c + 0.5) * cs; }
-
-// Fixed-point cell-relative coordinate of x in cell c (2^28 units per cell side),
-// clamped to two cell sides so pair differences never overflow int32.
+// Fixed-point cell-relative coordinate of x in cell c (2^28 units per cell side,
+// relative to the cell centre (c + 1/2) * cs), clamped to two cell sides so pair
+// differences never overflow int32.
+// No contraction: every kernel that encodes a position (binning permutation, drifts,
+// the force passes' own coordinate) must round the anchor product, the difference and
+// the scaling alike, or a particle's record could differ by one unit between them.
 __device__ __forceinline__ int to_units(double x, int c, double cs, double ucs) {
-    double t = rint((x - anchor(c, cs)) * ucs);
+#pragma clang fp contract(off)
+    const double a = ((double)c + 0.5) * cs;  // the anchor
+    double t = rint((x - a) * ucs);
     t = fmin(fmax(t, -(double)kUnitClamp), (double)kUnitClamp);
     return (int)t;
 }
@@ -970,7 +973,7 @@ template <int TPK, bool WRAP, bool STAGED, bool HALF, bool TL>
 __device__ __forceinline__ void list_pass(const Dev& d, const Params& p, const Pos* __restrict__ q,
                                           const const_double* qc, int cs0, int kb, int mb, int c0, int total,
                                           int start, int pre, int ekey, int scnt, double shx, double shy,
-                                          double shz, int pre13, int& n_own, int& open, uint16_t* stage,
+                                          double shz, int& n_own, int& open, uint16_t* stage,
                                           uint8_t* mark) {
     constexpr int G = WRAP ? 3 : 6;
     static_assert(G * kWave <= kMarkBytes, "mark window");
@@ -1024,8 +1027,13 @@ __device__ __forceinline__ void list_pass(const Dev& d, const Params& p, const P
     const int cap = p.cap, rows = p.rows;
     // The key loop, instantiated per chunk count so that every chunk's distances are
     // computed ahead of the (serial) compaction chain, with no branches between them.
-    auto key_loop = [&](auto n_c) {
+    // The home cell's members come first among the candidates, so key kb + a is
+    // candidate kb + a: with GEN false the pass starts at the block's first key
+    // (c0 == kb), key a's own candidate is lane a of the first chunk, and only that
+    // chunk's ballot drops a bit.
+    auto key_loop = [&](auto n_c, auto gen_c) {
         constexpr int N = decltype(n_c)::value;
+        constexpr bool GEN = decltype(gen_c)::value;
         double nx = qc[4 * (cs0 + kb)], ny = qc[4 * (cs0 + kb) + 1], nz = qc[4 * (cs0 + kb) + 2];
         for (int a = 0; a < mb; ++a) {
             const int key = cs0 + kb + a;
@@ -1038,11 +1046,11 @@ __device__ __forceinline__ void list_pass(const Dev& d, const Params& p, const P
                 ny = qc[4 * (key + 1) + 1];
                 nz = qc[4 * (key + 1) + 2];
             }
-            int cnt = c0 == 0 ? 0 : __builtin_amdgcn_readlane(n_own, a);  // uniform running count
+            int cnt = __builtin_amdgcn_readlane(n_own, a);  // uniform running count (0 in the first pass)
             // the key's own candidate: chunk sk, bit sb (scalar)
-            const int self = pre13 + kb + a - c0;
+            const int self = kb + a - c0;
             const int sk = self >> 6;
-            const unsigned long long sb = 1ull << (self & 63);
+            const unsigned long long sb = 1ull << (GEN ? self & 63 : a);
             char* __restrict__ kp = STAGED ? reinterpret_cast<char*>(stage + a * cap)
                                            : reinterpret_cast<char*>(d.list + list_addr(key, 0, TPK, rows));
             bool in[N];
@@ -1059,7 +1067,7 @@ __device__ __forceinline__ void list_pass(const Dev& d, const Params& p, const P
                 // the backward stencil cells hold no candidates)
                 const unsigned long long mask =
                     HALF ? __builtin_amdgcn_ballot_w64(in[k] && k * kWave + l > self)
-                         : __builtin_amdgcn_ballot_w64(in[k]) & ~(k == sk ? sb : 0ull);
+                         : __builtin_amdgcn_ballot_w64(in[k]) & ~(GEN ? (k == sk ? sb : 0ull) : (k == 0 ? sb : 0ull));
                 // the lane's place among the accepted lanes; the running count is added
                 // to the (scalar) base address instead where the layout allows
                 const uint32_t rel =
@@ -1083,22 +1091,30 @@ __device__ __forceinline__ void list_pass(const Dev& d, const Params& p, const P
             if (l == a) n_own = cnt;
         }
     };
-    switch (nch) {
-        case 1: key_loop(std::integral_constant<int, 1>{}); break;
-        case 2: key_loop(std::integral_constant<int, 2>{}); break;
-        default:
-            if constexpr (G == 3) {
-                key_loop(std::integral_constant<int, 3>{});
-            } else {
-                switch (nch) {
-                    case 3: key_loop(std::integral_constant<int, 3>{}); break;
-                    case 4: key_loop(std::integral_constant<int, 4>{}); break;
-                    case 5: key_loop(std::integral_constant<int, 5>{}); break;
-                    default: key_loop(std::integral_constant<int, 6>{}); break;
+    auto by_count = [&](auto gen_c) {
+        switch (nch) {
+            case 1: key_loop(std::integral_constant<int, 1>{}, gen_c); break;
+            case 2: key_loop(std::integral_constant<int, 2>{}, gen_c); break;
+            default:
+                if constexpr (G == 3) {
+                    key_loop(std::integral_constant<int, 3>{}, gen_c);
+                } else {
+                    switch (nch) {
+                        case 3: key_loop(std::integral_constant<int, 3>{}, gen_c); break;
+                        case 4: key_loop(std::integral_constant<int, 4>{}, gen_c); break;
+                        case 5: key_loop(std::integral_constant<int, 5>{}, gen_c); break;
+                        default: key_loop(std::integral_constant<int, 6>{}, gen_c); break;
+                    }
                 }
-            }
-            break;
-    }
+                break;
+        }
+    };
+    // own candidates of this pass: kb - c0 .. kb + mb - 1 - c0 (uniform); the half list
+    // drops them by position instead
+    if (HALF || kb == c0)
+        by_count(std::false_type{});
+    else
+        by_count(std::true_type{});
 }
 
 // Seven wavefronts per SIMD (at most 72 VGPRs, no vector spills in the full-list
@@ -1136,12 +1152,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7, 8))) 
         Pos* __restrict__ q = d.q[ld_const(&st.sq) ^ 1];  // permuted, made current after the build
         const int ly = gdiv(g, local, 0), cz = gdiv(g, local, 2);
         const int cx = local - ly * g.n[0], cy = ly - cz * g.n[1];
-        // stencil cell s = lane s < 27: start, count and image term
+        // lane l < 27 holds the l-th stencil cell of the candidate order: the home cell
+        // (s = 13) first, then s = 0 .. 12 and 14 .. 26, so every key's own candidate sits
+        // in the first chunk of a cell with at most 64 members; its start, count and
+        // image term
+        const int s_of_l = l == 0 ? 13 : (l <= 13 ? l - 1 : l);
         int start = 0, cnt = 0;
         double shx = 0.0, shy = 0.0, shz = 0.0;
         bool img = false;
         if (l < 27) {
-            const int ox = l % 3 - 1, oy = (l / 3) % 3 - 1, oz = l / 9 - 1;
+            const int ox = s_of_l % 3 - 1, oy = (s_of_l / 3) % 3 - 1, oz = s_of_l / 9 - 1;
             int rx, ry, rz;
             const int x = nb_axis(cx, ox, g.n[0], g.L[0], shx, rx);
             const int y = nb_axis(cy, oy, g.n[1], g.L[1], shy, ry);
@@ -1153,25 +1173,24 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7, 8))) 
             if (cnt > kMaxCellCount) atomicOr(&d.st[b].err, 2);  // ranks would not fit 11 bits
             // half list: only the home cell (s = 13) and the forward cells s > 13, whose
             // offsets are lexicographically positive, so each pair of cells meets once
-            if (HALF && l < 13) cnt = 0;
+            if (HALF && s_of_l < 13) cnt = 0;
         }
         const bool wrap = __ballot(img) != 0ull;  // uniform: this cell touches the box boundary
         const int incl = wave_incl_sum(cnt);
         const int pre = incl - cnt;
-        // entry of candidate ci of stencil cell s = l: ekey + ci (gather format: s << 11
-        // plus its rank; row-tile format: its index in the staged region of the home
-        // cell's row tile, whose piece p = r * 3 + side holds unwrapped cells in order)
-        int ekey = (l << kOffBits) - pre;
+        // entry of candidate ci of the lane's stencil cell s: ekey + ci (gather format:
+        // s << 11 plus its rank; row-tile format: its index in the staged region of the
+        // home cell's row tile, whose piece p = r * 3 + side holds unwrapped cells in order)
+        int ekey = (s_of_l << kOffBits) - pre;
         if constexpr (TL) {
             // staged index of the stencil cell's first member: its first slot plus the
             // (staged index - first slot) of the piece of the home cell's row tile holding it
-            const int r = l / 3, x = cx + l % 3 - 1;
+            const int r = s_of_l / 3, x = cx + s_of_l % 3 - 1;
             const int pc = r * 3 + (x < 0 ? 0 : (x >= g.n[0] ? 2 : 1));
             const int rt = ld_const(d.cell_rt + c);
             ekey = (l < 27 ? start + d.rt_delta[rt * 27 + pc] : 0) - pre;
         }
         const int total = __builtin_amdgcn_readlane(incl, 26);
-        const int pre13 = __builtin_amdgcn_readlane(pre, 13);  // the home cell's first candidate
         const const_double* qc = (const const_double*)q;     // 4 doubles per particle
         int need = 0;
         for (int kb = 0; kb < m; kb += kWave) {
@@ -1183,11 +1202,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7, 8))) 
                 if (wrap) {
                     for (int c0 = 0; c0 < total; c0 += 3 * kWave)
                         list_pass<TPK, true, true, HALF, TL>(d, p, q, qc, cs0, kb, mb, c0, total, start, pre, ekey, cnt, shx,
-                                                         shy, shz, pre13, n_own, open, stage, mark);
+                                                         shy, shz, n_own, open, stage, mark);
                 } else {
                     for (int c0 = 0; c0 < total; c0 += 6 * kWave)
                         list_pass<TPK, false, true, HALF, TL>(d, p, q, qc, cs0, kb, mb, c0, total, start, pre, ekey, cnt, shx,
-                                                          shy, shz, pre13, n_own, open, stage, mark);
+                                                          shy, shz, n_own, open, stage, mark);
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
@@ -1218,12 +1237,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7, 8))) 
                 int open = 0;
                 for (int c0 = 0; c0 < total; c0 += 3 * kWave)
                     list_pass<TPK, true, false, HALF, TL>(d, p, q, qc, cs0, kb, mb, c0, total, start, pre, ekey, cnt, shx, shy,
-                                                      shz, pre13, n_own, open, stage, mark);
+                                                      shz, n_own, open, stage, mark);
             } else {
                 int open = 0;
                 for (int c0 = 0; c0 < total; c0 += 6 * kWave)
                     list_pass<TPK, false, false, HALF, TL>(d, p, q, qc, cs0, kb, mb, c0, total, start, pre, ekey, cnt, shx,
-                                                       shy, shz, pre13, n_own, open, stage, mark);
+                                                       shy, shz, n_own, open, stage, mark);
             }
             if (l < mb) {
                 const int nk = n_own < cap ? n_own : cap;
