@@ -262,6 +262,27 @@ def test_steps_mixed_tiles_equal_global_gathers():
     assert a[4] == t[4] and a[4] > 0
 
 
+@pytest.mark.parametrize("flag", ["MD_F_TILE_ON", "MD_F_TILE_OFF"])
+def test_steps_mixed_split_calls_equal_one_call(flag):
+    """Sixty single-step calls (open kick and drift in their own pass, forces at the
+    end of each step) follow one sixty-step call (kicks, drift and the fixed-point
+    re-encoding fused into the force pass) bit for bit: every kernel encodes a
+    position into the same fixed-point record."""
+    b = B()
+    q, L = tile_case("rows26")
+    v = inputs.maxwell_boltzmann(q.shape[0], 1.0, 1.0, rng(8))
+    out = []
+    for split in ([60], [1] * 60):
+        with make_ctx(q, v, L, precision=1, threads_per_key=1, flags=getattr(b, flag)) as c:
+            for n in split:
+                c.step(n)
+            pos, vel = c.get_state()
+            out.append((pos.cpu().numpy(), vel.cpu().numpy(), c.stats()["rebuilds"]))
+    np.testing.assert_array_equal(out[0][0], out[1][0])
+    np.testing.assert_array_equal(out[0][1], out[1][1])
+    assert out[0][2] == out[1][2] and out[0][2] > 0
+
+
 @pytest.mark.parametrize("fast", [False, True], ids=["div", "fastrcp"])
 @pytest.mark.parametrize("name", ["rows26", "dilute", "small"])
 def test_forces_fp64_tiles_match_gathers_and_oracle(name, fast):
