@@ -940,7 +940,8 @@ __device__ __forceinline__ int nb_axis(int c, int o, int n, double L, double& su
 }
 
 // A4, one wavefront per home cell.  All keys of a cell share one candidate set:
-// the particles of its 27 stencil cells, concatenated in stencil order.  Lane l
+// the particles of its 27 stencil cells, concatenated with the home cell first and
+// the other 26 in stencil order after it.  Lane l
 // holds candidate l of each 64-wide chunk (loads are contiguous runs).  A pass
 // loads up to G chunks into registers, then the wavefront walks the cell's keys:
 // per (key, chunk) an exact FP64 test, a ballot, an mbcnt prefix on the key's
@@ -961,11 +962,12 @@ typedef const __attribute__((address_space(4))) double const_double;
 // a * cap + (e % TPK) * (cap / TPK) + e / TPK, i.e. already in per-lane chunk
 // order) and leave in whole 16-byte chunks afterwards; otherwise each entry is
 // stored to the list directly.
-// A candidate's stencil cell: each non-empty stencil cell s marks its first
-// candidate with s + 1 in a byte window of the pass (the wavefront's `mark`,
-// G * 64 bytes), and a running maximum over the window, started from the cell
-// that was open at the end of the previous pass (`open`), gives every candidate
-// the last cell starting at or before it.
+// A candidate's stencil cell: the non-empty stencil cell at position o of the
+// candidate order marks its first candidate with o + 1 in a byte window of the pass
+// (the wavefront's `mark`, G * 64 bytes), and a running maximum over the window,
+// started from the position that was open at the end of the previous pass (`open`),
+// gives every candidate the last position starting at or before it; lane o holds
+// that position's start, entry base and image term.
 constexpr int kStage = 2048;  // LDS list entries per wavefront (16 KB per block, 17.5 KB with the marks: 7 blocks per CU)
 constexpr int kMarkBytes = 6 * kWave;  // candidate window of a pass (G <= 6 chunks)
 
