@@ -1808,6 +1808,10 @@ __global__ __launch_bounds__(kRtBlock) void k_force_t(Dev d, Params p) {
     const int l = lane_id(), wib = wave_in_block();
     const int ntl = ld_const(d.ntiles);
     for (int t = xcd_block(blockIdx.x, gridDim.x); t < ntl; t += gridDim.x) {
+        // Staging runs at a raised wavefront priority, the pair loop at the normal one: a
+        // block that starts a tile gets its loads issued ahead of the arithmetic of the
+        // CU's other blocks, so their pair loops cover its memory latency.
+        __builtin_amdgcn_s_setprio(2);
         const int4 tr = d.rtile[t];
         const int b = __builtin_amdgcn_readfirstlane(tr.x);
         const BoxGeom g = ld_geom(d.geom + b);
@@ -1880,6 +1884,7 @@ __global__ __launch_bounds__(kRtBlock) void k_force_t(Dev d, Params p) {
         const char* __restrict__ sb = reinterpret_cast<const char*>(stg);
         double e_ke = 0.0, e_pe = 0.0, e_vir = 0.0;
         for (;;) {  // rounds of kRtBlock keys: a one-cell tile may hold more (uniform)
+            __builtin_amdgcn_s_setprio(0);  // the pair loop at the normal priority
             const uint32_t cc = qi.cc;
             const int4 ui = units3(qi, cc, g);  // own coordinate, from the record: no extra load
             const uint32_t kx = (uint32_t)ui.x, ky = (uint32_t)ui.y, kz = (uint32_t)ui.z;
@@ -1931,6 +1936,7 @@ __global__ __launch_bounds__(kRtBlock) void k_force_t(Dev d, Params p) {
             };
             for (int c = 0; c < nfull; ++c) chunk(c, std::false_type{}, U);
             if (ntail) chunk(nfull, std::true_type{}, ntail);
+            __builtin_amdgcn_s_setprio(1);  // the epilogue's loads and stores ahead of pair loops
             const double Fx = ((double)sx - (double)cx) * lam;
             const double Fy = ((double)sy - (double)cy2) * lam;
             const double Fz = ((double)sz - (double)cz2) * lam;
@@ -2043,6 +2049,7 @@ __global__ __launch_bounds__(kRtBlock) void k_force_t64(Dev d, Params p) {
     const int l = lane_id(), wib = wave_in_block();
     const int ntl = ld_const(d.ntiles);
     for (int t = xcd_block(blockIdx.x, gridDim.x); t < ntl; t += gridDim.x) {
+        __builtin_amdgcn_s_setprio(2);  // staging ahead of pair loops, as in k_force_t
         const int4 tr = d.rtile[t];
         const int b = __builtin_amdgcn_readfirstlane(tr.x);
         const BoxGeom g = ld_geom(d.geom + b);
@@ -2104,6 +2111,7 @@ __global__ __launch_bounds__(kRtBlock) void k_force_t64(Dev d, Params p) {
             }
         }
         __syncthreads();
+        __builtin_amdgcn_s_setprio(0);
         const double rc2 = p.rc2, c2x8 = 8.0 * p.c2;
         const bool fast = p.fastrcp != 0;  // uniform
         const char* __restrict__ sb = reinterpret_cast<const char*>(stg64);
