@@ -1070,19 +1070,18 @@ __device__ __forceinline__ void list_pass(const Dev& d, const Params& p, const P
                 const unsigned long long mask =
                     HALF ? __builtin_amdgcn_ballot_w64(in[k] && k * kWave + l > self)
                          : __builtin_amdgcn_ballot_w64(in[k]) & ~(GEN ? (k == sk ? sb : 0ull) : (k == 0 ? sb : 0ull));
-                // the lane's place among the accepted lanes; the running count is added
-                // to the (scalar) base address instead where the layout allows
-                const uint32_t rel =
-                    __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+                // the lane's entry position: the running count plus its place among the
+                // accepted lanes (the count enters as the lane-count base, no scalar add)
+                const uint32_t pos = __builtin_amdgcn_mbcnt_hi(
+                    (unsigned)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mask, (uint32_t)cnt));
                 unsigned long long sm = mask;
                 if (cnt + __popcll(mask) > cap)  // overflow: keep the entries that fit (rare)
                     sm = __builtin_amdgcn_ballot_w64(__builtin_amdgcn_inverse_ballot_w64(mask) &&
-                                                     (int)rel < cap - cnt);  // cnt may exceed cap
+                                                     (int)pos < cap);  // cnt may exceed cap
                 if (__builtin_amdgcn_inverse_ballot_w64(sm)) {
                     if constexpr (STAGED && TPK == 1) {
-                        (reinterpret_cast<uint16_t*>(kp) + cnt)[rel] = (uint16_t)ent[k];
+                        reinterpret_cast<uint16_t*>(kp)[pos] = (uint16_t)ent[k];
                     } else {
-                        const uint32_t pos = (uint32_t)cnt + rel;
                         const uint32_t off = STAGED ? ((pos % TPK) * (uint32_t)(cap / TPK) + pos / TPK) * 2u
                                                     : list_off_bytes<TPK>(pos);
                         *reinterpret_cast<uint16_t*>(kp + off) = (uint16_t)ent[k];
